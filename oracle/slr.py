@@ -1,0 +1,265 @@
+"""FP64 CPU oracle of the IRLS structured low-rank recovery of damped exponentials.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  The product
+(``libslrx`` and its Python binding) never calls it and shares no code with it.
+
+Every function follows the paper (Balachandrasekaran, Magnotta, Jacob,
+"Recovery of damped exponentials using structured low rank matrix
+completion", arXiv 1704.04511) step by step, in complex128, using NumPy's
+FFT and LAPACK ``eigh`` as library primitives.  Conventions (readings of the
+paper where it is silent, listed again in the design notes):
+
+* ``xhat`` (the paper's rho-hat) is k-space, complex ``[T][P][Q]``, DC at
+  ``[0, 0]``.  ``F`` is the unitary 2-D DFT (the matrix F of the measurement
+  model, Sec. II.A); images are ``rho_t = F^-1 xhat_t``.
+* Filter support Lambda = Lambda_s x {0..M-1}; Lambda_s holds the centred
+  offsets a = (a1, a2), a1 in [-floor(N1/2), N1-1-floor(N1/2)] (same for a2).
+  Lifted columns are ordered (m, a), m-major, a row-major.
+* Hybrid lifting (Sec. III.A, the approximation of eq. ``Toeplitz -
+  circ_rep``): T(xhat)[(n, w), (m, a)] = xhat_{n-m}[(w - a) mod (P, Q)] for
+  n = M-1..T-1 and all w, i.e. T(xhat) d is a 3-D convolution that is linear
+  (valid) along the parameter axis and circular in space.
+* The Gram matrix is R = T^H T (s x s, the filter side); its eigenvectors are
+  the filters (Sec. III.C, eq. ``eq:gram matrix``).
+* Per least-squares step the objective is ||S xhat - b||^2 + lam J(xhat) with
+  J = sum_i alpha_i ||T(xhat) u_i||^2; lam = 2/(mu p) relative to eq.
+  ``eq:x-update``.
+* epsilon^(0) = eps0_frac * lambda_max of the first Gram matrix, and after each
+  least-squares step epsilon <- epsilon / gamma (Sec. III.D); negative
+  round-off eigenvalues are clamped to zero before adding epsilon.
+* CG is warm-started from the current iterate, runs exactly ``n_cg``
+  iterations and stops early only on an exactly zero residual or curvature.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft
+
+__all__ = [
+    "dft2", "idft2", "filter_offsets", "pair_index", "lift", "gram",
+    "eig_weights", "weight_matrix", "filter_spectra", "penalty_masks",
+    "penalty_apply", "penalty_value", "normal_apply", "cg", "irls",
+]
+
+
+# ---------------------------------------------------------------- transforms
+def dft2(a: np.ndarray) -> np.ndarray:
+    """Unitary 2-D DFT over the last two axes (F in Sec. II.A, eq. ``measurement_ij``)."""
+    return np.fft.fft2(a, norm="ortho")
+
+
+def idft2(a: np.ndarray) -> np.ndarray:
+    """Inverse unitary 2-D DFT (F^* in Sec. II.A; Q^* = I (x) F^* in Sec. III.A)."""
+    return np.fft.ifft2(a, norm="ortho")
+
+
+# ------------------------------------------------------------ index helpers
+def filter_offsets(N1: int, N2: int) -> tuple[np.ndarray, np.ndarray]:
+    """Spatial support Lambda_s of one filter frame (Sec. II.C, N1 x N2), centred, row-major."""
+    a1 = np.arange(N1) - N1 // 2
+    a2 = np.arange(N2) - N2 // 2
+    A1, A2 = np.meshgrid(a1, a2, indexing="ij")
+    return A1.ravel(), A2.ravel()
+
+
+def pair_index(M: int) -> list[tuple[int, int]]:
+    """Tap pairs (m, m') with m <= m', in row-major order of the upper triangle."""
+    return [(m, mp) for m in range(M) for mp in range(m, M)]
+
+
+# ------------------------------------------------------------------ lifting
+def lift(xhat: np.ndarray, N1: int, N2: int, M: int) -> np.ndarray:
+    """Explicit lifted matrix T(xhat) in C^{(k P Q) x s} (Sec. II.B, eq. ``annihil-compact``).
+
+    Rows (n, w) for n = M-1..T-1 (k = T-M+1 valid shifts along the parameter
+    axis) and w in Z_P x Z_Q; columns (m, a).  Circular in space per the
+    hybrid approximation of Sec. III.A.  Tiny inputs only.
+    """
+    T, P, Q = xhat.shape
+    a1, a2 = filter_offsets(N1, N2)
+    NN = N1 * N2
+    k = T - M + 1
+    w1, w2 = np.meshgrid(np.arange(P), np.arange(Q), indexing="ij")
+    out = np.zeros((k * P * Q, M * NN), dtype=np.complex128)
+    for n in range(M - 1, T):
+        rows = slice((n - (M - 1)) * P * Q, (n - M + 2) * P * Q)
+        for m in range(M):
+            for ia in range(NN):
+                vals = xhat[n - m][(w1 - a1[ia]) % P, (w2 - a2[ia]) % Q]
+                out[rows, m * NN + ia] = vals.ravel()
+    return out
+
+
+# -------------------------------------------------------------- Gram matrix
+def gram(xhat: np.ndarray, N1: int, N2: int, M: int) -> np.ndarray:
+    """Gram matrix R = T(xhat)^H T(xhat) by FFT autocorrelation (Sec. III.C).
+
+    Block (m, m') of R (eq. ``eq:block-expression for R``) sums, over the
+    k valid parameter shifts, products of Toeplitz blocks; each product is read
+    from g = F_u(conj(rho_i) o rho_j) with a sliding N1 x N2 window over the
+    (2N1-1) x (2N2-1) lag neighbourhood (eq. ``eq:P_ij modified``).  Here
+    R[(m,a),(m',a')] = sum_{n=M-1}^{T-1} F_u(conj(rho_{n-m}) rho_{n-m'})[a - a'],
+    F_u the unnormalised forward DFT.  All M^2 blocks are formed directly.
+    """
+    T, P, Q = xhat.shape
+    rho = idft2(xhat)
+    a1, a2 = filter_offsets(N1, N2)
+    NN = N1 * N2
+    d1 = (a1[:, None] - a1[None, :]) % P
+    d2 = (a2[:, None] - a2[None, :]) % Q
+    R = np.empty((M * NN, M * NN), dtype=np.complex128)
+    for m in range(M):
+        for mp in range(M):
+            c = np.zeros((P, Q), dtype=np.complex128)
+            for n in range(M - 1, T):
+                c += np.conj(rho[n - m]) * rho[n - mp]
+            g = np.fft.fft2(c)
+            R[m * NN:(m + 1) * NN, mp * NN:(mp + 1) * NN] = g[d1, d2]
+    return R
+
+
+# ---------------------------------------------------------- weight update
+def eig_weights(R: np.ndarray, eps: float, p: float):
+    """Eigen-decomposition of R and IRLS weights (Sec. III.C, Algorithm 1 step 1).
+
+    alpha_i = (lambda_i + eps)^(p/2 - 1), with lambda_i clamped at 0.
+    Returns (lambda ascending, U, alpha).
+    """
+    lam, U = np.linalg.eigh(R)
+    alpha = (np.maximum(lam, 0.0) + eps) ** (p / 2.0 - 1.0)
+    return lam, U, alpha
+
+
+def weight_matrix(U: np.ndarray, alpha: np.ndarray) -> np.ndarray:
+    """H = U (Lambda + eps I)^(p/2-1) U^* (Sec. III.C, weight update eq. ``eq:weight-update``)."""
+    return (U * alpha[None, :]) @ U.conj().T
+
+
+def filter_spectra(u: np.ndarray, N1: int, N2: int, M: int, P: int, Q: int) -> np.ndarray:
+    """mu_m(r) = sum_{a in Lambda_s} u[(m, a)] e^{+2 pi i (a1 r1/P + a2 r2/Q)}.
+
+    The diagonal of D_l in eq. ``eq:circ_fft``: the transform of the zero-padded
+    filter frame (Sec. III.A).  ``u`` has shape (..., s); result (..., M, P, Q).
+    """
+    a1, a2 = filter_offsets(N1, N2)
+    NN = N1 * N2
+    lead = u.shape[:-1]
+    frames = np.zeros(lead + (M, P, Q), dtype=np.complex128)
+    uu = u.reshape(lead + (M, NN))
+    frames[..., a1 % P, a2 % Q] = uu
+    # e^{+2 pi i a r / N} summed over a = unnormalised inverse DFT
+    return scipy.fft.ifft2(frames, workers=-1) * (P * Q)
+
+
+def penalty_masks(U: np.ndarray, alpha: np.ndarray, N1: int, N2: int, M: int,
+                  P: int, Q: int, chunk: int = 64) -> np.ndarray:
+    """Per-pixel M x M penalty masks E_r (Sec. III.A; G precompute after eq. ``eq:grad_ls``).
+
+    E_r[m, m'] = sum_i alpha_i conj(mu^(i)_m(r)) mu^(i)_m'(r): the summed
+    (cross) power spectra of the weighted filters h^(i) = sqrt(alpha_i) u_i,
+    one filter at a time.  E_r is Hermitian, so the pairs m > m' are the
+    conjugates of m < m'.  Returned as complex128 [M][M][P][Q].
+    """
+    s = U.shape[1]
+    E = np.zeros((M, M, P * Q), dtype=np.complex128)
+    for i0 in range(0, s, chunk):
+        i1 = min(s, i0 + chunk)
+        mu = filter_spectra(U[:, i0:i1].T, N1, N2, M, P, Q)      # (c, M, P, Q)
+        mu *= np.sqrt(alpha[i0:i1])[:, None, None, None]
+        mu = mu.reshape(i1 - i0, M, P * Q)
+        cmu = np.conj(mu)
+        for m in range(M):
+            for mp in range(m, M):
+                E[m, mp] += np.einsum("ir,ir->r", cmu[:, m], mu[:, mp])
+    for m in range(M):
+        for mp in range(m):
+            E[m, mp] = np.conj(E[mp, m])
+    return E.reshape(M, M, P, Q)
+
+
+def penalty_apply(rho: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """Image-domain penalty operator G (Sec. III.A, eq. ``eq:grad_ls``).
+
+    J = sum_{n=M-1}^{T-1} sum_r z^H E_r z with z_m = rho_{n-m}(r); returns
+    dJ/d conj(rho): (G rho)_{n-m} += sum_m' E[m, m'] rho_{n-m'}.
+    """
+    M = E.shape[0]
+    T = rho.shape[0]
+    out = np.zeros_like(rho, dtype=np.complex128)
+    for n in range(M - 1, T):
+        for m in range(M):
+            for mp in range(M):
+                out[n - m] += E[m, mp] * rho[n - mp]
+    return out
+
+
+def penalty_value(rho: np.ndarray, E: np.ndarray) -> float:
+    """J(rho) = <rho, G rho> (real by construction)."""
+    return float(np.vdot(rho, penalty_apply(rho, E)).real)
+
+
+def normal_apply(xhat: np.ndarray, S: np.ndarray, E: np.ndarray, lam: float) -> np.ndarray:
+    """Normal operator of eq. ``eq:grad_ls``: S o xhat + lam F G F^* xhat (A = S, single coil)."""
+    return S * xhat + lam * dft2(penalty_apply(idft2(xhat), E))
+
+
+# ----------------------------------------------------------------------- CG
+def cg(apply, rhs: np.ndarray, x0: np.ndarray, n_iter: int, trace: list | None = None) -> np.ndarray:
+    """Conjugate gradients (Algorithm 1 step 2), warm start, exactly ``n_iter`` iterations."""
+    x = x0.astype(np.complex128).copy()
+    r = rhs - apply(x)
+    p = r.copy()
+    rr = float(np.vdot(r, r).real)
+    if trace is not None:
+        trace.append(rr)
+    for _ in range(n_iter):
+        if rr == 0.0:
+            break
+        q = apply(p)
+        pq = float(np.vdot(p, q).real)
+        if pq <= 0.0:
+            break
+        a = rr / pq
+        x += a * p
+        r -= a * q
+        rr_new = float(np.vdot(r, r).real)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        if trace is not None:
+            trace.append(rr)
+    return x
+
+
+# --------------------------------------------------------------------- IRLS
+def irls(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
+         n_irls: int, n_cg: int, p: float = 0.6, gamma: float = 1.4,
+         eps0_frac: float = 0.01, x0: np.ndarray | None = None,
+         trace: dict | None = None, return_kspace: bool = False) -> np.ndarray:
+    """Algorithm 1: alternate the weight update and the CG least-squares step.
+
+    Step 1 (Sec. III.C): Gram matrix by FFT autocorrelation, eigen-decomposition,
+    weights alpha_i = (lambda_i + eps)^(p/2-1) and masks E.  Step 2 (Sec. III.A):
+    a few CG iterations on (S + lam F G F^*) xhat = S o b.  Then eps <- eps/gamma
+    (Sec. III.D).  Returns the images F^-1 xhat (or xhat with ``return_kspace``).
+    """
+    S = S.astype(np.float64)
+    b = S * b.astype(np.complex128)
+    T, P, Q = b.shape
+    x = b.copy() if x0 is None else x0.astype(np.complex128).copy()
+    eps = None
+    for _ in range(n_irls):
+        R = gram(x, N1, N2, M)
+        lamR, U = np.linalg.eigh(R)
+        if eps is None:
+            eps = eps0_frac * float(lamR.max())
+        alpha = (np.maximum(lamR, 0.0) + eps) ** (p / 2.0 - 1.0)
+        E = penalty_masks(U, alpha, N1, N2, M, P, Q)
+        cg_trace = [] if trace is not None else None
+        x = cg(lambda v: normal_apply(v, S, E, lam), b, x, n_cg, cg_trace)
+        if trace is not None:
+            trace.setdefault("eps", []).append(eps)
+            trace.setdefault("lambda_max", []).append(float(lamR.max()))
+            trace.setdefault("cg_rr", []).append(cg_trace)
+        eps = eps / gamma
+    return x if return_kspace else idft2(x)

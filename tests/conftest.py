@@ -1,0 +1,29 @@
+"""Shared pytest configuration: the ``gpu`` marker and repository import path."""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+def pytest_collection_modifyitems(config, items):
+    # GPU tests need the device; without one they are reported as skipped, never faked.
+    try:
+        import torch  # noqa: F401
+        have_gpu = torch.cuda.is_available()
+    except Exception:  # pragma: no cover - torch missing
+        have_gpu = False
+    if have_gpu:
+        return
+    skip = pytest.mark.skip(reason="no GPU visible in this process")
+    for it in items:
+        if "gpu" in it.keywords:
+            it.add_marker(skip)
