@@ -1,0 +1,216 @@
+/*
+ * slrx -- structured low-rank recovery of damped-exponential image series on
+ * AMD MI355X (gfx950).  C ABI.
+ *
+ * Method: Balachandrasekaran, Magnotta, Jacob, "Recovery of damped exponentials
+ * using structured low rank matrix completion" (arXiv 1704.04511).  The
+ * library runs the IRLS loop of Algorithm 1 on one GPU:
+ *   step 1 (Sec. III.C): Gram matrix R of the multi-fold Toeplitz lifting of
+ *     the k-space samples, formed by Fourier autocorrelation of the images
+ *     (eq. "eq:block-expression for R", eq. "eq:P_ij modified"); its FP64
+ *     eigen-decomposition; weights alpha_i = (lambda_i + eps)^(p/2-1); the
+ *     summed filter power spectra as per-pixel penalty masks (Sec. III.A);
+ *   step 2 (Sec. III.A, eq. "eq:grad_ls"): a fixed number of conjugate-gradient
+ *     iterations on (S + lam F G F^H) x = S b;
+ *   then eps <- eps / gamma (Sec. III.D).
+ *
+ * Conventions
+ *   - k-space and images are complex64 (interleaved re, im float) arrays
+ *     [T][P][Q], frame-major, row-major frames, DC at index [0][0].  F is the
+ *     unitary 2-D DFT; images = F^-1 x per frame.
+ *   - Masks are uint8 [T][P][Q] with values 0 or 1 (nonzero counts as 1).
+ *   - lam is the penalty weight per least-squares step:
+ *     min ||S x - b||^2 + lam J(x);  lam = 2/(mu p) for the paper's mu.
+ *   - Filter support N1 x N2 x M (spatial x spatial x taps); s = N1 N2 M.
+ *   - Supported frame sizes P, Q in {8,16,32,64,96,128,160,192,256};
+ *     1 <= M <= min(T, 8); T <= 32; 1 <= N1 <= P; 1 <= N2 <= Q.
+ *
+ * Ownership and errors
+ *   - The library owns every device buffer it allocates.  Host inputs are
+ *     copied before the call returns.  Device inputs (SLRX_MEM_DEVICE) are
+ *     read on the plan's stream in stream order; they must stay valid until
+ *     the next slrx_sync on that plan.
+ *   - Every call returns an slrx_status; no C++ exception crosses the ABI.
+ *     Argument validation happens before any device work and is testable
+ *     without a GPU.  slrx_last_error() returns a message for the calling
+ *     thread's last failure.
+ *   - One plan is used by one thread at a time; different plans may run
+ *     concurrently on different streams.
+ */
+#ifndef SLRX_H
+#define SLRX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SLRX_OK = 0,
+  SLRX_EINVAL = -1,      /* invalid argument or unsupported size */
+  SLRX_ENOMEM = -2,      /* device allocation failed or budget exceeded */
+  SLRX_EDEVICE = -3,     /* HIP / rocSOLVER error */
+  SLRX_ESTATE = -4,      /* call not allowed in the plan's current state */
+  SLRX_ENUMERIC = -5,    /* eigen-decomposition failed or non-finite values */
+  SLRX_EBUSY = -6,       /* plan is running */
+  SLRX_ENOTREADY = -7    /* no completed run / request not finished */
+} slrx_status;
+
+typedef enum { SLRX_MEM_HOST = 0, SLRX_MEM_DEVICE = 1 } slrx_mem;
+
+/* Problem dimensions: T frames of P x Q; filter support N1 x N2 x M. */
+typedef struct {
+  int32_t P, Q, T;
+  int32_t N1, N2, M;
+} slrx_dims;
+
+/* Algorithm parameters.  lambda >= 0; p in [0, 1] (Schatten exponent,
+ * Sec. II.D); gamma > 1 (eps decrease, Sec. III.D); eps0_frac > 0
+ * (eps^(0) = eps0_frac * lambda_max of the first Gram matrix); n_irls >= 1
+ * outer iterations; n_cg >= 0 CG iterations per outer iteration. */
+typedef struct {
+  double lambda, p, gamma, eps0_frac;
+  int32_t n_irls, n_cg;
+  uint32_t flags; /* SLRX_FLAG_* */
+} slrx_params;
+
+#define SLRX_FLAG_TIMING 1u /* record per-phase device times (hipEvents) */
+#define SLRX_FLAG_KTIME 2u  /* record every launch of each kernel class (hipEvents) */
+
+/* Kernel classes timed under SLRX_FLAG_KTIME. */
+enum {
+  SLRX_K_ROWS = 0,    /* forward row pass of the CG operator (fused p update) */
+  SLRX_K_COLS = 1,    /* column pass: FFT, sampling mask, inverse FFT */
+  SLRX_K_FIN = 2,     /* inverse row pass + penalty G + combine + dot */
+  SLRX_K_UPDATE = 3,  /* CG vector update + residual norm */
+  SLRX_K_GRAM = 4,    /* Gram matrix (lagged products, pruned DFT, window) */
+  SLRX_K_EIGH = 5,    /* FP64 Hermitian eigen-decomposition */
+  SLRX_K_FILTER = 6,  /* weights + filter product H = U diag(alpha) U^H */
+  SLRX_K_MASKS = 7,   /* diagonal sums + mask synthesis */
+  SLRX_K_NCLASS = 8
+};
+
+/* Per-run statistics, filled by slrx_get_stats after a completed run. */
+#define SLRX_MAX_IRLS 256
+typedef struct {
+  int32_t n_irls_done;
+  double eps[SLRX_MAX_IRLS];        /* eps used by each outer iteration */
+  double lambda_max[SLRX_MAX_IRLS]; /* largest Gram eigenvalue per iteration */
+  double cg_rr_final[SLRX_MAX_IRLS];/* squared CG residual norm after each LS step */
+  double ms_total;                  /* device time of the whole run (ms) */
+  double ms_gram, ms_eigh, ms_weights, ms_cg; /* per phase, SLRX_FLAG_TIMING */
+  double kt_ms[SLRX_K_NCLASS];      /* summed launch durations per class, SLRX_FLAG_KTIME */
+  int32_t kt_count[SLRX_K_NCLASS];  /* launches per class */
+} slrx_stats;
+
+typedef struct slrx_plan slrx_plan;
+typedef struct slrx_server slrx_server;
+
+/* Default parameters: p = 0.6, gamma = 1.4, eps0_frac = 0.01, lambda = 1e-3,
+ * n_irls = 15, n_cg = 10, flags = 0. */
+void slrx_default_params(slrx_params* out);
+
+/* Validate dims/params without touching the device.  SLRX_OK or SLRX_EINVAL. */
+slrx_status slrx_validate(const slrx_dims* dims, const slrx_params* params);
+
+/* Device bytes a plan of these dims allocates (used for admission). */
+size_t slrx_footprint(const slrx_dims* dims);
+
+/* Create a plan on the current HIP device.  hip_stream: a hipStream_t to run
+ * on, or NULL for a stream owned by the plan.  Allocates all device state. */
+slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params* params,
+                             void* hip_stream, slrx_plan** out);
+void slrx_plan_destroy(slrx_plan* plan);
+
+/* Inputs.  b: complex64 [T][P][Q] sampled k-space (entries off the mask are
+ * ignored);  S: uint8 [T][P][Q];  x0: optional complex64 k-space initial
+ * guess (default x0 = S o b, the zero-filled data; Algorithm 1 init). */
+slrx_status slrx_set_kspace(slrx_plan* plan, const void* b, slrx_mem mem);
+slrx_status slrx_set_mask(slrx_plan* plan, const uint8_t* S, slrx_mem mem);
+slrx_status slrx_set_init(slrx_plan* plan, const void* x0, slrx_mem mem);
+slrx_status slrx_clear_init(slrx_plan* plan);
+/* Change the filter support; N1 N2 M must not exceed the sizes the plan was
+ * created with (buffers are sized at creation).  Algorithm parameters: */
+slrx_status slrx_set_filter(slrx_plan* plan, int32_t N1, int32_t N2, int32_t M);
+slrx_status slrx_set_params(slrx_plan* plan, const slrx_params* params);
+
+/* Enqueue the whole reconstruction on the plan's stream.  The FP64
+ * eigen-decomposition may synchronise the stream internally. */
+slrx_status slrx_run(slrx_plan* plan);
+/* Wait for the plan's work; reports numerical failures of the run. */
+slrx_status slrx_sync(slrx_plan* plan);
+
+/* Outputs (after slrx_sync): images F^-1 x and k-space x, complex64 [T][P][Q]. */
+slrx_status slrx_get_images(slrx_plan* plan, void* out, slrx_mem mem);
+slrx_status slrx_get_kspace(slrx_plan* plan, void* out, slrx_mem mem);
+slrx_status slrx_get_stats(slrx_plan* plan, slrx_stats* out);
+
+/* Run several plans back to back on one stream (NULL: each plan's own). */
+slrx_status slrx_run_batch(slrx_plan* const* plans, int32_t n, void* hip_stream);
+
+/* --- single steps of the loop, for testing each step against a reference --- */
+/* Images F^-1 x of the plan's current iterate (complex64 [T][P][Q]). */
+/* Gram matrix of the current iterate: complex128 s x s, column-major. */
+slrx_status slrx_step_gram(slrx_plan* plan, void* R_out, slrx_mem mem);
+/* Weight update from the current iterate with a given eps: eigenvalues
+ * (ascending, s doubles), filter product H = U diag(alpha) U^H (complex128
+ * s x s, row-major) and penalty masks E (complex64 [W][P][Q], W = M(M+1)/2,
+ * pairs m <= m' in row-major upper-triangle order).  Any output may be NULL. */
+slrx_status slrx_step_weights(slrx_plan* plan, double eps, double* lam_out,
+                              void* H_out, void* E_out, slrx_mem mem);
+/* Apply the normal operator to k-space v with masks E (complex64 [W][P][Q]):
+ * out = S o v + lam F G F^H v, complex64 k-space. */
+slrx_status slrx_step_apply(slrx_plan* plan, const void* E, const void* v,
+                            void* out, slrx_mem mem);
+/* Run n_cg CG iterations from the current iterate with given masks E. */
+slrx_status slrx_step_cg(slrx_plan* plan, const void* E, int32_t n_cg);
+
+/* --- continuous-batching server ------------------------------------------
+ * Requests queue in arrival order and are admitted (first fit) when one of
+ * max_slots slots is free and their device footprint (slrx_footprint) fits
+ * the remaining budget_bytes.  Each admitted request runs on a stream of its
+ * own, so the device interleaves the work of all admitted requests; a request
+ * arriving while others run starts as soon as a slot and memory free up.  A
+ * request's result does not depend on the others (own buffers, fixed-order
+ * reductions).  hip_stream is ignored (every slot has its own stream).
+ * Thread-safe: any thread may submit, poll, wait or fetch. */
+typedef struct {
+  double t_submit, t_admit, t_done; /* steady-clock seconds */
+  int32_t state;                    /* 0 queued, 1 running, 2 done */
+  int32_t status;                   /* slrx_status of a finished request */
+  size_t bytes;                     /* footprint charged against the budget */
+} slrx_request_info;
+
+slrx_status slrx_server_create(size_t budget_bytes, int32_t max_slots,
+                               void* hip_stream, slrx_server** out);
+/* Cancels queued requests, waits for running ones, frees server-owned state. */
+void slrx_server_destroy(slrx_server* srv);
+/* Submit an existing plan (k-space and mask set); it is run in place and its
+ * footprint is charged while it runs.  The plan must not be used until done. */
+slrx_status slrx_submit(slrx_server* srv, slrx_plan* plan, uint64_t* ticket);
+/* Submit host data; the server creates the plan (allocating its device state)
+ * at admission and keeps it resident until slrx_fetch_images/slrx_release.
+ * Fails with SLRX_ENOMEM if the footprint alone exceeds the budget. */
+slrx_status slrx_submit_data(slrx_server* srv, const slrx_dims* dims, const slrx_params* params,
+                             const void* b_host, const uint8_t* S_host, uint64_t* ticket);
+slrx_status slrx_poll(slrx_server* srv, uint64_t ticket, int32_t* done);
+/* Block until the request is done; returns its status. */
+slrx_status slrx_wait(slrx_server* srv, uint64_t ticket);
+slrx_status slrx_get_request_info(slrx_server* srv, uint64_t ticket, slrx_request_info* out);
+/* Budget in use (bytes) and number of queued requests. */
+slrx_status slrx_server_usage(slrx_server* srv, size_t* used, int32_t* queued);
+/* Copy a done server-owned request's images (complex64 [T][P][Q]) to host
+ * memory and free its device state. */
+slrx_status slrx_fetch_images(slrx_server* srv, uint64_t ticket, void* out_host);
+/* Forget a done request, freeing whatever it still holds. */
+slrx_status slrx_release(slrx_server* srv, uint64_t ticket);
+
+const char* slrx_status_str(slrx_status s);
+const char* slrx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLRX_H */

@@ -1,0 +1,396 @@
+"""Python binding of libslrx: IRLS structured low-rank recovery on MI355X.
+
+Argument marshalling only.  Every step of the reconstruction runs in the HIP
+library ``libslrx.so`` (built in-tree by ``paper_1704_04511_amd.build``); this
+module converts NumPy arrays / torch tensors to pointers and C structs.  There
+is no fallback: if the library is missing, importing :func:`lib` raises.
+
+Arrays: complex64 ``[T, P, Q]`` k-space or images (DC at [0, 0]); uint8 masks.
+Host NumPy arrays are copied by the library before a setter returns; torch
+CUDA tensors are passed as device pointers on the plan's stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+# PyTorch's HIP runtime must be the one in the process before libslrx loads.
+import torch  # noqa: F401
+
+__all__ = [
+    "Dims", "Params", "Stats", "RequestInfo", "Plan", "Server", "SlrxError", "lib", "library_path",
+    "footprint", "validate", "default_params", "run_batch", "exported_symbols",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libslrx.so")
+_lib = None
+_lock = threading.Lock()
+
+SLRX_MEM_HOST = 0
+SLRX_MEM_DEVICE = 1
+SLRX_FLAG_TIMING = 1
+SLRX_FLAG_KTIME = 2
+MAX_IRLS = 256
+KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "eigh", "filter", "masks")
+
+STATUS = {0: "SLRX_OK", -1: "SLRX_EINVAL", -2: "SLRX_ENOMEM", -3: "SLRX_EDEVICE", -4: "SLRX_ESTATE",
+          -5: "SLRX_ENUMERIC", -6: "SLRX_EBUSY", -7: "SLRX_ENOTREADY"}
+
+
+class SlrxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("Q", ctypes.c_int32), ("T", ctypes.c_int32),
+                ("N1", ctypes.c_int32), ("N2", ctypes.c_int32), ("M", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("p", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("eps0_frac", ctypes.c_double), ("n_irls", ctypes.c_int32), ("n_cg", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_irls_done", ctypes.c_int32),
+                ("eps", ctypes.c_double * MAX_IRLS),
+                ("lambda_max", ctypes.c_double * MAX_IRLS),
+                ("cg_rr_final", ctypes.c_double * MAX_IRLS),
+                ("ms_total", ctypes.c_double), ("ms_gram", ctypes.c_double), ("ms_eigh", ctypes.c_double),
+                ("ms_weights", ctypes.c_double), ("ms_cg", ctypes.c_double),
+                ("kt_ms", ctypes.c_double * 8), ("kt_count", ctypes.c_int32 * 8)]
+
+    def as_dict(self) -> dict:
+        n = self.n_irls_done
+        return {"n_irls": n, "eps": list(self.eps[:n]), "lambda_max": list(self.lambda_max[:n]),
+                "cg_rr_final": list(self.cg_rr_final[:n]), "ms_total": self.ms_total,
+                "ms_gram": self.ms_gram, "ms_eigh": self.ms_eigh, "ms_weights": self.ms_weights,
+                "ms_cg": self.ms_cg,
+                "kernel_ms": {k: self.kt_ms[i] for i, k in enumerate(KERNEL_CLASSES)},
+                "kernel_count": {k: self.kt_count[i] for i, k in enumerate(KERNEL_CLASSES)}}
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("state", ctypes.c_int32), ("status", ctypes.c_int32), ("bytes", ctypes.c_size_t)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_SIGS = {
+    "slrx_default_params": (None, [ctypes.POINTER(Params)]),
+    "slrx_validate": (_I, [ctypes.POINTER(Dims), ctypes.POINTER(Params)]),
+    "slrx_footprint": (ctypes.c_size_t, [ctypes.POINTER(Dims)]),
+    "slrx_plan_create": (_I, [ctypes.POINTER(Dims), ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]),
+    "slrx_plan_destroy": (None, [_P]),
+    "slrx_set_kspace": (_I, [_P, _P, _I]),
+    "slrx_set_mask": (_I, [_P, _P, _I]),
+    "slrx_set_init": (_I, [_P, _P, _I]),
+    "slrx_clear_init": (_I, [_P]),
+    "slrx_set_filter": (_I, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "slrx_set_params": (_I, [_P, ctypes.POINTER(Params)]),
+    "slrx_run": (_I, [_P]),
+    "slrx_sync": (_I, [_P]),
+    "slrx_get_images": (_I, [_P, _P, _I]),
+    "slrx_get_kspace": (_I, [_P, _P, _I]),
+    "slrx_get_stats": (_I, [_P, ctypes.POINTER(Stats)]),
+    "slrx_run_batch": (_I, [ctypes.POINTER(_P), ctypes.c_int32, _P]),
+    "slrx_step_gram": (_I, [_P, _P, _I]),
+    "slrx_step_weights": (_I, [_P, ctypes.c_double, _P, _P, _P, _I]),
+    "slrx_step_apply": (_I, [_P, _P, _P, _P, _I]),
+    "slrx_step_cg": (_I, [_P, _P, ctypes.c_int32]),
+    "slrx_server_create": (_I, [ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "slrx_server_destroy": (None, [_P]),
+    "slrx_submit": (_I, [_P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "slrx_poll": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
+    "slrx_wait": (_I, [_P, ctypes.c_uint64]),
+    "slrx_submit_data": (_I, [_P, ctypes.POINTER(Dims), ctypes.POINTER(Params), _P, _P,
+                              ctypes.POINTER(ctypes.c_uint64)]),
+    "slrx_get_request_info": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(RequestInfo)]),
+    "slrx_server_usage": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32)]),
+    "slrx_fetch_images": (_I, [_P, ctypes.c_uint64, _P]),
+    "slrx_release": (_I, [_P, ctypes.c_uint64]),
+    "slrx_status_str": (ctypes.c_char_p, [_I]),
+    "slrx_last_error": (ctypes.c_char_p, []),
+}
+
+
+def exported_symbols() -> list[str]:
+    return list(_SIGS)
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libslrx.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                raise RuntimeError(f"libslrx.so not built at {_LIB_PATH}; run python -m paper_1704_04511_amd.build")
+            L = ctypes.CDLL(_LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise SlrxError(status, lib().slrx_last_error().decode(errors="replace"))
+
+
+def default_params() -> Params:
+    p = Params()
+    lib().slrx_default_params(ctypes.byref(p))
+    return p
+
+
+def make_params(lam=1e-3, n_irls=15, n_cg=10, p=0.6, gamma=1.4, eps0_frac=0.01, timing=False,
+                ktime=False) -> Params:
+    flags = (SLRX_FLAG_TIMING if timing else 0) | (SLRX_FLAG_KTIME if ktime else 0)
+    return Params(float(lam), float(p), float(gamma), float(eps0_frac), int(n_irls), int(n_cg), flags)
+
+
+def validate(dims: Dims, params: Params | None = None) -> None:
+    _check(lib().slrx_validate(ctypes.byref(dims), ctypes.byref(params) if params is not None else None))
+
+
+def footprint(dims: Dims) -> int:
+    return int(lib().slrx_footprint(ctypes.byref(dims)))
+
+
+def _ptr(a, dtype, shape=None):
+    """(pointer, mem kind, keep-alive) for a NumPy array or a torch device tensor."""
+    if isinstance(a, torch.Tensor):
+        if not a.is_cuda:
+            a = a.contiguous().numpy()
+        else:
+            if not a.is_contiguous():
+                raise ValueError("device tensors must be contiguous")
+            tdt = {np.complex64: torch.complex64, np.uint8: torch.uint8, np.float64: torch.float64,
+                   np.complex128: torch.complex128}[dtype]
+            if a.dtype != tdt:
+                raise TypeError(f"expected {tdt}, got {a.dtype}")
+            if shape is not None and tuple(a.shape) != tuple(shape):
+                raise ValueError(f"expected shape {shape}, got {tuple(a.shape)}")
+            return ctypes.c_void_p(a.data_ptr()), SLRX_MEM_DEVICE, a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if shape is not None and arr.shape != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {arr.shape}")
+    return arr.ctypes.data_as(ctypes.c_void_p), SLRX_MEM_HOST, arr
+
+
+class Plan:
+    """One reconstruction problem resident on the GPU."""
+
+    def __init__(self, P, Q, T, N1, N2, M, params: Params | None = None, stream=None):
+        self.dims = Dims(P, Q, T, N1, N2, M)
+        self.params = params if params is not None else default_params()
+        h = ctypes.c_void_p()
+        st = None if stream is None else ctypes.c_void_p(int(stream))
+        _check(lib().slrx_plan_create(ctypes.byref(self.dims), ctypes.byref(self.params), st, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def shape(self):
+        d = self.dims
+        return (d.T, d.P, d.Q)
+
+    @property
+    def W(self):
+        return self.dims.M * (self.dims.M + 1) // 2
+
+    @property
+    def s(self):
+        d = self.dims
+        return d.N1 * d.N2 * d.M
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().slrx_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_kspace(self, b):
+        ptr, mem, keep = _ptr(b, np.complex64, self.shape)
+        _check(lib().slrx_set_kspace(self._h, ptr, mem))
+        self._keep_b = keep
+
+    def set_mask(self, S):
+        ptr, mem, keep = _ptr(S, np.uint8, self.shape)
+        _check(lib().slrx_set_mask(self._h, ptr, mem))
+        self._keep_S = keep
+
+    def set_init(self, x0):
+        ptr, mem, keep = _ptr(x0, np.complex64, self.shape)
+        _check(lib().slrx_set_init(self._h, ptr, mem))
+        self._keep_x0 = keep
+
+    def clear_init(self):
+        _check(lib().slrx_clear_init(self._h))
+
+    def set_filter(self, N1, N2, M):
+        _check(lib().slrx_set_filter(self._h, N1, N2, M))
+        self.dims.N1, self.dims.N2, self.dims.M = N1, N2, M
+
+    def set_params(self, params: Params):
+        _check(lib().slrx_set_params(self._h, ctypes.byref(params)))
+        self.params = params
+
+    def run(self):
+        _check(lib().slrx_run(self._h))
+
+    def sync(self):
+        _check(lib().slrx_sync(self._h))
+
+    def images(self, out=None):
+        if out is None:
+            out = np.empty(self.shape, np.complex64)
+        ptr, mem, _ = _ptr(out, np.complex64, self.shape)
+        _check(lib().slrx_get_images(self._h, ptr, mem))
+        return out
+
+    def kspace(self, out=None):
+        if out is None:
+            out = np.empty(self.shape, np.complex64)
+        ptr, mem, _ = _ptr(out, np.complex64, self.shape)
+        _check(lib().slrx_get_kspace(self._h, ptr, mem))
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().slrx_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    # ---- single steps
+    def step_gram(self):
+        s = self.s
+        R = np.empty((s, s), np.complex128, order="F")
+        _check(lib().slrx_step_gram(self._h, R.ctypes.data_as(ctypes.c_void_p), SLRX_MEM_HOST))
+        return R
+
+    def step_weights(self, eps: float):
+        s, d = self.s, self.dims
+        lam = np.empty(s, np.float64)
+        H = np.empty((s, s), np.complex128)
+        E = np.empty((self.W, d.P, d.Q), np.complex64)
+        _check(lib().slrx_step_weights(self._h, float(eps), lam.ctypes.data_as(ctypes.c_void_p),
+                                       H.ctypes.data_as(ctypes.c_void_p), E.ctypes.data_as(ctypes.c_void_p),
+                                       SLRX_MEM_HOST))
+        return lam, H, E
+
+    def step_apply(self, E, v):
+        d = self.dims
+        Ep, _, Ek = _ptr(E, np.complex64, (self.W, d.P, d.Q))
+        vp, _, vk = _ptr(v, np.complex64, self.shape)
+        out = np.empty(self.shape, np.complex64)
+        _check(lib().slrx_step_apply(self._h, Ep, vp, out.ctypes.data_as(ctypes.c_void_p), SLRX_MEM_HOST))
+        return out
+
+    def step_cg(self, E, n_cg: int):
+        d = self.dims
+        Ep, _, Ek = _ptr(E, np.complex64, (self.W, d.P, d.Q))
+        _check(lib().slrx_step_cg(self._h, Ep, int(n_cg)))
+
+
+def run_batch(plans, stream=None):
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    st = None if stream is None else ctypes.c_void_p(int(stream))
+    _check(lib().slrx_run_batch(arr, len(plans), st))
+
+
+class Server:
+    """Continuous-batching request server (see slrx.h)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 8, stream=None):
+        h = ctypes.c_void_p()
+        st = None if stream is None else ctypes.c_void_p(int(stream))
+        _check(lib().slrx_server_create(int(budget_bytes), int(max_slots), st, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().slrx_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, plan: Plan) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().slrx_submit(self._h, plan.handle, ctypes.byref(t)))
+        return t.value
+
+    def submit_data(self, b, S, N1, N2, M, params: Params | None = None) -> int:
+        """Queue a reconstruction of host arrays; the server allocates its plan at admission."""
+        b = np.ascontiguousarray(b, np.complex64)
+        S = np.ascontiguousarray(S, np.uint8)
+        if b.shape != S.shape or b.ndim != 3:
+            raise ValueError("b and S must both be [T, P, Q]")
+        T, P, Q = b.shape
+        dims = Dims(P, Q, T, N1, N2, M)
+        prm = params if params is not None else default_params()
+        t = ctypes.c_uint64()
+        _check(lib().slrx_submit_data(self._h, ctypes.byref(dims), ctypes.byref(prm),
+                                      b.ctypes.data_as(ctypes.c_void_p), S.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        _check(lib().slrx_poll(self._h, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        _check(lib().slrx_wait(self._h, ticket))
+
+    def info(self, ticket: int) -> dict:
+        ri = RequestInfo()
+        _check(lib().slrx_get_request_info(self._h, ticket, ctypes.byref(ri)))
+        return {"t_submit": ri.t_submit, "t_admit": ri.t_admit, "t_done": ri.t_done, "state": ri.state,
+                "status": ri.status, "bytes": ri.bytes}
+
+    def usage(self) -> tuple[int, int]:
+        used = ctypes.c_size_t()
+        q = ctypes.c_int32()
+        _check(lib().slrx_server_usage(self._h, ctypes.byref(used), ctypes.byref(q)))
+        return used.value, q.value
+
+    def fetch(self, ticket: int, shape) -> np.ndarray:
+        out = np.empty(shape, np.complex64)
+        _check(lib().slrx_fetch_images(self._h, ticket, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def release(self, ticket: int):
+        _check(lib().slrx_release(self._h, ticket))

@@ -1,0 +1,668 @@
+// libslrx C ABI: plans, the IRLS loop of Algorithm 1 on one GPU, single-step
+// entry points, batch execution.  Host orchestration only; every arithmetic
+// step runs in the kernels of k_op.hip / k_gram.hip (and rocSOLVER's FP64
+// Hermitian eigensolver).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+#include "../../include/slrx.h"
+
+using namespace slrx;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+slrx_status slrx::fail(slrx_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(SLRX_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                  __LINE__);                                                                \
+  } while (0)
+
+#define STCHK(expr)                     \
+  do {                                  \
+    slrx_status _s = (expr);            \
+    if (_s != SLRX_OK) return _s;       \
+  } while (0)
+
+slrx::KTimer::KTimer(slrx_plan* p, int c) : pl(p), cls(c) {
+  if (!pl->ktime) return;
+  auto& v = pl->kev[cls];
+  const int i = pl->kused[cls];
+  while ((int)v.size() < 2 * (i + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    v.push_back(e);
+  }
+  if (hipEventRecord(v[2 * i], pl->stream) != hipSuccess) return;
+  idx = i;
+  pl->kused[cls] = i + 1;
+}
+
+slrx::KTimer::~KTimer() {
+  if (idx >= 0) (void)hipEventRecord(pl->kev[cls][2 * idx + 1], pl->stream);
+}
+
+extern "C" const char* slrx_status_str(slrx_status s) {
+  switch (s) {
+    case SLRX_OK: return "ok";
+    case SLRX_EINVAL: return "invalid argument";
+    case SLRX_ENOMEM: return "out of device memory";
+    case SLRX_EDEVICE: return "device error";
+    case SLRX_ESTATE: return "invalid state";
+    case SLRX_ENUMERIC: return "numerical failure";
+    case SLRX_EBUSY: return "busy";
+    case SLRX_ENOTREADY: return "not ready";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* slrx_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" void slrx_default_params(slrx_params* out) {
+  if (!out) return;
+  out->lambda = 1e-3;
+  out->p = 0.6;
+  out->gamma = 1.4;
+  out->eps0_frac = 0.01;
+  out->n_irls = 15;
+  out->n_cg = 10;
+  out->flags = 0;
+}
+
+// -------------------------------------------------------------- validation
+static slrx_status validate_dims(const slrx_dims* d) {
+  if (!d) return fail(SLRX_EINVAL, "dims is NULL");
+  if (!fft_len_supported(d->P) || !fft_len_supported(d->Q))
+    return fail(SLRX_EINVAL, "unsupported frame size %dx%d (supported: 8,16,32,64,96,128,160,192,256)", d->P, d->Q);
+  if (d->T < 1 || d->T > max_frames()) return fail(SLRX_EINVAL, "T=%d out of range [1,%d]", d->T, max_frames());
+  if (d->M < 1 || d->M > d->T || d->M > max_taps())
+    return fail(SLRX_EINVAL, "M=%d out of range [1,min(T,%d)]", d->M, max_taps());
+  if (d->N1 < 1 || d->N1 > d->P || d->N2 < 1 || d->N2 > d->Q)
+    return fail(SLRX_EINVAL, "filter %dx%d does not fit the %dx%d frame", d->N1, d->N2, d->P, d->Q);
+  const long s = (long)d->N1 * d->N2 * d->M;
+  if (s > kMaxS) return fail(SLRX_EINVAL, "filter size s=%ld exceeds %d", s, kMaxS);
+  return SLRX_OK;
+}
+
+static slrx_status validate_params(const slrx_params* p) {
+  if (!p) return fail(SLRX_EINVAL, "params is NULL");
+  if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return fail(SLRX_EINVAL, "lambda must be finite and >= 0");
+  if (!(p->p >= 0.0 && p->p <= 1.0)) return fail(SLRX_EINVAL, "p must be in [0,1]");
+  if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return fail(SLRX_EINVAL, "gamma must be finite and > 1");
+  if (!(p->eps0_frac > 0.0) || !std::isfinite(p->eps0_frac)) return fail(SLRX_EINVAL, "eps0_frac must be finite and > 0");
+  if (p->n_irls < 1 || p->n_irls > SLRX_MAX_IRLS) return fail(SLRX_EINVAL, "n_irls must be in [1,%d]", SLRX_MAX_IRLS);
+  if (p->n_cg < 0 || p->n_cg > kMaxCg) return fail(SLRX_EINVAL, "n_cg must be in [0,%d]", kMaxCg);
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_validate(const slrx_dims* dims, const slrx_params* params) {
+  STCHK(validate_dims(dims));
+  if (params) STCHK(validate_params(params));
+  return SLRX_OK;
+}
+
+// ------------------------------------------------------------- footprint
+static size_t align_up(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Buffer layout of one plan; used both for the footprint and for allocation.
+struct Layout {
+  size_t off[kNumBuf];
+  size_t total;
+};
+
+static Layout plan_layout(const slrx_dims& d) {
+  const size_t V = (size_t)d.T * d.P * d.Q;
+  const size_t s = (size_t)d.N1 * d.N2 * d.M;
+  const size_t W = (size_t)d.M * (d.M + 1) / 2;
+  const size_t L1 = 2 * d.N1 - 1, L2 = 2 * d.N2 - 1;
+  size_t sz[kNumBuf] = {};
+  sz[B_B] = V * 8;
+  sz[B_BM] = V * 8;
+  sz[B_X0] = V * 8;
+  sz[B_IMG] = V * 8;
+  sz[B_X] = V * 8;
+  sz[B_R] = V * 8;
+  sz[B_P] = V * 8;
+  sz[B_Q] = V * 8;
+  sz[B_T] = V * 8;
+  sz[B_S] = V;
+  sz[B_ET] = W * d.P * d.Q * 8;
+  sz[B_ESTAGE] = W * d.P * d.Q * 8;
+  sz[B_TWPF] = d.P * 8;
+  sz[B_TWQF] = d.Q * 8;
+  sz[B_TWPD] = d.P * 16;
+  sz[B_TWQD] = d.Q * 16;
+  sz[B_C1] = W * d.P * L2 * 16;
+  sz[B_G] = W * L1 * L2 * 16;
+  sz[B_RM] = s * s * 16;
+  sz[B_LAM] = s * 8;
+  sz[B_EWORK] = s * 8;
+  sz[B_VT] = 2 * s * s * 8;
+  sz[B_HRE] = s * s * 8;
+  sz[B_HIM] = s * s * 8;
+  sz[B_WSUM] = W * L1 * L2 * 16;
+  sz[B_S1] = W * L1 * d.Q * 16;
+  sz[B_PARTA] = 4096 * 8;
+  sz[B_PARTB] = 4096 * 8;
+  sz[B_RRH] = (kMaxCg + 2) * 8;
+  sz[B_SCAL] = 64 * 8;
+  sz[B_STATS] = 3 * SLRX_MAX_IRLS * 8;
+  sz[B_INFO] = (SLRX_MAX_IRLS + 1) * 4;
+  sz[B_FLAG] = 64;
+  Layout L;
+  size_t o = 0;
+  for (int i = 0; i < kNumBuf; ++i) {
+    L.off[i] = o;
+    o += align_up(sz[i]);
+  }
+  L.total = o;
+  return L;
+}
+
+extern "C" size_t slrx_footprint(const slrx_dims* dims) {
+  if (validate_dims(dims) != SLRX_OK) return 0;
+  // plan buffers plus the eigensolver workspace (bounded estimate: 3 s^2 complex + s^2 real)
+  const size_t s = (size_t)dims->N1 * dims->N2 * dims->M;
+  return plan_layout(*dims).total + align_up(s * s * 16 * 3 + s * s * 8 + (1 << 20));
+}
+
+// ------------------------------------------------------------ plan create
+static slrx_status make_twiddles(slrx_plan* pl) {
+  const int P = pl->cap.P, Q = pl->cap.Q;
+  std::vector<float2> fp(P), fq(Q);
+  std::vector<double2> dp(P), dq(Q);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int t = 0; t < P; ++t) {
+    const double a = -two_pi * (double)t / (double)P;
+    dp[t] = make_double2(std::cos(a), std::sin(a));
+    fp[t] = make_float2((float)dp[t].x, (float)dp[t].y);
+  }
+  for (int t = 0; t < Q; ++t) {
+    const double a = -two_pi * (double)t / (double)Q;
+    dq[t] = make_double2(std::cos(a), std::sin(a));
+    fq[t] = make_float2((float)dq[t].x, (float)dq[t].y);
+  }
+  HIPCHK(hipMemcpy(pl->twPf, fp.data(), P * sizeof(float2), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->twQf, fq.data(), Q * sizeof(float2), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->twPd, dp.data(), P * sizeof(double2), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->twQd, dq.data(), Q * sizeof(double2), hipMemcpyHostToDevice));
+  return SLRX_OK;
+}
+
+static slrx_status setup_eigensolver(slrx_plan* pl) {
+  if (rocblas_create_handle(&pl->blas) != rocblas_status_success)
+    return fail(SLRX_EDEVICE, "rocblas_create_handle failed");
+  if (rocblas_set_stream(pl->blas, pl->stream) != rocblas_status_success)
+    return fail(SLRX_EDEVICE, "rocblas_set_stream failed");
+  const int s = pl->cap.N1 * pl->cap.N2 * pl->cap.M;
+  size_t ws = 0;
+  rocblas_start_device_memory_size_query(pl->blas);
+  // sizes for every s up to the capacity are bounded by the capacity's
+  rocsolver_zheevd(pl->blas, rocblas_evect_original, rocblas_fill_lower, s,
+                   (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework, pl->info);
+  rocblas_stop_device_memory_size_query(pl->blas, &ws);
+  if (ws < 1024) ws = 1024;
+  if (hipMalloc(&pl->blas_ws, ws) != hipSuccess) return fail(SLRX_ENOMEM, "eigensolver workspace (%zu bytes)", ws);
+  pl->blas_ws_size = ws;
+  if (rocblas_set_workspace(pl->blas, pl->blas_ws, ws) != rocblas_status_success)
+    return fail(SLRX_EDEVICE, "rocblas_set_workspace failed");
+  return SLRX_OK;
+}
+
+static void assign_buffers(slrx_plan* pl, const Layout& L) {
+  char* b = (char*)pl->arena;
+  auto at = [&](int i) { return (void*)(b + L.off[i]); };
+  pl->b = (float2*)at(B_B);
+  pl->bm = (float2*)at(B_BM);
+  pl->x0 = (float2*)at(B_X0);
+  pl->img = (float2*)at(B_IMG);
+  pl->x = (float2*)at(B_X);
+  pl->r = (float2*)at(B_R);
+  pl->p = (float2*)at(B_P);
+  pl->q = (float2*)at(B_Q);
+  pl->t = (float2*)at(B_T);
+  pl->S = (uint8_t*)at(B_S);
+  pl->Et = (float2*)at(B_ET);
+  pl->Estage = (float2*)at(B_ESTAGE);
+  pl->twPf = (float2*)at(B_TWPF);
+  pl->twQf = (float2*)at(B_TWQF);
+  pl->twPd = (double2*)at(B_TWPD);
+  pl->twQd = (double2*)at(B_TWQD);
+  pl->c1 = (double2*)at(B_C1);
+  pl->g = (double2*)at(B_G);
+  pl->Rm = (double2*)at(B_RM);
+  pl->lam = (double*)at(B_LAM);
+  pl->ework = (double*)at(B_EWORK);
+  pl->VT = (double*)at(B_VT);
+  pl->Hre = (double*)at(B_HRE);
+  pl->Him = (double*)at(B_HIM);
+  pl->wsum = (double2*)at(B_WSUM);
+  pl->s1 = (double2*)at(B_S1);
+  pl->partA = (double*)at(B_PARTA);
+  pl->partB = (double*)at(B_PARTB);
+  pl->rr_hist = (double*)at(B_RRH);
+  pl->scal = (double*)at(B_SCAL);
+  pl->stats = (double*)at(B_STATS);
+  pl->info = (rocblas_int*)at(B_INFO);
+  pl->flag = (int*)at(B_FLAG);
+}
+
+extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params* params, void* hip_stream,
+                                        slrx_plan** out) {
+  if (!out) return fail(SLRX_EINVAL, "out is NULL");
+  *out = nullptr;
+  STCHK(validate_dims(dims));
+  slrx_params prm;
+  if (params) {
+    STCHK(validate_params(params));
+    prm = *params;
+  } else {
+    slrx_default_params(&prm);
+  }
+  slrx_plan* pl = new (std::nothrow) slrx_plan();
+  if (!pl) return fail(SLRX_ENOMEM, "host allocation failed");
+  pl->cap = *dims;
+  pl->d = *dims;
+  pl->prm = prm;
+  HIPCHK(hipGetDevice(&pl->device));
+  if (hip_stream) {
+    pl->stream = (hipStream_t)hip_stream;
+    pl->own_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete pl;
+      return fail(SLRX_EDEVICE, "hipStreamCreate failed");
+    }
+    pl->own_stream = true;
+  }
+  const Layout L = plan_layout(*dims);
+  if (hipMalloc(&pl->arena, L.total) != hipSuccess) {
+    (void)hipGetLastError();
+    slrx_plan_destroy(pl);
+    return fail(SLRX_ENOMEM, "device allocation of %zu bytes failed", L.total);
+  }
+  pl->arena_bytes = L.total;
+  assign_buffers(pl, L);
+  slrx_status st = setup_eigensolver(pl);
+  if (st == SLRX_OK && hipMemset(pl->arena, 0, L.total) != hipSuccess) st = fail(SLRX_EDEVICE, "hipMemset failed");
+  if (st == SLRX_OK) st = make_twiddles(pl);
+  if (st == SLRX_OK) {
+    for (int i = 0; i < 2; ++i)
+      if (hipEventCreate(&pl->ev_run[i]) != hipSuccess) st = fail(SLRX_EDEVICE, "hipEventCreate failed");
+  }
+  if (st != SLRX_OK) {
+    slrx_plan_destroy(pl);
+    return st;
+  }
+  *out = pl;
+  return SLRX_OK;
+}
+
+extern "C" void slrx_plan_destroy(slrx_plan* pl) {
+  if (!pl) return;
+  if (pl->stream) (void)hipStreamSynchronize(pl->stream);
+  for (auto& e : pl->ev_phase) (void)hipEventDestroy(e);
+  for (auto& v : pl->kev)
+    for (auto& e : v) (void)hipEventDestroy(e);
+  for (int i = 0; i < 2; ++i)
+    if (pl->ev_run[i]) (void)hipEventDestroy(pl->ev_run[i]);
+  if (pl->blas) rocblas_destroy_handle(pl->blas);
+  if (pl->blas_ws) (void)hipFree(pl->blas_ws);
+  if (pl->arena) (void)hipFree(pl->arena);
+  if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
+  delete pl;
+}
+
+// ------------------------------------------------------------- host copies
+static slrx_status copy_in(slrx_plan* pl, void* dst, const void* src, size_t bytes, slrx_mem mem) {
+  if (!src) return fail(SLRX_EINVAL, "input pointer is NULL");
+  if (mem == SLRX_MEM_HOST) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
+  } else if (mem == SLRX_MEM_DEVICE) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, pl->stream));
+  } else {
+    return fail(SLRX_EINVAL, "bad memory kind %d", (int)mem);
+  }
+  return SLRX_OK;
+}
+
+static slrx_status copy_out(slrx_plan* pl, void* dst, const void* src, size_t bytes, slrx_mem mem) {
+  if (!dst) return fail(SLRX_EINVAL, "output pointer is NULL");
+  if (mem == SLRX_MEM_HOST) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
+  } else if (mem == SLRX_MEM_DEVICE) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, pl->stream));
+  } else {
+    return fail(SLRX_EINVAL, "bad memory kind %d", (int)mem);
+  }
+  return SLRX_OK;
+}
+
+static slrx_status check_idle(slrx_plan* pl) {
+  if (!pl) return fail(SLRX_EINVAL, "plan is NULL");
+  if (pl->running) {
+    const hipError_t q = hipEventQuery(pl->ev_run[1]);
+    if (q == hipErrorNotReady) return fail(SLRX_EBUSY, "plan is running");
+  }
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_set_kspace(slrx_plan* pl, const void* b, slrx_mem mem) {
+  STCHK(check_idle(pl));
+  STCHK(copy_in(pl, pl->b, b, pl->vol() * sizeof(float2), mem));
+  pl->has_b = true;
+  pl->prepared = false;
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_set_mask(slrx_plan* pl, const uint8_t* S, slrx_mem mem) {
+  STCHK(check_idle(pl));
+  STCHK(copy_in(pl, pl->S, S, pl->vol(), mem));
+  pl->has_S = true;
+  pl->prepared = false;
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_set_init(slrx_plan* pl, const void* x0, slrx_mem mem) {
+  STCHK(check_idle(pl));
+  STCHK(copy_in(pl, pl->x0, x0, pl->vol() * sizeof(float2), mem));
+  pl->has_init = true;
+  pl->prepared = false;
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_clear_init(slrx_plan* pl) {
+  STCHK(check_idle(pl));
+  pl->has_init = false;
+  pl->prepared = false;
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_set_filter(slrx_plan* pl, int32_t N1, int32_t N2, int32_t M) {
+  STCHK(check_idle(pl));
+  slrx_dims d = pl->d;
+  d.N1 = N1;
+  d.N2 = N2;
+  d.M = M;
+  STCHK(validate_dims(&d));
+  if (N1 > pl->cap.N1 || N2 > pl->cap.N2 || M > pl->cap.M)
+    return fail(SLRX_EINVAL, "filter %dx%dx%d exceeds the plan's capacity %dx%dx%d", N1, N2, M, pl->cap.N1,
+                pl->cap.N2, pl->cap.M);
+  pl->d = d;
+  pl->ran = false;
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_set_params(slrx_plan* pl, const slrx_params* prm) {
+  STCHK(check_idle(pl));
+  STCHK(validate_params(prm));
+  pl->prm = *prm;
+  return SLRX_OK;
+}
+
+slrx_status slrx::enqueue_run(slrx_plan* pl) {
+  STCHK(prepare(pl));
+  const bool timing = (pl->prm.flags & SLRX_FLAG_TIMING) != 0;
+  const int nirls = pl->prm.n_irls;
+  pl->ktime = (pl->prm.flags & SLRX_FLAG_KTIME) != 0;
+  for (int c = 0; c < SLRX_K_NCLASS; ++c) pl->kused[c] = 0;
+  if (timing) {
+    const size_t need = (size_t)nirls * 4 + 1;
+    while (pl->ev_phase.size() < need) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      pl->ev_phase.push_back(e);
+    }
+  }
+  HIPCHK(hipMemsetAsync(pl->info, 0, (SLRX_MAX_IRLS + 1) * sizeof(rocblas_int), pl->stream));
+  HIPCHK(hipEventRecord(pl->ev_run[0], pl->stream));
+  for (int it = 0; it < nirls; ++it) {
+    if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it], pl->stream));
+    STCHK(step_gram(pl));
+    if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 1], pl->stream));
+    STCHK(step_eigh(pl, it));
+    if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 2], pl->stream));
+    STCHK(step_weights(pl, it, it == 0, pl->prm.gamma));
+    if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 3], pl->stream));
+    STCHK(run_cg(pl, pl->prm.n_cg, it));
+  }
+  if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * nirls], pl->stream));
+  HIPCHK(hipEventRecord(pl->ev_run[1], pl->stream));
+  pl->running = true;
+  pl->ran = false;
+  pl->run_irls = nirls;
+  pl->run_timing = timing;
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_run(slrx_plan* pl) {
+  STCHK(check_idle(pl));
+  return enqueue_run(pl);
+}
+
+slrx_status slrx::finish(slrx_plan* pl) {
+  if (!pl->running) return SLRX_OK;
+  HIPCHK(hipEventSynchronize(pl->ev_run[1]));
+  pl->running = false;
+  pl->ran = true;
+  std::vector<rocblas_int> info(pl->run_irls);
+  HIPCHK(hipMemcpy(info.data(), pl->info, pl->run_irls * sizeof(rocblas_int), hipMemcpyDeviceToHost));
+  std::vector<double> st(3 * SLRX_MAX_IRLS);
+  HIPCHK(hipMemcpy(st.data(), pl->stats, st.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int it = 0; it < pl->run_irls; ++it) {
+    if (info[it] != 0) {
+      pl->ran = false;
+      return fail(SLRX_ENUMERIC, "eigen-decomposition did not converge at outer iteration %d (info %d)", it,
+                  (int)info[it]);
+    }
+    if (!std::isfinite(st[SLRX_MAX_IRLS + it]) || !std::isfinite(st[it])) {
+      pl->ran = false;
+      return fail(SLRX_ENUMERIC, "non-finite Gram eigenvalues at outer iteration %d", it);
+    }
+  }
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_sync(slrx_plan* pl) {
+  if (!pl) return fail(SLRX_EINVAL, "plan is NULL");
+  STCHK(finish(pl));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  return SLRX_OK;
+}
+
+static slrx_status require_done(slrx_plan* pl) {
+  if (!pl) return fail(SLRX_EINVAL, "plan is NULL");
+  if (pl->running) {
+    if (hipEventQuery(pl->ev_run[1]) == hipErrorNotReady) return fail(SLRX_EBUSY, "plan is running");
+    STCHK(finish(pl));
+  }
+  if (!pl->ran) return fail(SLRX_ENOTREADY, "no completed run");
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_get_images(slrx_plan* pl, void* out, slrx_mem mem) {
+  STCHK(require_done(pl));
+  STCHK(images(pl));
+  return copy_out(pl, out, pl->img, pl->vol() * sizeof(float2), mem);
+}
+
+extern "C" slrx_status slrx_get_kspace(slrx_plan* pl, void* out, slrx_mem mem) {
+  STCHK(require_done(pl));
+  return copy_out(pl, out, pl->x, pl->vol() * sizeof(float2), mem);
+}
+
+extern "C" slrx_status slrx_get_stats(slrx_plan* pl, slrx_stats* out) {
+  if (!out) return fail(SLRX_EINVAL, "out is NULL");
+  STCHK(require_done(pl));
+  std::memset(out, 0, sizeof *out);
+  std::vector<double> st(3 * SLRX_MAX_IRLS);
+  HIPCHK(hipMemcpy(st.data(), pl->stats, st.size() * sizeof(double), hipMemcpyDeviceToHost));
+  out->n_irls_done = pl->run_irls;
+  for (int i = 0; i < pl->run_irls; ++i) {
+    out->eps[i] = st[i];
+    out->lambda_max[i] = st[SLRX_MAX_IRLS + i];
+    out->cg_rr_final[i] = st[2 * SLRX_MAX_IRLS + i];
+  }
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, pl->ev_run[0], pl->ev_run[1]));
+  out->ms_total = ms;
+  if (pl->ktime) {
+    for (int c = 0; c < SLRX_K_NCLASS; ++c) {
+      double tot = 0.0;
+      for (int i = 0; i < pl->kused[c]; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pl->kev[c][2 * i], pl->kev[c][2 * i + 1]));
+        tot += ms;
+      }
+      out->kt_ms[c] = tot;
+      out->kt_count[c] = pl->kused[c];
+    }
+  }
+  if (pl->run_timing) {
+    for (int it = 0; it < pl->run_irls; ++it) {
+      float a = 0, b = 0, c = 0, e = 0;
+      HIPCHK(hipEventElapsedTime(&a, pl->ev_phase[4 * it], pl->ev_phase[4 * it + 1]));
+      HIPCHK(hipEventElapsedTime(&b, pl->ev_phase[4 * it + 1], pl->ev_phase[4 * it + 2]));
+      HIPCHK(hipEventElapsedTime(&c, pl->ev_phase[4 * it + 2], pl->ev_phase[4 * it + 3]));
+      HIPCHK(hipEventElapsedTime(&e, pl->ev_phase[4 * it + 3], pl->ev_phase[4 * it + 4]));
+      out->ms_gram += a;
+      out->ms_eigh += b;
+      out->ms_weights += c;
+      out->ms_cg += e;
+    }
+  }
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_run_batch(slrx_plan* const* plans, int32_t n, void* hip_stream) {
+  if (!plans || n < 0) return fail(SLRX_EINVAL, "bad plan list");
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(SLRX_EINVAL, "plan %d is NULL", i);
+    STCHK(check_idle(plans[i]));
+  }
+  for (int i = 0; i < n; ++i) {
+    slrx_plan* pl = plans[i];
+    hipStream_t own = pl->stream;
+    if (hip_stream) pl->stream = (hipStream_t)hip_stream;
+    if (hip_stream && pl->blas) rocblas_set_stream(pl->blas, pl->stream);
+    slrx_status st = enqueue_run(pl);
+    if (hip_stream) {
+      pl->stream = own;
+      if (pl->blas) rocblas_set_stream(pl->blas, own);
+    }
+    if (st != SLRX_OK) return st;
+  }
+  return SLRX_OK;
+}
+
+// ------------------------------------------------------------ single steps
+static slrx_status ensure_prepared(slrx_plan* pl) {
+  STCHK(check_idle(pl));
+  if (pl->running) STCHK(finish(pl));
+  if (!pl->prepared) STCHK(prepare(pl));
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_step_gram(slrx_plan* pl, void* R_out, slrx_mem mem) {
+  STCHK(ensure_prepared(pl));
+  STCHK(step_gram(pl));
+  const size_t s = (size_t)pl->d.N1 * pl->d.N2 * pl->d.M;
+  STCHK(copy_out(pl, R_out, pl->Rm, s * s * 16, mem));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_step_weights(slrx_plan* pl, double eps, double* lam_out, void* H_out, void* E_out,
+                                         slrx_mem mem) {
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(SLRX_EINVAL, "eps must be finite and > 0");
+  STCHK(ensure_prepared(pl));
+  STCHK(step_gram(pl));
+  STCHK(step_eigh(pl, -1));
+  HIPCHK(hipMemcpyAsync(pl->scal, &eps, sizeof(double), hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  STCHK(step_weights(pl, -1, false, 1.0));
+  const slrx_dims& d = pl->d;
+  const size_t s = (size_t)d.N1 * d.N2 * d.M;
+  const size_t W = (size_t)d.M * (d.M + 1) / 2;
+  if (lam_out) STCHK(copy_out(pl, lam_out, pl->lam, s * 8, mem));
+  if (H_out) {
+    if (mem == SLRX_MEM_DEVICE) {
+      HIPCHK(launch_interleave((long)(s * s), pl->Hre, pl->Him, (double2*)H_out, pl->stream));
+    } else {
+      std::vector<double> re(s * s), im(s * s);
+      HIPCHK(hipMemcpyAsync(re.data(), pl->Hre, s * s * 8, hipMemcpyDeviceToHost, pl->stream));
+      HIPCHK(hipMemcpyAsync(im.data(), pl->Him, s * s * 8, hipMemcpyDeviceToHost, pl->stream));
+      HIPCHK(hipStreamSynchronize(pl->stream));
+      double* h = (double*)H_out;
+      for (size_t i = 0; i < s * s; ++i) {
+        h[2 * i] = re[i];
+        h[2 * i + 1] = im[i];
+      }
+    }
+  }
+  if (E_out) {
+    STCHK(store_masks(pl));
+    STCHK(copy_out(pl, E_out, pl->Estage, W * d.P * d.Q * sizeof(float2), mem));
+  }
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  int info = 0;
+  HIPCHK(hipMemcpy(&info, pl->info + SLRX_MAX_IRLS, sizeof(int), hipMemcpyDeviceToHost));
+  if (info != 0) return fail(SLRX_ENUMERIC, "eigen-decomposition did not converge (info %d)", info);
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_step_apply(slrx_plan* pl, const void* E, const void* v, void* out, slrx_mem mem) {
+  STCHK(ensure_prepared(pl));
+  const slrx_dims& d = pl->d;
+  const size_t W = (size_t)d.M * (d.M + 1) / 2;
+  STCHK(copy_in(pl, pl->Estage, E, W * d.P * d.Q * sizeof(float2), mem));
+  STCHK(load_masks(pl, pl->Estage));
+  STCHK(copy_in(pl, pl->r, v, pl->vol() * sizeof(float2), mem));
+  STCHK(apply_op(pl, pl->r, pl->q, false, pl->partA));
+  STCHK(copy_out(pl, out, pl->q, pl->vol() * sizeof(float2), mem));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_step_cg(slrx_plan* pl, const void* E, int32_t n_cg) {
+  if (n_cg < 0 || n_cg > kMaxCg) return fail(SLRX_EINVAL, "n_cg out of range");
+  STCHK(ensure_prepared(pl));
+  pl->ktime = false;
+  const slrx_dims& d = pl->d;
+  const size_t W = (size_t)d.M * (d.M + 1) / 2;
+  STCHK(copy_in(pl, pl->Estage, E, W * d.P * d.Q * sizeof(float2), SLRX_MEM_HOST));
+  STCHK(load_masks(pl, pl->Estage));
+  STCHK(run_cg(pl, n_cg, -1));
+  HIPCHK(hipEventRecord(pl->ev_run[0], pl->stream));
+  HIPCHK(hipEventRecord(pl->ev_run[1], pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  pl->ran = true;
+  pl->run_irls = 0;
+  pl->run_timing = false;
+  return SLRX_OK;
+}

@@ -1,0 +1,197 @@
+// Stockham autosort FFT building blocks for data staged in LDS (gfx950).
+//
+// A length-N transform is a sequence of radix-R passes (R in {2,3,4,5,8,16});
+// pass s with radix R and current sub-transform length NS reads R elements at
+// stride N/R, multiplies by the twiddles w^{r k}, k = j mod NS, w = e^{s 2 pi i / (NS R)},
+// applies the R-point DFT in registers and writes them at stride NS starting at
+// (j / NS) NS R + k.  After the last pass the output is in natural order.
+// Passes run in place: every thread first pulls all of its butterflies into
+// registers, the block synchronises, then the results are written back.
+#pragma once
+#include "common.h"
+
+// ------------------------------------------------------------ small DFTs
+// X[k] = sum_j x[j] e^{SIGN 2 pi i j k / R}, in place on a register array.
+template <int R, int SIGN> struct Dft;
+
+template <int SIGN> struct Dft<2, SIGN> {
+  static SLRX_DEV void run(float2* v) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int SIGN> struct Dft<4, SIGN> {
+  static SLRX_DEV void run(float2* v) {
+    float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    float2 a2 = cadd(v[1], v[3]), a3 = cmul_i<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = cadd(a1, a3);
+    v[3] = csub(a1, a3);
+  }
+};
+
+template <int SIGN> struct Dft<3, SIGN> {
+  static SLRX_DEV void run(float2* v) {
+    const float h = 0.86602540378443865f;  // sqrt(3)/2
+    float2 t = cadd(v[1], v[2]);
+    float2 d = cmul_i<SIGN>(cscale(csub(v[1], v[2]), h));
+    float2 m = csub(v[0], cscale(t, 0.5f));
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, d);
+    v[2] = csub(m, d);
+  }
+};
+
+template <int SIGN> struct Dft<5, SIGN> {
+  static SLRX_DEV void run(float2* v) {
+    const float c1 = 0.30901699437494742f;   // cos(2 pi/5)
+    const float c2 = -0.80901699437494742f;  // cos(4 pi/5)
+    const float s1 = 0.95105651629515357f;   // sin(2 pi/5)
+    const float s2 = 0.58778525229247313f;   // sin(4 pi/5)
+    float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    float2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+    float2 x0 = v[0];
+    float2 a1 = make_float2(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
+    float2 a2 = make_float2(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
+    float2 b1 = cmul_i<SIGN>(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+    float2 b2 = cmul_i<SIGN>(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+    v[0] = cadd(x0, cadd(t1, t2));
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
+  }
+};
+
+// Radix 8 and 16 by one decimation-in-frequency split into two halves:
+// X[2k] = DFT_{R/2}(x_j + x_{j+R/2}), X[2k+1] = DFT_{R/2}((x_j - x_{j+R/2}) w^j).
+template <int SIGN> struct Dft<8, SIGN> {
+  static SLRX_DEV void run(float2* v) {
+    const float c = 0.70710678118654752f;
+    float2 a[4], b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      a[j] = cadd(v[j], v[j + 4]);
+      b[j] = csub(v[j], v[j + 4]);
+    }
+    // w8^j = e^{SIGN i pi j / 4}
+    b[1] = cmul(b[1], make_float2(c, SIGN * c));
+    b[2] = cmul_i<SIGN>(b[2]);
+    b[3] = cmul(b[3], make_float2(-c, SIGN * c));
+    Dft<4, SIGN>::run(a);
+    Dft<4, SIGN>::run(b);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] = a[k];
+      v[2 * k + 1] = b[k];
+    }
+  }
+};
+
+template <int SIGN> struct Dft<16, SIGN> {
+  static SLRX_DEV void run(float2* v) {
+    // cos/sin(pi j / 8), j = 0..7
+    const float cs[8] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f,
+                         0.0f, -0.38268343236508978f, -0.70710678118654752f, -0.92387953251128674f};
+    const float sn[8] = {0.0f, 0.38268343236508978f, 0.70710678118654752f, 0.92387953251128674f,
+                         1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f};
+    float2 a[8], b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      a[j] = cadd(v[j], v[j + 8]);
+      float2 d = csub(v[j], v[j + 8]);
+      b[j] = (j == 0) ? d : (j == 4) ? cmul_i<SIGN>(d) : cmul(d, make_float2(cs[j], SIGN * sn[j]));
+    }
+    Dft<8, SIGN>::run(a);
+    Dft<8, SIGN>::run(b);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      v[2 * k] = a[k];
+      v[2 * k + 1] = b[k];
+    }
+  }
+};
+
+// ------------------------------------------------------------- FFT plans
+template <int... Rs> struct Radices {};
+template <int N> struct FftPlan;
+template <> struct FftPlan<8> { using L = Radices<8>; };
+template <> struct FftPlan<16> { using L = Radices<16>; };
+template <> struct FftPlan<32> { using L = Radices<8, 4>; };
+template <> struct FftPlan<64> { using L = Radices<16, 4>; };
+template <> struct FftPlan<96> { using L = Radices<16, 3, 2>; };
+template <> struct FftPlan<128> { using L = Radices<16, 8>; };
+template <> struct FftPlan<160> { using L = Radices<16, 5, 2>; };
+template <> struct FftPlan<192> { using L = Radices<16, 4, 3>; };
+template <> struct FftPlan<256> { using L = Radices<16, 16>; };
+
+// Layout of a batch of transforms in LDS: element e of transform b sits at
+// b * BS + e * ES.  COLMAJOR chooses which index varies fastest across threads
+// (transform index for column tiles, element index for row tiles).
+// MAXB transforms at most; nb of them are live (runtime).
+template <int N, int R, int NS, int SIGN, int MAXB, int NT, int ES, int BS, bool COLMAJOR>
+SLRX_DEV void fft_pass(float2* lds, const float2* tw, int nb) {
+  constexpr int NBF = N / R;                 // butterflies per transform
+  constexpr int MAXTOT = MAXB * NBF;
+  constexpr int PER = (MAXTOT + NT - 1) / NT;
+  const int tot = nb * NBF;
+  float2 v[PER][R];
+  int base[PER], jj[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = threadIdx.x + i * NT;
+    int bt, j;
+    if (COLMAJOR) { bt = b % nb; j = b / nb; }
+    else { bt = b / NBF; j = b % NBF; }
+    base[i] = bt * BS;
+    jj[i] = j;
+    if (b < tot) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = lds[base[i] + (j + r * NBF) * ES];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = threadIdx.x + i * NT;
+    if (b < tot) {
+      const int j = jj[i];
+      const int k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[r * k * (N / (NS * R))];
+          if (SIGN > 0) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      Dft<R, SIGN>::run(v[i]);
+      const int o = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[base[i] + (o + r * NS) * ES] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int SIGN, int MAXB, int NT, int ES, int BS, bool COLMAJOR, int NS, int R, int... Rest>
+SLRX_DEV void fft_passes(float2* lds, const float2* tw, int nb) {
+  fft_pass<N, R, NS, SIGN, MAXB, NT, ES, BS, COLMAJOR>(lds, tw, nb);
+  if constexpr (sizeof...(Rest) > 0)
+    fft_passes<N, SIGN, MAXB, NT, ES, BS, COLMAJOR, NS * R, Rest...>(lds, tw, nb);
+}
+
+template <int N, int SIGN, int MAXB, int NT, int ES, int BS, bool COLMAJOR, int... Rs>
+SLRX_DEV void fft_run(float2* lds, const float2* tw, int nb, Radices<Rs...>) {
+  fft_passes<N, SIGN, MAXB, NT, ES, BS, COLMAJOR, 1, Rs...>(lds, tw, nb);
+}
+
+// Unnormalised length-N DFTs (sign SIGN) of nb <= MAXB transforms held in LDS.
+// tw[t] = e^{-2 pi i t / N} (also in LDS).  Must be called by all NT threads.
+template <int N, int SIGN, int MAXB, int NT, int ES, int BS, bool COLMAJOR>
+SLRX_DEV void fft_lds(float2* lds, const float2* tw, int nb) {
+  fft_run<N, SIGN, MAXB, NT, ES, BS, COLMAJOR>(lds, tw, nb, typename FftPlan<N>::L{});
+}

@@ -1,0 +1,362 @@
+// Weight update kernels (FP64): Gram matrix by Fourier autocorrelation,
+// IRLS weights, the filter product H = U diag(alpha) U^H on FP64 MFMA, and the
+// penalty masks E (summed power spectra of the weighted filters).
+//
+// Gram (Sec. III.C, eq. "eq:block-expression for R" and eq. "eq:P_ij modified"):
+//   c_{m,m'}(r) = sum_{n=M-1}^{T-1} conj(rho_{n-m}(r)) rho_{n-m'}(r),
+//   R[(m,a),(m',a')] = F_u(c_{m,m'})[a - a'],
+// where only the (2N1-1) x (2N2-1) lags of the sliding window are ever read,
+// so F_u is evaluated at those lags only (a pruned DFT, two small passes).
+//
+// Masks (Sec. III.A, eq. "eq:circ_fft" and the G precompute after eq.
+// "eq:grad_ls"): E_r[m,m'] = sum_i alpha_i conj(mu_m^(i)(r)) mu_m'^(i)(r)
+//   = sum_Delta w_{m',m}[Delta] e^{+2 pi i Delta.r},
+//   w_{m',m}[Delta] = sum_{a'-a = Delta} H[(m',a'),(m,a)].
+#include "common.h"
+#include "kernels.h"
+
+namespace slrx {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ Gram pass 1
+// Block per image row r1: lagged products for every tap pair (FP64), then the
+// pruned DFT along r2 at lags delta2 = -(N2-1)..(N2-1).
+template <int M>
+__global__ __launch_bounds__(256) void k_gram_rows(GramArgs a) {
+  constexpr int W = M * (M + 1) / 2;
+  extern __shared__ double2 sm[];  // cw[W][Q], tw[Q]
+  const int P = a.P, Q = a.Q, T = a.T, N2 = a.N2;
+  const int L2 = 2 * N2 - 1;
+  double2* cw = sm;
+  double2* tw = sm + (size_t)W * Q;
+  const int r1 = blockIdx.x;
+  const long fs = (long)P * Q;
+  for (int i = threadIdx.x; i < Q; i += 256) tw[i] = a.twQ[i];
+  for (int r2 = threadIdx.x; r2 < Q; r2 += 256) {
+    const long off = (long)r1 * Q + r2;
+    double2 acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = make_double2(0.0, 0.0);
+    double2 z[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) z[m] = f2d(a.rho[(long)(M - 1 - m) * fs + off]);
+    for (int n = M - 1; n < T; ++n) {
+      if (n > M - 1) {
+#pragma unroll
+        for (int m = M - 1; m > 0; --m) z[m] = z[m - 1];
+        z[0] = f2d(a.rho[(long)n * fs + off]);
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int mp = m; mp < M; ++mp) {
+          const int w = pair_id(m, mp, M);
+          acc[w] = dadd(acc[w], dcmul(z[m], z[mp]));
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) cw[(size_t)w * Q + r2] = acc[w];
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < W * L2; o += 256) {
+    const int w = o / L2, j2 = o % L2;
+    const int d2 = j2 - (N2 - 1);
+    const int dq = ((d2 % Q) + Q) % Q;
+    double sx = 0.0, sy = 0.0;
+    int idx = 0;
+    const double2* cr = cw + (size_t)w * Q;
+    for (int r2 = 0; r2 < Q; ++r2) {
+      const double2 c = cr[r2], t = tw[idx];
+      sx += c.x * t.x - c.y * t.y;
+      sy += c.x * t.y + c.y * t.x;
+      idx += dq;
+      if (idx >= Q) idx -= Q;
+    }
+    a.c1[((size_t)w * P + r1) * L2 + j2] = make_double2(sx, sy);
+  }
+}
+
+// Pass 2: pruned DFT along r1 at lags delta1 = -(N1-1)..(N1-1).
+__global__ __launch_bounds__(256) void k_gram_cols(GramArgs a, int W) {
+  const int L1 = 2 * a.N1 - 1, L2 = 2 * a.N2 - 1;
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= W * L1 * L2) return;
+  const int w = o / (L1 * L2), j1 = (o / L2) % L1, j2 = o % L2;
+  const int P = a.P;
+  const int d1 = j1 - (a.N1 - 1);
+  const int dp = ((d1 % P) + P) % P;
+  double sx = 0.0, sy = 0.0;
+  int idx = 0;
+  for (int r1 = 0; r1 < P; ++r1) {
+    const double2 c = a.c1[((size_t)w * P + r1) * L2 + j2];
+    const double2 t = a.twP[idx];
+    sx += c.x * t.x - c.y * t.y;
+    sy += c.x * t.y + c.y * t.x;
+    idx += dp;
+    if (idx >= P) idx -= P;
+  }
+  a.g[o] = make_double2(sx, sy);
+}
+
+// Pass 3: window extraction into R (column-major, full Hermitian matrix).
+__global__ __launch_bounds__(256) void k_gram_assemble(GramArgs a) {
+  const int N1 = a.N1, N2 = a.N2, M = a.M;
+  const int NN = N1 * N2, s = NN * M;
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)s * s) return;
+  const int i = (int)(idx % s), j = (int)(idx / s);  // R[i + j s]
+  const int m = i / NN, ia = i % NN, mp = j / NN, ib = j % NN;
+  const int a1 = ia / N2 - N1 / 2, a2 = ia % N2 - N2 / 2;
+  const int b1 = ib / N2 - N1 / 2, b2 = ib % N2 - N2 / 2;
+  const int L2 = 2 * N2 - 1, L1 = 2 * N1 - 1;
+  double2 v;
+  if (m <= mp) {
+    const int w = pair_id(m, mp, M);
+    v = a.g[((size_t)w * L1 + (a1 - b1 + N1 - 1)) * L2 + (a2 - b2 + N2 - 1)];
+  } else {
+    const int w = pair_id(mp, m, M);
+    v = dconj(a.g[((size_t)w * L1 + (b1 - a1 + N1 - 1)) * L2 + (b2 - a2 + N2 - 1)]);
+  }
+  a.R[idx] = v;
+}
+
+template <int M>
+static hipError_t gram_m(const GramArgs& a, hipStream_t s) {
+  constexpr int W = M * (M + 1) / 2;
+  const size_t lds = ((size_t)W * a.Q + a.Q) * sizeof(double2);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_gram_rows<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(((size_t)W * 256 + 256) * sizeof(double2)));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  k_gram_rows<M><<<a.P, 256, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
+  hipError_t e;
+  switch (a.M) {
+    case 1: e = gram_m<1>(a, s); break;
+    case 2: e = gram_m<2>(a, s); break;
+    case 3: e = gram_m<3>(a, s); break;
+    case 4: e = gram_m<4>(a, s); break;
+    case 5: e = gram_m<5>(a, s); break;
+    case 6: e = gram_m<6>(a, s); break;
+    case 7: e = gram_m<7>(a, s); break;
+    case 8: e = gram_m<8>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  const int W = a.M * (a.M + 1) / 2;
+  const int n2 = W * (2 * a.N1 - 1) * (2 * a.N2 - 1);
+  k_gram_cols<<<(n2 + 255) / 256, 256, 0, s>>>(a, W);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const long sN = (long)a.N1 * a.N2 * a.M;
+  k_gram_assemble<<<(unsigned)((sN * sN + 255) / 256), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- weights
+// eps^(0) = eps0_frac * lambda_max on the first iteration, else eps <- eps / gamma.
+__global__ void k_eps(WeightArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double lmax = a.lamv[a.s - 1];
+  const double e = a.first ? a.eps0_frac * lmax : (*a.eps) / a.gamma;
+  *a.eps = e;
+  if (a.lam_max_out) *a.lam_max_out = lmax;
+  if (a.eps_out) *a.eps_out = e;
+}
+
+// V = U diag(sqrt(alpha)), alpha_k = (max(lambda_k, 0) + eps)^(p/2 - 1), stored K-major.
+__global__ __launch_bounds__(256) void k_weights(WeightArgs a) {
+  const int s = a.s;
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)s * s) return;
+  const int i = (int)(idx % s), k = (int)(idx / s);
+  const double lk = a.lamv[k];
+  const double al = pow((lk > 0.0 ? lk : 0.0) + *a.eps, a.p * 0.5 - 1.0);
+  const double sa = sqrt(al);
+  const double2 u = a.U[idx];
+  a.VT[(long)k * s + i] = u.x * sa;
+  a.VT[(long)(s + k) * s + i] = u.y * sa;
+}
+
+hipError_t launch_weights(const WeightArgs& a, hipStream_t s) {
+  k_eps<<<1, 64, 0, s>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long n = (long)a.s * a.s;
+  k_weights<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------- filter product (MFMA)
+// Hre[i][j] = sum_{k'<2s} A[k'][i] A[k'][j],  A = VT = [Re V^T; Im V^T]
+// Him[i][j] = sum_{k<s} (Im_k[i] Re_k[j] - Re_k[i] Im_k[j])
+// i.e. [Hre; Him] = [A; B] A^T with B = [Im; -Re] (real form of V V^H).
+// Block: 64 x 64 output tile, 4 waves in 2 x 2, each 32 x 32 = 2 x 2 MFMA
+// 16x16x4 f64 tiles; K staged through LDS in chunks of 16.
+__global__ __launch_bounds__(256) void k_filter_product(int s, const double* __restrict__ VT,
+                                                        double* __restrict__ Hre, double* __restrict__ Him) {
+  constexpr int TB = 64, KC = 16;
+  __shared__ double Lre[KC][TB];
+  __shared__ double Lim[KC][TB];
+  __shared__ double Rt[KC][TB];
+  const int i0 = blockIdx.y * TB, j0 = blockIdx.x * TB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  const int K = 2 * s;
+  v4d accR[2][2], accI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      accR[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      accI[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int e = tid; e < KC * TB; e += 256) {
+      const int kk = e / TB, c = e % TB;
+      const int k = k0 + kk;
+      double li = 0.0, lr = 0.0, lm = 0.0;
+      if (k < K) {
+        const int ii = i0 + c, jj = j0 + c;
+        if (ii < s) {
+          lr = VT[(long)k * s + ii];
+          lm = (k < s) ? VT[(long)(s + k) * s + ii] : -VT[(long)(k - s) * s + ii];
+        }
+        if (jj < s) li = VT[(long)k * s + jj];
+      }
+      Lre[kk][c] = lr;
+      Lim[kk][c] = lm;
+      Rt[kk][c] = li;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < KC; kq += 4) {
+      const int kl = kq + (lane >> 4);
+      double ar[2], am[2], br[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = Lre[kl][wi + a * 16 + (lane & 15)];
+        am[a] = Lim[kl][wi + a * 16 + (lane & 15)];
+        br[a] = Rt[kl][wj + a * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], accR[a][b], 0, 0, 0);
+          accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[a], br[b], accI[a][b], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  // D layout of the f64 16x16x4 MFMA: item v of lane l is row l/16 + 4v, column l%16.
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ii = i0 + wi + a * 16 + (lane >> 4) + 4 * v;
+        const int jj = j0 + wj + b * 16 + (lane & 15);
+        if (ii < s && jj < s) {
+          Hre[(long)ii * s + jj] = accR[a][b][v];
+          Him[(long)ii * s + jj] = accI[a][b][v];
+        }
+      }
+}
+
+hipError_t launch_filter_product(int s, const double* VT, double* Hre, double* Him, hipStream_t st) {
+  dim3 grid((s + 63) / 64, (s + 63) / 64);
+  k_filter_product<<<grid, 256, 0, st>>>(s, VT, Hre, Him);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ masks
+// w_{m',m}[Delta] for pairs (m <= m'), Delta = a' - a.
+__global__ __launch_bounds__(256) void k_diagsum(MaskArgs a, int W, int s) {
+  const int N1 = a.N1, N2 = a.N2, M = a.M, NN = N1 * N2;
+  const int L1 = 2 * N1 - 1, L2 = 2 * N2 - 1;
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= W * L1 * L2) return;
+  const int w = o / (L1 * L2), j1 = (o / L2) % L1, j2 = o % L2;
+  int m = 0, mp = 0;
+  for (int mm = 0; mm < M; ++mm)
+    for (int nn = mm; nn < M; ++nn)
+      if (pair_id(mm, nn, M) == w) { m = mm; mp = nn; }
+  const int d1 = j1 - (N1 - 1), d2 = j2 - (N2 - 1);
+  double sx = 0.0, sy = 0.0;
+  const int i1lo = d1 < 0 ? -d1 : 0, i1hi = d1 > 0 ? N1 - d1 : N1;
+  const int i2lo = d2 < 0 ? -d2 : 0, i2hi = d2 > 0 ? N2 - d2 : N2;
+  for (int i1 = i1lo; i1 < i1hi; ++i1)
+    for (int i2 = i2lo; i2 < i2hi; ++i2) {
+      const long row = (long)mp * NN + (i1 + d1) * N2 + (i2 + d2);  // (m', a')
+      const long col = (long)m * NN + i1 * N2 + i2;                  // (m, a)
+      sx += a.Hre[row * s + col];
+      sy += a.Him[row * s + col];
+    }
+  a.wsum[o] = make_double2(sx, sy);
+}
+
+// s1[w][j1][r2] = sum_{j2} w[w][j1][j2] e^{+2 pi i Delta2 r2 / Q}
+__global__ __launch_bounds__(256) void k_mask_rows(MaskArgs a, int W) {
+  const int L1 = 2 * a.N1 - 1, L2 = 2 * a.N2 - 1, Q = a.Q;
+  const long o = (long)blockIdx.x * 256 + threadIdx.x;
+  if (o >= (long)W * L1 * Q) return;
+  const int r2 = (int)(o % Q);
+  const long wj = o / Q;  // w * L1 + j1
+  double sx = 0.0, sy = 0.0;
+  for (int j2 = 0; j2 < L2; ++j2) {
+    const int d2 = j2 - (a.N2 - 1);
+    const int t = (int)((((long)d2 % Q + Q) % Q) * r2 % Q);
+    const double2 c = a.wsum[wj * L2 + j2];
+    const double2 tw = a.twQ[t];  // conj gives the + sign
+    sx += c.x * tw.x + c.y * tw.y;
+    sy += c.y * tw.x - c.x * tw.y;
+  }
+  a.s1[o] = make_double2(sx, sy);
+}
+
+// E_w(r1, r2) = sum_{j1} s1[w][j1][r2] e^{+2 pi i Delta1 r1 / P}, rounded to FP32 and
+// stored as transposed planes Et[w][r2][r1] (the layout of the column penalty pass).
+__global__ __launch_bounds__(256) void k_mask_cols(MaskArgs a, int W) {
+  const int L1 = 2 * a.N1 - 1, P = a.P, Q = a.Q;
+  const long o = (long)blockIdx.x * 256 + threadIdx.x;
+  if (o >= (long)W * P * Q) return;
+  const int r1 = (int)(o % P);
+  const int r2 = (int)((o / P) % Q);
+  const int w = (int)(o / ((long)P * Q));
+  double sx = 0.0, sy = 0.0;
+  for (int j1 = 0; j1 < L1; ++j1) {
+    const int d1 = j1 - (a.N1 - 1);
+    const int t = (int)((((long)d1 % P + P) % P) * r1 % P);
+    const double2 c = a.s1[((long)w * L1 + j1) * Q + r2];
+    const double2 tw = a.twP[t];
+    sx += c.x * tw.x + c.y * tw.y;
+    sy += c.y * tw.x - c.x * tw.y;
+  }
+  a.Et[o] = make_float2((float)sx, (float)sy);
+}
+
+hipError_t launch_masks(const MaskArgs& a, hipStream_t s) {
+  const int W = a.M * (a.M + 1) / 2;
+  const int sN = a.N1 * a.N2 * a.M;
+  const int L1 = 2 * a.N1 - 1, L2 = 2 * a.N2 - 1;
+  const int n1 = W * L1 * L2;
+  k_diagsum<<<(n1 + 255) / 256, 256, 0, s>>>(a, W, sN);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long n2 = (long)W * L1 * a.Q;
+  k_mask_rows<<<(unsigned)((n2 + 255) / 256), 256, 0, s>>>(a, W);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const long n3 = (long)W * a.P * a.Q;
+  k_mask_cols<<<(unsigned)((n3 + 255) / 256), 256, 0, s>>>(a, W);
+  return hipGetLastError();
+}
+
+}  // namespace slrx

@@ -1,0 +1,132 @@
+// Launch wrappers of the libslrx kernels (host side).  All launches are
+// asynchronous on the given stream and return hipGetLastError().
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace slrx {
+
+// Supported transform lengths along each image axis.
+bool fft_len_supported(int n);
+int max_frames();  // largest T handled by the column penalty pass
+int max_taps();    // largest M
+
+// ---------------------------------------------------------------- FFT passes
+enum RowMode { ROW_PLAIN = 0, ROW_MASKED = 1, ROW_PUPDATE = 2 };
+
+// Row DFT (length Q) of a row-major volume; output transposed per frame
+// ([t][col][row]).  ROW_PUPDATE also forms p = r + beta p (beta from partials).
+struct RowArgs {
+  int P, Q, T;
+  int mode;              // RowMode
+  int sign;              // -1 forward, +1 inverse (unnormalised)
+  const float2* src;     // input (r for ROW_PUPDATE)
+  float2* pvec;          // ROW_PUPDATE: p (read p_old, write p)
+  const uint8_t* S;      // ROW_MASKED: mask
+  float2* dst;           // transposed output
+  float scale;
+  const float2* tw;      // e^{-2 pi i t / Q}, t < Q
+  int k;                 // ROW_PUPDATE: CG iteration index
+  const double* part;    // ROW_PUPDATE: partials holding rr_k
+  int npart;
+  double* rr_hist;       // rr_hist[k] written by block 0; rr_hist[k-1] read
+};
+hipError_t launch_rows(const RowArgs& a, hipStream_t s);
+
+// Column DFT (length P) of a transposed volume; output row-major.
+struct ColArgs {
+  int P, Q, T;
+  int sign;
+  const float2* src;     // transposed
+  float2* dst;           // row-major
+  float scale;
+  const float2* tw;      // e^{-2 pi i t / P}, t < P
+};
+hipError_t launch_cols(const ColArgs& a, hipStream_t s);
+
+// Column pass of the operator on a transposed volume, in place: inverse column
+// DFT, penalty G over all frames scaled by `scale`, forward column DFT.
+struct PenArgs {
+  int P, Q, T, M;
+  float2* buf;           // transposed [t][c][r]
+  const float2* Et;      // masks, transposed planes [w][c][r]
+  float scale;           // lam / (P Q)
+  const float2* tw;      // e^{-2 pi i t / P}
+};
+hipError_t launch_pen(const PenArgs& a, hipStream_t s);
+
+// Forward row DFT of the transposed penalty volume back to row-major, plus the
+// data term S o v and the CG dot product (or the initial residual).
+struct FinArgs {
+  int P, Q, T;
+  int init;              // 1: out = y - A v, partial <out,out>;  0: out = A v, partial <v,out>
+  const float2* t;       // transposed penalty volume
+  const float2* v;       // x (init) or p, row-major k-space
+  const uint8_t* S;
+  const float2* y;       // right-hand side S o b (init)
+  float2* out;
+  double* part;          // per-block partials
+  int* flag;             // CG stop flag (cleared by block 0 when init)
+  const float2* tw;      // e^{-2 pi i t / Q}
+};
+hipError_t launch_fin(const FinArgs& a, hipStream_t s);
+int fin_blocks(int P, int T);
+
+// CG vector update x += alpha p, r -= alpha q, partial <r,r>.
+struct UpdArgs {
+  long n;
+  float2 *x, *r;
+  const float2 *p, *q;
+  const double* partA; int nA;   // <p,q> partials
+  const double* rr_hist; int k;  // rr_k
+  double* partB;                 // out partials
+  int* flag;
+};
+hipError_t launch_update(const UpdArgs& a, hipStream_t s);
+int update_blocks(long n);
+
+hipError_t launch_mask_data(long n, const uint8_t* S, const float2* b, float2* out, hipStream_t s);
+hipError_t launch_store_sum(const double* part, int n, double* dst, hipStream_t s);
+hipError_t launch_interleave(long n, const double* re, const double* im, double2* out, hipStream_t s);
+// out[w][j][i] = in[w][i][j] for W planes of A x B.
+hipError_t launch_transpose_planes(int W, int A, int B, const float2* in, float2* out, hipStream_t s);
+
+// ---------------------------------------------------------------- Gram etc.
+struct GramArgs {
+  int P, Q, T, N1, N2, M;
+  const float2* rho;        // images [T][P][Q]
+  double2* c1;              // [W][P][2N2-1]
+  double2* g;               // [W][2N1-1][2N2-1]
+  double2* R;               // s x s, column-major
+  const double2* twP;       // e^{-2 pi i t/P}, t < P
+  const double2* twQ;
+};
+hipError_t launch_gram(const GramArgs& a, hipStream_t s);
+
+struct WeightArgs {
+  int s;
+  const double* lamv;       // eigenvalues, ascending
+  const double2* U;         // eigenvectors, column-major s x s
+  double* VT;               // [2s][s]: rows k' < s: Re(U[:,k']) sqrt(alpha), then Im
+  double* eps;              // eps state (in/out)
+  double* lam_max_out;      // per-iteration record (may be null)
+  double* eps_out;          // per-iteration record (may be null)
+  int first;                // 1 on the first IRLS iteration
+  double eps0_frac, gamma, p;
+};
+hipError_t launch_weights(const WeightArgs& a, hipStream_t s);
+
+// H = V V^H on FP64 MFMA: Hre, Him row-major s x s.
+hipError_t launch_filter_product(int s, const double* VT, double* Hre, double* Him, hipStream_t st);
+
+struct MaskArgs {
+  int P, Q, N1, N2, M;
+  const double* Hre; const double* Him;
+  double2* wsum;            // [W][2N1-1][2N2-1]
+  double2* s1;              // [W][2N1-1][Q]
+  float2* Et;               // [W][Q][P] (transposed planes)
+  const double2* twP; const double2* twQ;
+};
+hipError_t launch_masks(const MaskArgs& a, hipStream_t s);
+
+}  // namespace slrx

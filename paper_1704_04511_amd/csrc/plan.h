@@ -1,0 +1,93 @@
+// Internal plan state of libslrx (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <vector>
+
+#include "../../include/slrx.h"
+
+namespace slrx {
+
+constexpr int kMaxS = 4096;    // largest filter size s = N1 N2 M
+constexpr int kMaxCg = 10000;  // largest CG iteration count
+
+enum Buf {
+  B_B, B_BM, B_X0, B_IMG, B_X, B_R, B_P, B_Q, B_T, B_S, B_ET, B_ESTAGE,
+  B_TWPF, B_TWQF, B_TWPD, B_TWQD,
+  B_C1, B_G, B_RM, B_LAM, B_EWORK, B_VT, B_HRE, B_HIM, B_WSUM, B_S1,
+  B_PARTA, B_PARTB, B_RRH, B_SCAL, B_STATS, B_INFO, B_FLAG,
+  kNumBuf
+};
+
+slrx_status fail(slrx_status st, const char* fmt, ...);
+
+
+}  // namespace slrx
+
+struct slrx_plan {
+  slrx_dims cap{};   // dims the buffers were sized for
+  slrx_dims d{};     // current dims (filter may be smaller than cap)
+  slrx_params prm{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  float2 *b = nullptr, *bm = nullptr, *x0 = nullptr, *img = nullptr, *x = nullptr;
+  float2 *r = nullptr, *p = nullptr, *q = nullptr, *t = nullptr;
+  uint8_t* S = nullptr;
+  float2* Et = nullptr;      // penalty masks, transposed planes [W][Q][P]
+  float2* Estage = nullptr;  // masks in the ABI layout [W][P][Q]
+  float2 *twPf = nullptr, *twQf = nullptr;
+  double2 *twPd = nullptr, *twQd = nullptr;
+  double2 *c1 = nullptr, *g = nullptr, *Rm = nullptr;
+  double *lam = nullptr, *ework = nullptr, *VT = nullptr, *Hre = nullptr, *Him = nullptr;
+  double2 *wsum = nullptr, *s1 = nullptr;
+  double *partA = nullptr, *partB = nullptr, *rr_hist = nullptr, *scal = nullptr, *stats = nullptr;
+  rocblas_int* info = nullptr;
+  int* flag = nullptr;
+
+  rocblas_handle blas = nullptr;
+  void* blas_ws = nullptr;
+  size_t blas_ws_size = 0;
+
+  hipEvent_t ev_run[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> ev_phase;
+  // per-kernel-class launch timing (SLRX_FLAG_KTIME): event pairs, reused across runs
+  std::vector<hipEvent_t> kev[SLRX_K_NCLASS];
+  int kused[SLRX_K_NCLASS] = {};
+  bool ktime = false;
+
+  bool has_b = false, has_S = false, has_init = false;
+  bool prepared = false, running = false, ran = false;
+  int run_irls = 0;
+  bool run_timing = false;
+
+  size_t vol() const { return (size_t)d.T * d.P * d.Q; }
+};
+
+namespace slrx {
+// Records an event pair around the launches made during its lifetime.
+struct KTimer {
+  slrx_plan* pl;
+  int cls;
+  int idx = -1;
+  KTimer(slrx_plan* p, int c);
+  ~KTimer();
+};
+slrx_status fft2(slrx_plan* pl, const float2* src, float2* dst, int sign, const uint8_t* mask);
+slrx_status prepare(slrx_plan* pl);
+slrx_status images(slrx_plan* pl);
+slrx_status penalty_pass(slrx_plan* pl);
+slrx_status load_masks(slrx_plan* pl, const float2* E_dev);
+slrx_status store_masks(slrx_plan* pl);
+slrx_status step_gram(slrx_plan* pl);
+slrx_status step_eigh(slrx_plan* pl, int it);
+slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma);
+slrx_status apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part);
+slrx_status run_cg(slrx_plan* pl, int n_cg, int it);
+slrx_status enqueue_run(slrx_plan* pl);
+slrx_status finish(slrx_plan* pl);
+}  // namespace slrx

@@ -1,0 +1,253 @@
+// Device steps of the IRLS loop (host orchestration of the kernels).
+//
+// State per plan: x is the k-space iterate (Algorithm 1's rho-hat), bm = S o b
+// the masked data (the right-hand side A^H b of eq. "eq:grad_ls"), img the
+// images F^-1 x used by the Gram matrix and the output, Et the penalty masks.
+#include <hip/hip_runtime.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+
+#include "kernels.h"
+#include "plan.h"
+
+using namespace slrx;
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return fail(SLRX_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                  __LINE__);                                                                 \
+  } while (0)
+
+#define STCHK(expr)               \
+  do {                            \
+    slrx_status _s = (expr);      \
+    if (_s != SLRX_OK) return _s; \
+  } while (0)
+
+// Unitary 2-D transforms per frame: dst = F src (sign -1) or F^-1 src (+1);
+// uses the plan's transposed scratch volume t.
+slrx_status slrx::fft2(slrx_plan* pl, const float2* src, float2* dst, int sign, const uint8_t* mask) {
+  const slrx_dims& d = pl->d;
+  RowArgs ra{};
+  ra.P = d.P; ra.Q = d.Q; ra.T = d.T;
+  ra.mode = mask ? ROW_MASKED : ROW_PLAIN;
+  ra.sign = sign;
+  ra.src = src;
+  ra.S = mask;
+  ra.dst = pl->t;
+  ra.scale = 1.0f;
+  ra.tw = pl->twQf;
+  HIPCHK(launch_rows(ra, pl->stream));
+  ColArgs ca{};
+  ca.P = d.P; ca.Q = d.Q; ca.T = d.T;
+  ca.sign = sign;
+  ca.src = pl->t;
+  ca.dst = dst;
+  ca.scale = (float)(1.0 / std::sqrt((double)d.P * d.Q));
+  ca.tw = pl->twPf;
+  HIPCHK(launch_cols(ca, pl->stream));
+  return SLRX_OK;
+}
+
+// Masked data bm = S o b (the right-hand side) and the initial iterate
+// x = S o b (zero-filled k-space, Algorithm 1 initialisation) or the user's x0.
+slrx_status slrx::prepare(slrx_plan* pl) {
+  if (!pl->has_b || !pl->has_S) return fail(SLRX_ESTATE, "k-space and mask must be set before running");
+  const long V = (long)pl->vol();
+  HIPCHK(launch_mask_data(V, pl->S, pl->b, pl->bm, pl->stream));
+  const float2* x0 = pl->has_init ? pl->x0 : pl->bm;
+  HIPCHK(hipMemcpyAsync(pl->x, x0, V * sizeof(float2), hipMemcpyDeviceToDevice, pl->stream));
+  pl->prepared = true;
+  return SLRX_OK;
+}
+
+slrx_status slrx::images(slrx_plan* pl) { return fft2(pl, pl->x, pl->img, +1, nullptr); }
+
+// Gram matrix of the current iterate into Rm (column-major).
+slrx_status slrx::step_gram(slrx_plan* pl) {
+  const slrx_dims& d = pl->d;
+  KTimer kt(pl, SLRX_K_GRAM);
+  STCHK(images(pl));
+  GramArgs ga{};
+  ga.P = d.P; ga.Q = d.Q; ga.T = d.T; ga.N1 = d.N1; ga.N2 = d.N2; ga.M = d.M;
+  ga.rho = pl->img;
+  ga.c1 = pl->c1;
+  ga.g = pl->g;
+  ga.R = pl->Rm;
+  ga.twP = pl->twPd;
+  ga.twQ = pl->twQd;
+  HIPCHK(launch_gram(ga, pl->stream));
+  return SLRX_OK;
+}
+
+slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
+  const int s = pl->d.N1 * pl->d.N2 * pl->d.M;
+  KTimer kt(pl, SLRX_K_EIGH);
+  rocblas_status rs = rocsolver_zheevd(pl->blas, rocblas_evect_original, rocblas_fill_lower, s,
+                                       (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework,
+                                       pl->info + (it < 0 ? SLRX_MAX_IRLS : it));
+  if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zheevd failed (status %d)", (int)rs);
+  return SLRX_OK;
+}
+
+// Weights, filter product and masks from the eigenpairs in lam / Rm.
+slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma) {
+  const slrx_dims& d = pl->d;
+  const int s = d.N1 * d.N2 * d.M;
+  WeightArgs wa{};
+  wa.s = s;
+  wa.lamv = pl->lam;
+  wa.U = pl->Rm;
+  wa.VT = pl->VT;
+  wa.eps = pl->scal;
+  wa.lam_max_out = it >= 0 ? pl->stats + SLRX_MAX_IRLS + it : nullptr;
+  wa.eps_out = it >= 0 ? pl->stats + it : nullptr;
+  wa.first = first ? 1 : 0;
+  wa.eps0_frac = pl->prm.eps0_frac;
+  wa.gamma = gamma;
+  wa.p = pl->prm.p;
+  {
+    KTimer kt(pl, SLRX_K_FILTER);
+    HIPCHK(launch_weights(wa, pl->stream));
+    HIPCHK(launch_filter_product(s, pl->VT, pl->Hre, pl->Him, pl->stream));
+  }
+  MaskArgs ma{};
+  ma.P = d.P; ma.Q = d.Q; ma.N1 = d.N1; ma.N2 = d.N2; ma.M = d.M;
+  ma.Hre = pl->Hre;
+  ma.Him = pl->Him;
+  ma.wsum = pl->wsum;
+  ma.s1 = pl->s1;
+  ma.Et = pl->Et;
+  ma.twP = pl->twPd;
+  ma.twQ = pl->twQd;
+  KTimer kt(pl, SLRX_K_MASKS);
+  HIPCHK(launch_masks(ma, pl->stream));
+  return SLRX_OK;
+}
+
+// A v = S o v + lam F G F^-1 v in k-space (init: out = bm - A v).
+slrx_status slrx::apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part) {
+  const slrx_dims& d = pl->d;
+  RowArgs ra{};
+  ra.P = d.P; ra.Q = d.Q; ra.T = d.T;
+  ra.mode = ROW_PLAIN;
+  ra.sign = +1;
+  ra.src = v;
+  ra.dst = pl->t;
+  ra.scale = 1.0f;
+  ra.tw = pl->twQf;
+  HIPCHK(launch_rows(ra, pl->stream));
+  STCHK(penalty_pass(pl));
+  FinArgs fa{};
+  fa.P = d.P; fa.Q = d.Q; fa.T = d.T;
+  fa.init = init ? 1 : 0;
+  fa.t = pl->t;
+  fa.v = v;
+  fa.S = pl->S;
+  fa.y = pl->bm;
+  fa.out = out;
+  fa.part = part;
+  fa.flag = pl->flag;
+  fa.tw = pl->twQf;
+  HIPCHK(launch_fin(fa, pl->stream));
+  return SLRX_OK;
+}
+
+slrx_status slrx::penalty_pass(slrx_plan* pl) {
+  const slrx_dims& d = pl->d;
+  PenArgs pa{};
+  pa.P = d.P; pa.Q = d.Q; pa.T = d.T; pa.M = d.M;
+  pa.buf = pl->t;
+  pa.Et = pl->Et;
+  pa.scale = (float)(pl->prm.lambda / ((double)d.P * d.Q));
+  pa.tw = pl->twPf;
+  HIPCHK(launch_pen(pa, pl->stream));
+  return SLRX_OK;
+}
+
+// n_cg iterations of CG on (S + lam F G F^-1) x = S o b, warm-started at x.
+slrx_status slrx::run_cg(slrx_plan* pl, int n_cg, int it) {
+  const slrx_dims& d = pl->d;
+  const long V = (long)pl->vol();
+  const int nfin = fin_blocks(d.P, d.T);
+  const int nupd = update_blocks(V);
+  STCHK(apply_op(pl, pl->x, pl->r, true, pl->partA));
+  for (int k = 0; k < n_cg; ++k) {
+    RowArgs ra{};
+    ra.P = d.P; ra.Q = d.Q; ra.T = d.T;
+    ra.mode = ROW_PUPDATE;
+    ra.sign = +1;
+    ra.src = pl->r;
+    ra.pvec = pl->p;
+    ra.dst = pl->t;
+    ra.scale = 1.0f;
+    ra.tw = pl->twQf;
+    ra.k = k;
+    ra.part = k == 0 ? pl->partA : pl->partB;
+    ra.npart = k == 0 ? nfin : nupd;
+    ra.rr_hist = pl->rr_hist;
+    {
+      KTimer kt(pl, SLRX_K_ROWS);
+      HIPCHK(launch_rows(ra, pl->stream));
+    }
+    {
+      KTimer kt(pl, SLRX_K_COLS);
+      STCHK(penalty_pass(pl));
+    }
+    FinArgs fa{};
+    fa.P = d.P; fa.Q = d.Q; fa.T = d.T;
+    fa.init = 0;
+    fa.t = pl->t;
+    fa.v = pl->p;
+    fa.S = pl->S;
+    fa.y = pl->bm;
+    fa.out = pl->q;
+    fa.part = pl->partA;
+    fa.flag = pl->flag;
+    fa.tw = pl->twQf;
+    {
+      KTimer kt(pl, SLRX_K_FIN);
+      HIPCHK(launch_fin(fa, pl->stream));
+    }
+    UpdArgs ua{};
+    ua.n = V;
+    ua.x = pl->x;
+    ua.r = pl->r;
+    ua.p = pl->p;
+    ua.q = pl->q;
+    ua.partA = pl->partA;
+    ua.nA = nfin;
+    ua.rr_hist = pl->rr_hist;
+    ua.k = k;
+    ua.partB = pl->partB;
+    ua.flag = pl->flag;
+    {
+      KTimer kt(pl, SLRX_K_UPDATE);
+      HIPCHK(launch_update(ua, pl->stream));
+    }
+  }
+  if (it >= 0) {
+    HIPCHK(launch_store_sum(n_cg == 0 ? pl->partA : pl->partB, n_cg == 0 ? nfin : nupd,
+                            pl->stats + 2 * SLRX_MAX_IRLS + it, pl->stream));
+  }
+  return SLRX_OK;
+}
+
+// Masks given in the ABI layout [W][P][Q] -> the plan's transposed planes.
+slrx_status slrx::load_masks(slrx_plan* pl, const float2* E_dev) {
+  const slrx_dims& d = pl->d;
+  const int W = d.M * (d.M + 1) / 2;
+  HIPCHK(launch_transpose_planes(W, d.P, d.Q, E_dev, pl->Et, pl->stream));
+  return SLRX_OK;
+}
+
+// The plan's transposed planes -> [W][P][Q] in the staging buffer.
+slrx_status slrx::store_masks(slrx_plan* pl) {
+  const slrx_dims& d = pl->d;
+  const int W = d.M * (d.M + 1) / 2;
+  HIPCHK(launch_transpose_planes(W, d.Q, d.P, pl->Et, pl->Estage, pl->stream));
+  return SLRX_OK;
+}

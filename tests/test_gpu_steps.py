@@ -1,0 +1,136 @@
+"""GPU parity of each step of the IRLS hot path against the FP64 oracle.
+
+Each test drives one entry point of the C ABI (through the thin binding) on
+seeded inputs and compares element by element with the oracle on the same
+inputs.  FP32 data path (complex64 FFTs, CG, penalty) and FP64 Gram /
+eigen-decomposition / filter product: the bars below are relative Frobenius
+errors derived from FP32 rounding (~6e-8 per operation, grown by the FFT
+length and the conditioning of the step).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from tests.gpu_util import crandn, masks_to_pairs, nrmse, pairs, pairs_to_masks, say
+
+pytestmark = pytest.mark.gpu
+
+slrx = pytest.importorskip("paper_1704_04511_amd")
+
+# (T, P, Q, N1, N2, M): several tiles, odd radices (96 = 16*3*2, 160 = 16*5*2,
+# 192 = 16*4*3), even/odd filters, M = 1 and M = T.
+STEP_SHAPES = [
+    (5, 16, 16, 3, 3, 2),
+    (8, 64, 64, 5, 5, 3),
+    (6, 32, 96, 4, 5, 3),
+    (4, 160, 32, 3, 2, 4),
+    (3, 192, 16, 2, 3, 1),
+    (12, 8, 8, 1, 1, 1),
+    (16, 128, 128, 9, 9, 5),
+]
+
+
+def problem(seed, T, P, Q, frac=0.4):
+    rng = np.random.default_rng(seed)
+    x = crandn(rng, T, P, Q).astype(np.complex64)
+    S = (rng.random((T, P, Q)) < frac).astype(np.uint8)
+    return rng, x, S
+
+
+def make_plan(T, P, Q, N1, N2, M, lam=1e-2, n_irls=1, n_cg=5):
+    return slrx.Plan(P, Q, T, N1, N2, M, slrx.make_params(lam=lam, n_irls=n_irls, n_cg=n_cg))
+
+
+@pytest.mark.parametrize("shape", STEP_SHAPES)
+def test_gram_matches_oracle(shape):
+    T, P, Q, N1, N2, M = shape
+    say(f"gram {shape}")
+    rng, x, _ = problem(1, T, P, Q)
+    S = np.ones((T, P, Q), np.uint8)
+    with make_plan(*shape) as pl:
+        pl.set_kspace(x)
+        pl.set_mask(S)
+        R = pl.step_gram()
+    R_ref = oracle.gram(x.astype(np.complex128), N1, N2, M)
+    err = np.linalg.norm(R - R_ref) / np.linalg.norm(R_ref)
+    assert err < 2e-6, err
+    assert np.abs(R - R.conj().T).max() <= 1e-12 * np.abs(R).max()
+
+
+@pytest.mark.parametrize("shape", STEP_SHAPES)
+def test_weights_and_masks_match_oracle(shape):
+    T, P, Q, N1, N2, M = shape
+    say(f"weights {shape}")
+    rng, x, _ = problem(2, T, P, Q)
+    S = np.ones((T, P, Q), np.uint8)
+    R_ref = oracle.gram(x.astype(np.complex128), N1, N2, M)
+    lam_ref = np.linalg.eigvalsh(R_ref)
+    eps = 0.01 * lam_ref.max()
+    with make_plan(*shape) as pl:
+        pl.set_kspace(x)
+        pl.set_mask(S)
+        lam, H, E = pl.step_weights(eps)
+    assert np.abs(lam - lam_ref).max() < 2e-6 * lam_ref.max()
+    ev, U, alpha = oracle.eig_weights(R_ref, eps, 0.6)
+    H_ref = oracle.weight_matrix(U, alpha)
+    assert nrmse(H, H_ref) < 2e-5
+    E_ref = oracle.penalty_masks(U, alpha, N1, N2, M, P, Q)
+    for w, (m, mp) in enumerate(pairs(M)):
+        assert nrmse(E[w], E_ref[m, mp]) < 2e-5, (m, mp)
+
+
+@pytest.mark.parametrize("shape", STEP_SHAPES)
+def test_normal_operator_matches_oracle(shape):
+    T, P, Q, N1, N2, M = shape
+    say(f"apply {shape}")
+    rng, x, S = problem(3, T, P, Q)
+    R = oracle.gram(x.astype(np.complex128), N1, N2, M)
+    ev, U, alpha = oracle.eig_weights(R, 0.05 * np.linalg.eigvalsh(R).max(), 0.6)
+    E = oracle.penalty_masks(U, alpha, N1, N2, M, P, Q)
+    Ew = masks_to_pairs(E)
+    v = crandn(rng, T, P, Q).astype(np.complex64)
+    lam = 0.7 / np.abs(E).max()
+    with make_plan(*shape, lam=lam) as pl:
+        pl.set_kspace(x)
+        pl.set_mask(S)
+        out = pl.step_apply(Ew, v)
+    ref = oracle.normal_apply(v.astype(np.complex128), S, pairs_to_masks(Ew, M), lam)
+    assert nrmse(out, ref) < 2e-6
+
+
+@pytest.mark.parametrize("shape", STEP_SHAPES[:5])
+def test_cg_matches_oracle(shape):
+    T, P, Q, N1, N2, M = shape
+    say(f"cg {shape}")
+    rng, x, S = problem(4, T, P, Q, frac=0.5)
+    b = (S * x).astype(np.complex64)
+    R = oracle.gram(b.astype(np.complex128), N1, N2, M)
+    ev, U, alpha = oracle.eig_weights(R, 0.02 * np.linalg.eigvalsh(R).max(), 0.6)
+    E = oracle.penalty_masks(U, alpha, N1, N2, M, P, Q)
+    Ew = masks_to_pairs(E)
+    lam = 0.5 / np.abs(E).max()
+    for n_cg in (0, 1, 3, 12):
+        with make_plan(*shape, lam=lam) as pl:
+            pl.set_kspace(b)
+            pl.set_mask(S)
+            pl.step_cg(Ew, n_cg)
+            img = pl.images()
+        Sd = S.astype(np.float64)
+        xk = oracle.cg(lambda v: oracle.normal_apply(v, Sd, pairs_to_masks(Ew, M), lam),
+                       Sd * b, Sd * b.astype(np.complex128), n_cg)
+        assert nrmse(img, oracle.idft2(xk)) < 1e-5, n_cg
+
+
+def test_fft_roundtrip_and_kspace_output():
+    # with E = 0 and a full mask the operator is the identity through F^H then F
+    T, P, Q, N1, N2, M = 4, 96, 160, 3, 3, 2
+    say("fft roundtrip 96x160")
+    rng, x, _ = problem(5, T, P, Q)
+    S = np.ones((T, P, Q), np.uint8)
+    Ew = np.zeros((3, P, Q), np.complex64)
+    with make_plan(T, P, Q, N1, N2, M) as pl:
+        pl.set_kspace(x)
+        pl.set_mask(S)
+        out = pl.step_apply(Ew, x)
+    assert nrmse(out, x) < 1e-6
