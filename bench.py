@@ -31,25 +31,62 @@ def algorithmic_bytes(kind: str, T: int, P: int, Q: int, M: int, N1: int, N2: in
     """
     V = T * P * Q
     W = M * (M + 1) // 2
+    s = N1 * N2 * M
     c = 8
-    if kind == "rows":     # read r, p_old; write p, row-transformed t
+    if kind == "rows":     # read r, p_old; write p and the row-transformed volume t
         return 4 * V * c
-    if kind == "cols":     # read t, S; write t
-        return 2 * V * c + V
-    if kind == "fin":      # read t, p, E; write q
-        return 3 * V * c + W * P * Q * c
+    if kind == "cols":     # read t and the masks E; write t
+        return 2 * V * c + W * P * Q * c
+    if kind == "fin":      # read t, p, S (1 B); write q
+        return 3 * V * c + V
     if kind == "update":   # read x, p, r, q; write x, r
         return 6 * V * c
-    if kind == "gram":     # read the images once; write R (s x s complex128)
-        s = N1 * N2 * M
-        return V * c + s * s * 16
+    if kind == "gram":     # images (read x, write/read t, write img), read img, write R
+        return 5 * V * c + s * s * 16
     if kind == "masks":    # read H (2 s^2 doubles); write E
-        s = N1 * N2 * M
         return 2 * s * s * 8 + W * P * Q * c
     if kind == "filter":   # read U (s^2 complex128); write H (2 s^2 doubles)
-        s = N1 * N2 * M
         return s * s * 16 + 2 * s * s * 8
     return 0.0
+
+
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix
+
+
+def roofline(kind, avg_ms, T, P, Q, M, N1, N2):
+    """Roofline entry of one kernel class: the filter product is an FP64 MFMA
+    contraction (8 s^3 flop per launch); every other class is bound by HBM."""
+    if kind == "filter":
+        s = N1 * N2 * M
+        flop = 8.0 * s ** 3
+        ach = flop / (avg_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": kind, "achieved": round(ach, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                "flop_per_launch": flop, "avg_launch_ms": round(avg_ms, 5)}
+    nbytes = algorithmic_bytes(kind, T, P, Q, M, N1, N2)
+    ach = nbytes / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kind, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes,
+            "avg_launch_ms": round(avg_ms, 5)}
+
+
+def measured_traffic(kind: str):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "c3_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    csrc = os.path.join(ROOT, "paper_1704_04511_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec.get("bytes_per_launch", {}).get(kind)
 
 
 def cpu_baseline(pb, n_outer: int = 1) -> dict:
@@ -72,6 +109,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=1)
+    ap.add_argument("--n-irls", type=int, default=None,
+                    help="override the outer iteration count (profiling runs only; changes the workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
@@ -87,6 +126,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     pb = workload.config_problem("c3")
+    if args.n_irls is not None:
+        pb.n_irls = args.n_irls
     T, P, Q = pb.b.shape
     prm = slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg, p=pb.p, gamma=pb.gamma,
                            eps0_frac=pb.eps0_frac, ktime=True)
@@ -111,9 +152,9 @@ def main() -> int:
     kms, kcnt = st["kernel_ms"], st["kernel_count"]
     own = [k for k in ("rows", "cols", "fin", "update", "gram", "filter", "masks") if kcnt[k] > 0]
     dom = max(own, key=lambda k: kms[k])
-    avg_ms = kms[dom] / kcnt[dom]
-    nbytes = algorithmic_bytes(dom, T, P, Q, pb.M, pb.N1, pb.N2)
-    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    roofs = {k: roofline(k, kms[k] / kcnt[k], T, P, Q, pb.M, pb.N1, pb.N2) for k in own}
+    for k in own:
+        roofs[k]["traffic"] = measured_traffic(k)
     cg_kinds = ("rows", "cols", "fin", "update")
     cg_bytes = sum(algorithmic_bytes(k, T, P, Q, pb.M, pb.N1, pb.N2) * kcnt[k] for k in cg_kinds)
     cg_ms = sum(kms[k] for k in cg_kinds)
@@ -135,9 +176,9 @@ def main() -> int:
                                "lambda=1e-3, p=0.6",
                    "P": P, "Q": Q, "T": T, "filter": [pb.N1, pb.N2, pb.M], "n_irls": pb.n_irls,
                    "n_cg": pb.n_cg, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 5)},
+        "roofline": roofs[dom],
+        "roofline_by_kernel": {k: {kk: v for kk, v in r.items() if kk in ("bound", "achieved", "unit", "frac")}
+                               for k, r in roofs.items()},
         "phases_ms_per_step": {k: round(kms[k], 3) for k in kms},
         "launches_per_step": {k: kcnt[k] for k in kcnt},
         "cg_algorithmic_gbs": round(cg_bytes / (cg_ms * 1e-3) / 1e9, 1) if cg_ms > 0 else None,
