@@ -78,6 +78,9 @@ typedef struct {
 
 #define SLRX_FLAG_TIMING 1u /* record per-phase device times (hipEvents) */
 #define SLRX_FLAG_KTIME 2u  /* record every launch of each kernel class (hipEvents) */
+#define SLRX_FLAG_LIBEIGH 4u /* eigen-decomposition entirely by rocSOLVER zheevd (reference
+                                path); default: own Householder tridiagonalisation on the GPU,
+                                then rocSOLVER's divide-and-conquer and back-transformation */
 
 /* Kernel classes timed under SLRX_FLAG_KTIME. */
 enum {

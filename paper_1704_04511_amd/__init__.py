@@ -34,6 +34,7 @@ SLRX_MEM_HOST = 0
 SLRX_MEM_DEVICE = 1
 SLRX_FLAG_TIMING = 1
 SLRX_FLAG_KTIME = 2
+SLRX_FLAG_LIBEIGH = 4
 MAX_IRLS = 256
 KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "eigh", "filter", "masks")
 
@@ -159,8 +160,9 @@ def default_params() -> Params:
 
 
 def make_params(lam=1e-3, n_irls=15, n_cg=10, p=0.6, gamma=1.4, eps0_frac=0.01, timing=False,
-                ktime=False) -> Params:
-    flags = (SLRX_FLAG_TIMING if timing else 0) | (SLRX_FLAG_KTIME if ktime else 0)
+                ktime=False, lib_eigh=False) -> Params:
+    flags = ((SLRX_FLAG_TIMING if timing else 0) | (SLRX_FLAG_KTIME if ktime else 0)
+             | (SLRX_FLAG_LIBEIGH if lib_eigh else 0))
     return Params(float(lam), float(p), float(gamma), float(eps0_frac), int(n_irls), int(n_cg), flags)
 
 

@@ -65,6 +65,8 @@ slrx::KTimer::~KTimer() {
   if (idx >= 0) (void)hipEventRecord(pl->kev[cls][2 * idx + 1], pl->stream);
 }
 
+bool slrx_plan::lib_eigh() const { return (prm.flags & SLRX_FLAG_LIBEIGH) != 0 || s() > tri_max_n(); }
+
 extern "C" const char* slrx_status_str(slrx_status s) {
   switch (s) {
     case SLRX_OK: return "ok";
@@ -172,6 +174,11 @@ static Layout plan_layout(const slrx_dims& d) {
   sz[B_STATS] = 3 * SLRX_MAX_IRLS * 8;
   sz[B_INFO] = (SLRX_MAX_IRLS + 1) * 4;
   sz[B_FLAG] = 64;
+  sz[B_AW] = s * s * 16;
+  sz[B_UZ] = s * s * 16;
+  sz[B_TAU] = s * 16;
+  sz[B_TRIV] = 2 * s * 16;
+  sz[B_TRIP] = 2 * s * 16;
   Layout L;
   size_t o = 0;
   for (int i = 0; i < kNumBuf; ++i) {
@@ -223,6 +230,11 @@ static slrx_status setup_eigensolver(slrx_plan* pl) {
   // sizes for every s up to the capacity are bounded by the capacity's
   rocsolver_zheevd(pl->blas, rocblas_evect_original, rocblas_fill_lower, s,
                    (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework, pl->info);
+  rocsolver_zstedc(pl->blas, rocblas_evect_tridiagonal, s, pl->lam, pl->ework, (rocblas_double_complex*)pl->UZ,
+                   s, pl->info);
+  rocsolver_zunmtr(pl->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, s, s,
+                   (rocblas_double_complex*)pl->Rm, s, (rocblas_double_complex*)pl->tau,
+                   (rocblas_double_complex*)pl->UZ, s);
   rocblas_stop_device_memory_size_query(pl->blas, &ws);
   if (ws < 1024) ws = 1024;
   if (hipMalloc(&pl->blas_ws, ws) != hipSuccess) return fail(SLRX_ENOMEM, "eigensolver workspace (%zu bytes)", ws);
@@ -268,6 +280,11 @@ static void assign_buffers(slrx_plan* pl, const Layout& L) {
   pl->stats = (double*)at(B_STATS);
   pl->info = (rocblas_int*)at(B_INFO);
   pl->flag = (int*)at(B_FLAG);
+  pl->Aw = (double2*)at(B_AW);
+  pl->UZ = (double2*)at(B_UZ);
+  pl->tau = (double2*)at(B_TAU);
+  pl->triv = (double2*)at(B_TRIV);
+  pl->trip = (double2*)at(B_TRIP);
 }
 
 extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params* params, void* hip_stream,
@@ -590,7 +607,7 @@ static slrx_status ensure_prepared(slrx_plan* pl) {
 
 extern "C" slrx_status slrx_step_gram(slrx_plan* pl, void* R_out, slrx_mem mem) {
   STCHK(ensure_prepared(pl));
-  STCHK(step_gram(pl));
+  STCHK(step_gram(pl, true));
   const size_t s = (size_t)pl->d.N1 * pl->d.N2 * pl->d.M;
   STCHK(copy_out(pl, R_out, pl->Rm, s * s * 16, mem));
   HIPCHK(hipStreamSynchronize(pl->stream));

@@ -105,7 +105,9 @@ __global__ __launch_bounds__(256) void k_gram_assemble(GramArgs a) {
   const int NN = N1 * N2, s = NN * M;
   const long idx = (long)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (long)s * s) return;
-  const int i = (int)(idx % s), j = (int)(idx / s);  // R[i + j s]
+  // element (i, j): column-major R[i + j s], or row-major R[i s + j]
+  const int i = a.rowmajor ? (int)(idx / s) : (int)(idx % s);
+  const int j = a.rowmajor ? (int)(idx % s) : (int)(idx / s);
   const int m = i / NN, ia = i % NN, mp = j / NN, ib = j % NN;
   const int a1 = ia / N2 - N1 / 2, a2 = ia % N2 - N2 / 2;
   const int b1 = ib / N2 - N1 / 2, b2 = ib % N2 - N2 / 2;

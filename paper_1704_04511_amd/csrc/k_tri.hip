@@ -1,0 +1,196 @@
+// Householder reduction of the Hermitian Gram matrix to real symmetric
+// tridiagonal form, R = Q T Q^H (FP64), first stage of the eigen-decomposition
+// in the weight update (Sec. III.C, Algorithm 1 step 1).
+//
+// Column k needs a global matrix-vector product with the trailing block, so
+// every column is one launch (the launch boundary is the grid-wide sync).  A
+// launch for column k:
+//   * in every workgroup (redundantly, identical arithmetic): finishes the
+//     previous reflector's w = tau p - |tau|^2/2 (p^H v) v from the previous
+//     launch's p = A v, corrects row k with the pending rank-2 update
+//     A <- A - v w^H - w v^H, and forms reflector k, H = I - tau v v^H with
+//     H^H x = (beta, 0, ..)^T, beta real (the elementary reflector convention
+//     of LAPACK's zlarfg);
+//   * on its rows i > k: applies the pending rank-2 update and accumulates
+//     p_i = sum_j A_ij v_j for the next launch.
+// The working matrix Aw is full (both triangles) and row-major; reflectors are
+// stored as LAPACK's zhetrd (lower) stores them: v(k+2:n) in column k of the
+// column-major matrix Vst below the subdiagonal, tau(k), diagonal D, real
+// subdiagonal E.
+#include "common.h"
+#include "kernels.h"
+
+namespace slrx {
+
+constexpr int kTriNT = 256;
+constexpr int kTriRows = 4;  // rows of the trailing block per workgroup (one per wave)
+constexpr int kTriUnroll = 4;  // row elements in flight per lane
+
+SLRX_DEV double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+SLRX_DEV double2 dscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// Deterministic block sum of a complex value (fixed shuffle/tree order).
+SLRX_DEV double2 block_sum2(double2 v, double2* red) {
+  const int tid = threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_down(v.x, off, 64);
+    v.y += __shfl_down(v.y, off, 64);
+  }
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int w = 0; w < kTriNT / 64; ++w) s = dadd(s, red[w]);
+    red[kTriNT / 64] = s;
+  }
+  __syncthreads();
+  v = red[kTriNT / 64];
+  __syncthreads();
+  return v;
+}
+
+__global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
+  extern __shared__ double2 sm[];
+  __shared__ double2 red[kTriNT / 64 + 1];
+  const int n = a.n, k = a.k;
+  const int b = blockIdx.y;  // problem in a batch
+  double2* Aw = a.Aw + (size_t)b * a.strideA;
+  double2* vp = sm;           // v_{k-1}, indices >= k
+  double2* wp = sm + n;       // w_{k-1} (first holds p_{k-1})
+  double2* col = sm + 2 * n;  // corrected row k, then v_k
+  const int tid = threadIdx.x;
+  const bool pending = k > 0;
+
+  // 1. pending reflector k-1: w = tau p + c v, c = -|tau|^2/2 (p^H v)
+  if (pending) {
+    const double2* vprev = a.vbuf[(k - 1) & 1] + (size_t)b * n;
+    const double2* pprev = a.pbuf[(k - 1) & 1] + (size_t)b * n;
+    double2 d = make_double2(0.0, 0.0);
+    for (int j = k + tid; j < n; j += kTriNT) {
+      const double2 v = vprev[j], p = pprev[j];
+      vp[j] = v;
+      wp[j] = p;
+      d = dadd(d, dcmul(p, v));
+    }
+    d = block_sum2(d, red);
+    const double2 t = a.tau[(size_t)b * n + (k - 1)];
+    const double c = -0.5 * (t.x * t.x + t.y * t.y);
+    const double2 cd = dscale(d, c);
+    for (int j = k + tid; j < n; j += kTriNT) wp[j] = dadd(dmul(t, wp[j]), dmul(cd, vp[j]));
+    __syncthreads();
+  }
+
+  // 2. column k of the current matrix = conj(row k), with the pending update
+  const double2* rowk = Aw + (size_t)k * n;
+  for (int i = k + tid; i < n; i += kTriNT) {
+    double2 x = dconj(rowk[i]);
+    if (pending) {
+      // (A - v w^H - w v^H)(i, k)
+      x = dsub(x, dadd(dmul(vp[i], dconj(wp[k])), dmul(wp[i], dconj(vp[k]))));
+    }
+    col[i] = x;
+  }
+  __syncthreads();
+  if (k == n - 1) {  // last diagonal entry, no reflector left
+    if (blockIdx.x == 0 && tid == 0) a.D[(size_t)b * n + k] = col[k].x;
+    return;
+  }
+
+  // 3. reflector k on x = col[k+1 .. n-1]
+  double xn = 0.0;
+  for (int i = k + 2 + tid; i < n; i += kTriNT) xn += col[i].x * col[i].x + col[i].y * col[i].y;
+  const double2 xn2 = block_sum2(make_double2(xn, 0.0), red);
+  const double2 alpha = col[k + 1];
+  double beta;
+  double2 tau, scale;
+  if (xn2.x == 0.0 && alpha.y == 0.0) {
+    tau = make_double2(0.0, 0.0);
+    beta = alpha.x;
+    scale = make_double2(0.0, 0.0);
+  } else {
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2.x);
+    beta = alpha.x >= 0.0 ? -nrm : nrm;
+    tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    // scale = 1 / (alpha - beta)
+    const double2 den = make_double2(alpha.x - beta, alpha.y);
+    const double dd = den.x * den.x + den.y * den.y;
+    scale = make_double2(den.x / dd, -den.y / dd);
+  }
+  const double dk = col[k].x;
+  __syncthreads();
+  for (int i = k + 1 + tid; i < n; i += kTriNT) col[i] = (i == k + 1) ? make_double2(1.0, 0.0) : dmul(col[i], scale);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    double2* vout = a.vbuf[k & 1] + (size_t)b * n;
+    double2* Vst = a.Vst + (size_t)b * a.strideA;
+    for (int i = k + 1 + tid; i < n; i += kTriNT) {
+      vout[i] = col[i];
+      Vst[(size_t)k * n + i] = (i == k + 1) ? make_double2(beta, 0.0) : col[i];
+    }
+    if (tid == 0) {
+      a.D[(size_t)b * n + k] = dk;
+      a.E[(size_t)b * n + k] = beta;
+      a.tau[(size_t)b * n + k] = tau;
+    }
+  }
+
+  // 4. rows of the trailing block: pending update, then p_i = sum_j A_ij v_j
+  const int lane = tid & 63, wave = tid >> 6;
+  double2* pout = a.pbuf[k & 1] + (size_t)b * n;
+  for (int rr = wave; rr < kTriRows; rr += kTriNT / 64) {
+    const int i = k + 1 + blockIdx.x * kTriRows + rr;
+    if (i >= n) break;
+    double2* row = Aw + (size_t)i * n;
+    const double2 vpi = pending ? vp[i] : make_double2(0.0, 0.0);
+    const double2 wpi = pending ? wp[i] : make_double2(0.0, 0.0);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j0 = k + 1 + lane; j0 < n; j0 += 64 * kTriUnroll) {
+      double2 x[kTriUnroll];
+#pragma unroll
+      for (int u = 0; u < kTriUnroll; ++u) {
+        const int j = j0 + 64 * u;
+        x[u] = j < n ? row[j] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < kTriUnroll; ++u) {
+        const int j = j0 + 64 * u;
+        if (j < n) {
+          if (pending) {
+            x[u] = dsub(x[u], dadd(dmul(vpi, dconj(wp[j])), dmul(wpi, dconj(vp[j]))));
+            row[j] = x[u];
+          }
+          acc = dadd(acc, dmul(x[u], col[j]));
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_down(acc.x, off, 64);
+      acc.y += __shfl_down(acc.y, off, 64);
+    }
+    if (lane == 0) pout[i] = acc;
+  }
+}
+
+int tri_max_n() { return 3000; }
+
+hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s) {
+  const int n = base.n;
+  const size_t lds = (size_t)3 * n * sizeof(double2);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_tri_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)((size_t)3 * tri_max_n() * sizeof(double2)));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  TriArgs a = base;
+  for (int k = 0; k < n; ++k) {
+    a.k = k;
+    const int rows = n - k - 1;
+    const int gx = rows > 0 ? (rows + kTriRows - 1) / kTriRows : 1;
+    k_tri_step<<<dim3(gx, nbatch), kTriNT, lds, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace slrx

@@ -97,7 +97,8 @@ struct GramArgs {
   const float2* rho;        // images [T][P][Q]
   double2* c1;              // [W][P][2N2-1]
   double2* g;               // [W][2N1-1][2N2-1]
-  double2* R;               // s x s, column-major
+  double2* R;               // s x s full Hermitian: column-major, or row-major if rowmajor
+  int rowmajor;
   const double2* twP;       // e^{-2 pi i t/P}, t < P
   const double2* twQ;
 };
@@ -115,6 +116,24 @@ struct WeightArgs {
   double eps0_frac, gamma, p;
 };
 hipError_t launch_weights(const WeightArgs& a, hipStream_t s);
+
+// Householder tridiagonalisation R = Q T Q^H of nbatch n x n Hermitian matrices
+// (one launch per column).  Aw: row-major full matrices (overwritten); Vst:
+// reflectors in LAPACK zhetrd lower layout (column-major); D, E: real
+// tridiagonal; tau: reflector scalars; vbuf/pbuf: 2 x nbatch x n scratch each.
+struct TriArgs {
+  int n, k;
+  double2* Aw;
+  double2* Vst;
+  long strideA;             // elements between matrices of the batch
+  double* D;
+  double* E;
+  double2* tau;
+  double2* vbuf[2];
+  double2* pbuf[2];
+};
+hipError_t launch_tridiag(const TriArgs& a, int nbatch, hipStream_t s);
+int tri_max_n();
 
 // H = V V^H on FP64 MFMA: Hre, Him row-major s x s.
 hipError_t launch_filter_product(int s, const double* VT, double* Hre, double* Him, hipStream_t st);

@@ -17,6 +17,7 @@ enum Buf {
   B_TWPF, B_TWQF, B_TWPD, B_TWQD,
   B_C1, B_G, B_RM, B_LAM, B_EWORK, B_VT, B_HRE, B_HIM, B_WSUM, B_S1,
   B_PARTA, B_PARTB, B_RRH, B_SCAL, B_STATS, B_INFO, B_FLAG,
+  B_AW, B_UZ, B_TAU, B_TRIV, B_TRIP,
   kNumBuf
 };
 
@@ -45,6 +46,7 @@ struct slrx_plan {
   double2 *c1 = nullptr, *g = nullptr, *Rm = nullptr;
   double *lam = nullptr, *ework = nullptr, *VT = nullptr, *Hre = nullptr, *Him = nullptr;
   double2 *wsum = nullptr, *s1 = nullptr;
+  double2 *Aw = nullptr, *UZ = nullptr, *tau = nullptr, *triv = nullptr, *trip = nullptr;
   double *partA = nullptr, *partB = nullptr, *rr_hist = nullptr, *scal = nullptr, *stats = nullptr;
   rocblas_int* info = nullptr;
   int* flag = nullptr;
@@ -66,6 +68,9 @@ struct slrx_plan {
   bool run_timing = false;
 
   size_t vol() const { return (size_t)d.T * d.P * d.Q; }
+  int s() const { return d.N1 * d.N2 * d.M; }
+  // own tridiagonalisation unless the flag asks for the library path or s is too large
+  bool lib_eigh() const;
 };
 
 namespace slrx {
@@ -83,7 +88,7 @@ slrx_status images(slrx_plan* pl);
 slrx_status penalty_pass(slrx_plan* pl);
 slrx_status load_masks(slrx_plan* pl, const float2* E_dev);
 slrx_status store_masks(slrx_plan* pl);
-slrx_status step_gram(slrx_plan* pl);
+slrx_status step_gram(slrx_plan* pl, bool colmajor = false);
 slrx_status step_eigh(slrx_plan* pl, int it);
 slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma);
 slrx_status apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part);

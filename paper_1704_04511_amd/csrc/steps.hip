@@ -66,8 +66,10 @@ slrx_status slrx::prepare(slrx_plan* pl) {
 
 slrx_status slrx::images(slrx_plan* pl) { return fft2(pl, pl->x, pl->img, +1, nullptr); }
 
-// Gram matrix of the current iterate into Rm (column-major).
-slrx_status slrx::step_gram(slrx_plan* pl) {
+// Gram matrix of the current iterate: row-major into Aw for the own
+// tridiagonalisation, column-major into Rm for rocSOLVER zheevd (or when
+// colmajor is forced, for the single-step entry point).
+slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor) {
   const slrx_dims& d = pl->d;
   KTimer kt(pl, SLRX_K_GRAM);
   STCHK(images(pl));
@@ -76,20 +78,48 @@ slrx_status slrx::step_gram(slrx_plan* pl) {
   ga.rho = pl->img;
   ga.c1 = pl->c1;
   ga.g = pl->g;
-  ga.R = pl->Rm;
+  const bool lib = pl->lib_eigh() || colmajor;
+  ga.R = lib ? pl->Rm : pl->Aw;
+  ga.rowmajor = lib ? 0 : 1;
   ga.twP = pl->twPd;
   ga.twQ = pl->twQd;
   HIPCHK(launch_gram(ga, pl->stream));
   return SLRX_OK;
 }
 
+// Eigen-decomposition of the Gram matrix: own Householder tridiagonalisation,
+// rocSOLVER divide-and-conquer on the tridiagonal and back-transformation
+// (eigenvectors into UZ); or rocSOLVER zheevd on Rm (SLRX_FLAG_LIBEIGH).
 slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
-  const int s = pl->d.N1 * pl->d.N2 * pl->d.M;
+  const int s = pl->s();
+  rocblas_int* info = pl->info + (it < 0 ? SLRX_MAX_IRLS : it);
   KTimer kt(pl, SLRX_K_EIGH);
-  rocblas_status rs = rocsolver_zheevd(pl->blas, rocblas_evect_original, rocblas_fill_lower, s,
-                                       (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework,
-                                       pl->info + (it < 0 ? SLRX_MAX_IRLS : it));
-  if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zheevd failed (status %d)", (int)rs);
+  if (pl->lib_eigh()) {
+    rocblas_status rs = rocsolver_zheevd(pl->blas, rocblas_evect_original, rocblas_fill_lower, s,
+                                         (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework, info);
+    if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zheevd failed (status %d)", (int)rs);
+    return SLRX_OK;
+  }
+  TriArgs ta{};
+  ta.n = s;
+  ta.Aw = pl->Aw;
+  ta.Vst = pl->Rm;
+  ta.strideA = (long)s * s;
+  ta.D = pl->lam;
+  ta.E = pl->ework;
+  ta.tau = pl->tau;
+  ta.vbuf[0] = pl->triv;
+  ta.vbuf[1] = pl->triv + s;
+  ta.pbuf[0] = pl->trip;
+  ta.pbuf[1] = pl->trip + s;
+  HIPCHK(launch_tridiag(ta, 1, pl->stream));
+  rocblas_status rs = rocsolver_zstedc(pl->blas, rocblas_evect_tridiagonal, s, pl->lam, pl->ework,
+                                       (rocblas_double_complex*)pl->UZ, s, info);
+  if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zstedc failed (status %d)", (int)rs);
+  rs = rocsolver_zunmtr(pl->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, s, s,
+                        (rocblas_double_complex*)pl->Rm, s, (rocblas_double_complex*)pl->tau,
+                        (rocblas_double_complex*)pl->UZ, s);
+  if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zunmtr failed (status %d)", (int)rs);
   return SLRX_OK;
 }
 
@@ -100,7 +130,7 @@ slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma) 
   WeightArgs wa{};
   wa.s = s;
   wa.lamv = pl->lam;
-  wa.U = pl->Rm;
+  wa.U = pl->lib_eigh() ? pl->Rm : pl->UZ;
   wa.VT = pl->VT;
   wa.eps = pl->scal;
   wa.lam_max_out = it >= 0 ? pl->stats + SLRX_MAX_IRLS + it : nullptr;

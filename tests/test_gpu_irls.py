@@ -55,6 +55,22 @@ def test_c1_full_counts():
     check(workload.config_problem("c1"))
 
 
+def test_c1_library_eigensolver_path():
+    # the reference path (rocSOLVER zheevd for the whole decomposition) agrees too
+    pb = workload.config_problem("c1")
+    say("irls c1 with SLRX_FLAG_LIBEIGH")
+    T, P, Q = pb.b.shape
+    prm = slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg, lib_eigh=True)
+    with slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, prm) as pl:
+        pl.set_kspace(pb.b)
+        pl.set_mask(pb.S)
+        pl.run()
+        pl.sync()
+        img = pl.images()
+    ref, _ = run_oracle(pb)
+    assert nrmse(img, ref) <= TOL
+
+
 def test_c2_three_outer_iterations():
     check(workload.config_problem("c2"), n_irls=3)
 

@@ -28,6 +28,9 @@ STEP_SHAPES = [
     (3, 192, 16, 2, 3, 1),
     (12, 8, 8, 1, 1, 1),
     (16, 128, 128, 9, 9, 5),
+    (6, 16, 16, 2, 1, 1),
+    (6, 16, 16, 1, 1, 3),
+    (20, 256, 256, 15, 15, 5),
 ]
 
 
