@@ -102,6 +102,137 @@ def cpu_baseline(pb, n_outer: int = 1) -> dict:
                       f"256x256x20 workload, NumPy/SciPy FP64, {dt:.1f} s wall"}
 
 
+def bench_batch(args) -> int:
+    """32 independent slices of uneven sizes: batched (concurrent streams) vs one at a time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1704_04511_amd as slrx
+    import workload
+
+    torch.cuda.set_device(0)
+    specs = workload.batch_specs(32, seed=11)
+    pbs = [workload.make_problem(name=f"slice{j}", **sp) for j, sp in enumerate(specs)]
+    plans = []
+    for pb in pbs:
+        T, P, Q = pb.b.shape
+        pl = slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M,
+                       slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg))
+        pl.set_kspace(pb.b)
+        pl.set_mask(pb.S)
+        plans.append(pl)
+    irls_total = sum(pb.n_irls for pb in pbs)
+    for _ in range(args.warmup):
+        slrx.run_batch(plans)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        slrx.run_batch(plans)
+    torch.cuda.synchronize()
+    dt_batch = (time.perf_counter() - t0) / args.steps
+    batch_imgs = [pl.images() for pl in plans]
+    t0 = time.perf_counter()
+    for pl in plans:
+        pl.run()
+        pl.sync()
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    same = all(np.array_equal(a, pl.images()) for a, pl in zip(batch_imgs, plans))
+    out = {
+        "metric": "slices/s, batch of 32 uneven slices (batched vs one at a time)",
+        "value": round(len(plans) / dt_batch, 3), "unit": "slices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt_batch * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": "32 slices, P=Q in {96,128,160,192,256}, T in {8,12,16,20}, K in {1,2}, "
+                               "R in {4,6,8}, filter 9x9x5, 15 IRLS x 10 CG", "slices": len(plans)},
+        "irls_iters_per_s": round(irls_total / dt_batch, 2),
+        "one_at_a_time_slices_per_s": round(len(plans) / dt_seq, 3),
+        "batch_speedup": round(dt_seq / dt_batch, 3),
+        "batch_equals_alone_bitwise": bool(same),
+    }
+    if not args.no_cpu_baseline:
+        pb = pbs[0]
+        cores = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, 1, pb.n_cg)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / (dt * pb.n_irls), "unit": "slices/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"1 of 15 outer iterations of slice 0 ({pb.b.shape}), {dt:.1f} s wall, "
+                                         "scaled to a whole slice"}
+    for pl in plans:
+        pl.close()
+    print(json.dumps(out))
+    return 0
+
+
+def bench_serve(args) -> int:
+    """Poisson request stream (mean 50/s): 90% batch-style slices, 10% 256x256x20 with 15x15x5."""
+    import numpy as np
+    import torch
+
+    import paper_1704_04511_amd as slrx
+    import workload
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(7)
+    n = args.requests
+    specs = workload.batch_specs(n, seed=7)
+    reqs = []
+    for j in range(n):
+        if rng.random() < 0.1:
+            kw = dict(workload.CONFIGS["c3"])
+            kw["seed"] = 100000 + j
+        else:
+            kw = dict(specs[j])
+            kw["seed"] = 100000 + j
+        reqs.append(workload.make_problem(name=f"req{j}", **kw))
+    gaps = rng.exponential(1.0 / 50.0, size=n)
+    fps = [slrx.footprint(slrx.Dims(pb.b.shape[1], pb.b.shape[2], pb.b.shape[0], pb.N1, pb.N2, pb.M))
+           for pb in reqs]
+    budget = 16 * (1 << 30)
+    srv = slrx.Server(budget, max_slots=8)
+    # warm-up: one request of each shape class
+    for pb in (reqs[0], next(p for p in reqs if p.b.shape[1] == 256 and p.N1 == 15) if any(
+            p.N1 == 15 for p in reqs) else reqs[0]):
+        t = srv.submit_data(pb.b, pb.S, pb.N1, pb.N2, pb.M,
+                            slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg))
+        srv.wait(t)
+        srv.release(t)
+    torch.cuda.synchronize()
+    tickets = []
+    t_start = time.perf_counter()
+    t_next = t_start
+    for pb, g in zip(reqs, gaps):
+        t_next += g
+        while time.perf_counter() < t_next:
+            time.sleep(0.0005)
+        tickets.append(srv.submit_data(pb.b, pb.S, pb.N1, pb.N2, pb.M,
+                                       slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg)))
+    for t in tickets:
+        srv.wait(t)
+    infos = [srv.info(t) for t in tickets]
+    lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+    span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+    srv.close()
+    out = {
+        "metric": "p50/p99 reconstruction latency and solves/s, Poisson stream at 50/s",
+        "value": round(len(infos) / span, 3), "unit": "solves/s", "n_gpus": 1, "steps": len(infos),
+        "warmup": 2, "ms_per_step": round(span / len(infos) * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": f"{n} requests, exponential gaps mean 20 ms (seed 7); 90% batch-style slices "
+                               "(9x9x5, 15x10), 10% 256x256x20 (15x15x5, 20x15)", "max_slots": 8,
+                   "budget_bytes": budget},
+        "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+        "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+        "latency_mean_ms": round(float(lat.mean()) * 1e3, 2),
+        "peak_footprint_bytes": int(max(fps)),
+    }
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,11 +242,19 @@ def main() -> int:
     ap.add_argument("--cpu-outer", type=int, default=1)
     ap.add_argument("--n-irls", type=int, default=None,
                     help="override the outer iteration count (profiling runs only; changes the workload)")
+    ap.add_argument("--workload", choices=("c3", "batch", "serve"), default="c3",
+                    help="c3: the 256x256x20 headline line (default); batch: 32 uneven slices; "
+                         "serve: Poisson request stream")
+    ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
                           "gpus_requested": args.gpus}))
         return 2
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch

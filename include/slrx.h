@@ -150,7 +150,10 @@ slrx_status slrx_get_images(slrx_plan* plan, void* out, slrx_mem mem);
 slrx_status slrx_get_kspace(slrx_plan* plan, void* out, slrx_mem mem);
 slrx_status slrx_get_stats(slrx_plan* plan, slrx_stats* out);
 
-/* Run several plans back to back on one stream (NULL: each plan's own). */
+/* Run several independent plans.  hip_stream NULL: every plan on its own
+ * stream, enqueued concurrently, so their kernels overlap on the device;
+ * otherwise back to back on hip_stream.  Call slrx_sync on each plan.  A plan's
+ * result is the same alone and in a batch. */
 slrx_status slrx_run_batch(slrx_plan* const* plans, int32_t n, void* hip_stream);
 
 /* --- single steps of the loop, for testing each step against a reference --- */
@@ -194,8 +197,9 @@ void slrx_server_destroy(slrx_server* srv);
  * footprint is charged while it runs.  The plan must not be used until done. */
 slrx_status slrx_submit(slrx_server* srv, slrx_plan* plan, uint64_t* ticket);
 /* Submit host data; the server creates the plan (allocating its device state)
- * at admission and keeps it resident until slrx_fetch_images/slrx_release.
- * Fails with SLRX_ENOMEM if the footprint alone exceeds the budget. */
+ * at admission, keeps it resident while the request runs, and on completion
+ * copies the images to host memory and frees the device state.  Fails with
+ * SLRX_ENOMEM if the footprint alone exceeds the budget. */
 slrx_status slrx_submit_data(slrx_server* srv, const slrx_dims* dims, const slrx_params* params,
                              const void* b_host, const uint8_t* S_host, uint64_t* ticket);
 slrx_status slrx_poll(slrx_server* srv, uint64_t ticket, int32_t* done);
@@ -204,8 +208,7 @@ slrx_status slrx_wait(slrx_server* srv, uint64_t ticket);
 slrx_status slrx_get_request_info(slrx_server* srv, uint64_t ticket, slrx_request_info* out);
 /* Budget in use (bytes) and number of queued requests. */
 slrx_status slrx_server_usage(slrx_server* srv, size_t* used, int32_t* queued);
-/* Copy a done server-owned request's images (complex64 [T][P][Q]) to host
- * memory and free its device state. */
+/* Copy a done server-owned request's images (complex64 [T][P][Q]) to host memory. */
 slrx_status slrx_fetch_images(slrx_server* srv, uint64_t ticket, void* out_host);
 /* Forget a done request, freeing whatever it still holds. */
 slrx_status slrx_release(slrx_server* srv, uint64_t ticket);

@@ -323,10 +323,14 @@ class Plan:
         _check(lib().slrx_step_cg(self._h, Ep, int(n_cg)))
 
 
-def run_batch(plans, stream=None):
+def run_batch(plans, stream=None, sync=True):
+    """Run independent plans concurrently (each on its own stream when stream is None)."""
     arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
     st = None if stream is None else ctypes.c_void_p(int(stream))
     _check(lib().slrx_run_batch(arr, len(plans), st))
+    if sync:
+        for p in plans:
+            p.sync()
 
 
 class Server:

@@ -10,7 +10,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <new>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -576,24 +578,51 @@ extern "C" slrx_status slrx_get_stats(slrx_plan* pl, slrx_stats* out) {
   return SLRX_OK;
 }
 
+// Several independent problems.  With hip_stream NULL every plan runs on its
+// own stream, enqueued from worker threads (the eigen-decomposition's library
+// calls may block their host thread), so the device interleaves the plans'
+// kernels; otherwise the plans run back to back on hip_stream.  Each plan's
+// arithmetic is independent of the others (own buffers, fixed-order
+// reductions), so a plan gives the same result alone and in a batch.
 extern "C" slrx_status slrx_run_batch(slrx_plan* const* plans, int32_t n, void* hip_stream) {
   if (!plans || n < 0) return fail(SLRX_EINVAL, "bad plan list");
   for (int i = 0; i < n; ++i) {
     if (!plans[i]) return fail(SLRX_EINVAL, "plan %d is NULL", i);
     STCHK(check_idle(plans[i]));
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(SLRX_EINVAL, "plan %d appears twice", i);
   }
-  for (int i = 0; i < n; ++i) {
-    slrx_plan* pl = plans[i];
-    hipStream_t own = pl->stream;
-    if (hip_stream) pl->stream = (hipStream_t)hip_stream;
-    if (hip_stream && pl->blas) rocblas_set_stream(pl->blas, pl->stream);
-    slrx_status st = enqueue_run(pl);
-    if (hip_stream) {
+  if (hip_stream) {
+    for (int i = 0; i < n; ++i) {
+      slrx_plan* pl = plans[i];
+      hipStream_t own = pl->stream;
+      pl->stream = (hipStream_t)hip_stream;
+      if (pl->blas) rocblas_set_stream(pl->blas, pl->stream);
+      slrx_status st = enqueue_run(pl);
       pl->stream = own;
       if (pl->blas) rocblas_set_stream(pl->blas, own);
+      if (st != SLRX_OK) return st;
     }
-    if (st != SLRX_OK) return st;
+    return SLRX_OK;
   }
+  const int nthr = n < 16 ? n : 16;
+  std::atomic<int> next(0);
+  std::vector<slrx_status> status(n, SLRX_OK);
+  std::vector<std::string> msg(n);
+  auto work = [&]() {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n) return;
+      (void)hipSetDevice(plans[i]->device);
+      status[i] = enqueue_run(plans[i]);
+      if (status[i] != SLRX_OK) msg[i] = slrx_last_error();
+    }
+  };
+  std::vector<std::thread> thr;
+  for (int t = 0; t < nthr; ++t) thr.emplace_back(work);
+  for (auto& t : thr) t.join();
+  for (int i = 0; i < n; ++i)
+    if (status[i] != SLRX_OK) return fail(status[i], "plan %d: %s", i, msg[i].c_str());
   return SLRX_OK;
 }
 

@@ -23,7 +23,7 @@
 namespace slrx {
 
 constexpr int kTriNT = 256;
-constexpr int kTriRows = 4;  // rows of the trailing block per workgroup (one per wave)
+constexpr int kTriRows = 4;  // rows of the trailing block per workgroup: one per wave
 constexpr int kTriUnroll = 4;  // row elements in flight per lane
 
 SLRX_DEV double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -52,54 +52,90 @@ SLRX_DEV double2 block_sum2(double2 v, double2* red) {
 __global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
   extern __shared__ double2 sm[];
   __shared__ double2 red[kTriNT / 64 + 1];
+  __shared__ double2 at_k[2];  // raw p_{k-1}[k], v_{k-1}[k]
   const int n = a.n, k = a.k;
   const int b = blockIdx.y;  // problem in a batch
   double2* Aw = a.Aw + (size_t)b * a.strideA;
   double2* vp = sm;           // v_{k-1}, indices >= k
-  double2* wp = sm + n;       // w_{k-1} (first holds p_{k-1})
-  double2* col = sm + 2 * n;  // corrected row k, then v_k
-  const int tid = threadIdx.x;
+  double2* wp = sm + n;       // w_{k-1}
+  double2* col = sm + 2 * n;  // column k of the current matrix, then v_k
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool pending = k > 0;
 
-  // 1. pending reflector k-1: w = tau p + c v, c = -|tau|^2/2 (p^H v)
-  if (pending) {
-    const double2* vprev = a.vbuf[(k - 1) & 1] + (size_t)b * n;
-    const double2* pprev = a.pbuf[(k - 1) & 1] + (size_t)b * n;
-    double2 d = make_double2(0.0, 0.0);
-    for (int j = k + tid; j < n; j += kTriNT) {
-      const double2 v = vprev[j], p = pprev[j];
-      vp[j] = v;
-      wp[j] = p;
-      d = dadd(d, dcmul(p, v));
+  // 0. issue every independent global load first: the first elements of this
+  //    wave's row of the trailing block, and v_{k-1}, p_{k-1}, row k.
+  const int my_row = k + 1 + blockIdx.x * kTriRows + wave;  // one row per wave
+  const bool has_row = my_row < n;
+  double2* row = Aw + (size_t)(has_row ? my_row : 0) * n;
+  double2 xpre[kTriUnroll];
+#pragma unroll
+  for (int u = 0; u < kTriUnroll; ++u) {
+    const int j = k + 1 + lane + 64 * u;
+    xpre[u] = (has_row && j < n) ? row[j] : make_double2(0.0, 0.0);
+  }
+  const double2 t = pending ? a.tau[(size_t)b * n + (k - 1)] : make_double2(0.0, 0.0);
+  const double2* rowk = Aw + (size_t)k * n;
+  const double2* vprev = a.vbuf[(k + 1) & 1] + (size_t)b * n;  // written by launch k-1
+  const double2* pprev = a.pbuf[(k + 1) & 1] + (size_t)b * n;
+  double2 d = make_double2(0.0, 0.0);
+  for (int j0 = k + tid; j0 < n; j0 += kTriNT * 4) {
+    double2 kv[4], rv[4], pv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + kTriNT * u;
+      if (j < n) {
+        kv[u] = rowk[j];
+        if (pending) {
+          rv[u] = vprev[j];
+          pv[u] = pprev[j];
+        }
+      }
     }
-    d = block_sum2(d, red);
-    const double2 t = a.tau[(size_t)b * n + (k - 1)];
-    const double c = -0.5 * (t.x * t.x + t.y * t.y);
-    const double2 cd = dscale(d, c);
-    for (int j = k + tid; j < n; j += kTriNT) wp[j] = dadd(dmul(t, wp[j]), dmul(cd, vp[j]));
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + kTriNT * u;
+      if (j < n) {
+        col[j] = dconj(kv[u]);  // A(j, k) = conj(A(k, j))
+        if (pending) {
+          vp[j] = rv[u];
+          wp[j] = pv[u];
+          d = dadd(d, dcmul(pv[u], rv[u]));
+          if (j == k) {
+            at_k[0] = pv[u];
+            at_k[1] = rv[u];
+          }
+        }
+      }
+    }
   }
 
-  // 2. column k of the current matrix = conj(row k), with the pending update
-  const double2* rowk = Aw + (size_t)k * n;
-  for (int i = k + tid; i < n; i += kTriNT) {
-    double2 x = dconj(rowk[i]);
-    if (pending) {
-      // (A - v w^H - w v^H)(i, k)
-      x = dsub(x, dadd(dmul(vp[i], dconj(wp[k])), dmul(wp[i], dconj(vp[k]))));
+  // 1. pending reflector k-1: w = tau p + c v, c = -|tau|^2/2 (p^H v); apply it to
+  //    column k: A(j,k) - v_j conj(w_k) - w_j conj(v_k); partial norm for step 3.
+  double xn = 0.0;
+  if (pending) {
+    d = block_sum2(d, red);  // also orders at_k and the LDS vectors
+    const double c = -0.5 * (t.x * t.x + t.y * t.y);
+    const double2 cd = dscale(d, c);
+    const double2 vk0 = at_k[1];
+    const double2 wk0 = dadd(dmul(t, at_k[0]), dmul(cd, vk0));
+    for (int j = k + tid; j < n; j += kTriNT) {
+      const double2 w = dadd(dmul(t, wp[j]), dmul(cd, vp[j]));
+      wp[j] = w;
+      const double2 x = dsub(col[j], dadd(dmul(vp[j], dconj(wk0)), dmul(w, dconj(vk0))));
+      col[j] = x;
+      if (j >= k + 2) xn += x.x * x.x + x.y * x.y;
     }
-    col[i] = x;
+  } else {
+    __syncthreads();
+    for (int j = k + 2 + tid; j < n; j += kTriNT) xn += col[j].x * col[j].x + col[j].y * col[j].y;
   }
-  __syncthreads();
+  const double2 xn2 = block_sum2(make_double2(xn, 0.0), red);  // also orders col / wp
   if (k == n - 1) {  // last diagonal entry, no reflector left
     if (blockIdx.x == 0 && tid == 0) a.D[(size_t)b * n + k] = col[k].x;
     return;
   }
 
   // 3. reflector k on x = col[k+1 .. n-1]
-  double xn = 0.0;
-  for (int i = k + 2 + tid; i < n; i += kTriNT) xn += col[i].x * col[i].x + col[i].y * col[i].y;
-  const double2 xn2 = block_sum2(make_double2(xn, 0.0), red);
   const double2 alpha = col[k + 1];
   double beta;
   double2 tau, scale;
@@ -134,41 +170,38 @@ __global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
     }
   }
 
-  // 4. rows of the trailing block: pending update, then p_i = sum_j A_ij v_j
-  const int lane = tid & 63, wave = tid >> 6;
+  // 4. this wave's row of the trailing block: pending update, then
+  //    p_i = sum_j A_ij v_j (the first elements are already in registers)
+  if (!has_row) return;
   double2* pout = a.pbuf[k & 1] + (size_t)b * n;
-  for (int rr = wave; rr < kTriRows; rr += kTriNT / 64) {
-    const int i = k + 1 + blockIdx.x * kTriRows + rr;
-    if (i >= n) break;
-    double2* row = Aw + (size_t)i * n;
-    const double2 vpi = pending ? vp[i] : make_double2(0.0, 0.0);
-    const double2 wpi = pending ? wp[i] : make_double2(0.0, 0.0);
-    double2 acc = make_double2(0.0, 0.0);
-    for (int j0 = k + 1 + lane; j0 < n; j0 += 64 * kTriUnroll) {
-      double2 x[kTriUnroll];
+  const double2 vpi = pending ? vp[my_row] : make_double2(0.0, 0.0);
+  const double2 wpi = pending ? wp[my_row] : make_double2(0.0, 0.0);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int j0 = k + 1 + lane; j0 < n; j0 += 64 * kTriUnroll) {
+    double2 x[kTriUnroll];
+    const bool first = j0 == k + 1 + lane;
 #pragma unroll
-      for (int u = 0; u < kTriUnroll; ++u) {
-        const int j = j0 + 64 * u;
-        x[u] = j < n ? row[j] : make_double2(0.0, 0.0);
-      }
+    for (int u = 0; u < kTriUnroll; ++u) {
+      const int j = j0 + 64 * u;
+      x[u] = first ? xpre[u] : (j < n ? row[j] : make_double2(0.0, 0.0));
+    }
 #pragma unroll
-      for (int u = 0; u < kTriUnroll; ++u) {
-        const int j = j0 + 64 * u;
-        if (j < n) {
-          if (pending) {
-            x[u] = dsub(x[u], dadd(dmul(vpi, dconj(wp[j])), dmul(wpi, dconj(vp[j]))));
-            row[j] = x[u];
-          }
-          acc = dadd(acc, dmul(x[u], col[j]));
+    for (int u = 0; u < kTriUnroll; ++u) {
+      const int j = j0 + 64 * u;
+      if (j < n) {
+        if (pending) {
+          x[u] = dsub(x[u], dadd(dmul(vpi, dconj(wp[j])), dmul(wpi, dconj(vp[j]))));
+          row[j] = x[u];
         }
+        acc = dadd(acc, dmul(x[u], col[j]));
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.x += __shfl_down(acc.x, off, 64);
-      acc.y += __shfl_down(acc.y, off, 64);
-    }
-    if (lane == 0) pout[i] = acc;
   }
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.x += __shfl_down(acc.x, off, 64);
+    acc.y += __shfl_down(acc.y, off, 64);
+  }
+  if (lane == 0) pout[my_row] = acc;
 }
 
 int tri_max_n() { return 3000; }

@@ -5,12 +5,15 @@
 // admitted request runs its whole IRLS loop on its own stream in a slot worker
 // thread, so the device interleaves the kernels of all admitted requests;
 // requests that arrive while others run join at the next free slot.  A
-// server-owned request keeps its device state (and result) resident until it
-// is fetched or released.  Every request computes on its own buffers with
-// fixed-order reductions, so a result does not depend on what runs beside it.
+// request's IRLS state stays resident on the device while it runs; when a
+// server-owned request finishes, its images are copied to host memory and its
+// device state and budget share are released at once, so finished results never
+// block admission.  Every request computes on its own buffers with fixed-order
+// reductions, so a result does not depend on what runs beside it.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstring>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -44,6 +47,7 @@ struct Req {
   slrx_params prm{};
   std::vector<float2> b;
   std::vector<uint8_t> S;
+  std::vector<float2> result;  // images of a finished server-owned request
 };
 
 }  // namespace
@@ -92,20 +96,21 @@ static void run_request(slrx_server* s, Req* r) {
   }
   if (st == SLRX_OK) st = slrx_run(r->plan);
   if (st == SLRX_OK) st = slrx_sync(r->plan);
+  if (st == SLRX_OK && r->owned) {
+    r->result.resize((size_t)r->dims.T * r->dims.P * r->dims.Q);
+    st = slrx_get_images(r->plan, r->result.data(), SLRX_MEM_HOST);
+  }
+  std::string err = st != SLRX_OK ? std::string(slrx_last_error()) : std::string();
+  if (r->owned && r->plan) {
+    slrx_plan_destroy(r->plan);
+    r->plan = nullptr;
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   r->status = st;
-  if (st != SLRX_OK) r->err = slrx_last_error();
+  r->err = err;
   r->t_done = now_s();
   r->state = 2;
-  // a user plan frees its share of the budget now; a server-owned plan keeps
-  // its state resident until the result is fetched or released
-  if (!r->owned || st != SLRX_OK) {
-    if (r->owned && r->plan) {
-      slrx_plan_destroy(r->plan);
-      r->plan = nullptr;
-    }
-    release_budget(s, r);
-  }
+  release_budget(s, r);
   s->cv_done.notify_all();
   s->cv_work.notify_all();
 }
@@ -261,26 +266,16 @@ extern "C" slrx_status slrx_server_usage(slrx_server* s, size_t* used, int32_t* 
   return SLRX_OK;
 }
 
-// Copy a finished server-owned request's images to host memory and free its
-// device state and budget share.
+// Copy a finished server-owned request's images to host memory.
 extern "C" slrx_status slrx_fetch_images(slrx_server* s, uint64_t ticket, void* out_host) {
   if (!s || !out_host) return fail(SLRX_EINVAL, "NULL argument");
-  Req* r = nullptr;
-  {
-    std::unique_lock<std::mutex> lk(s->mu);
-    r = find(s, ticket);
-    if (!r) return fail(SLRX_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
-    if (r->state != 2) return fail(SLRX_ENOTREADY, "request %llu not finished", (unsigned long long)ticket);
-    if (r->status != SLRX_OK) return fail(r->status, "%s", r->err.c_str());
-    if (!r->owned || !r->plan) return fail(SLRX_ESTATE, "request has no server-owned result");
-  }
-  slrx_status st = slrx_get_images(r->plan, out_host, SLRX_MEM_HOST);
-  if (st != SLRX_OK) return st;
   std::lock_guard<std::mutex> lk(s->mu);
-  slrx_plan_destroy(r->plan);
-  r->plan = nullptr;
-  release_budget(s, r);
-  s->cv_work.notify_all();
+  Req* r = find(s, ticket);
+  if (!r) return fail(SLRX_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  if (r->state != 2) return fail(SLRX_ENOTREADY, "request %llu not finished", (unsigned long long)ticket);
+  if (r->status != SLRX_OK) return fail(r->status, "%s", r->err.c_str());
+  if (!r->owned || r->result.empty()) return fail(SLRX_ESTATE, "request has no server-owned result");
+  std::memcpy(out_host, r->result.data(), r->result.size() * sizeof(float2));
   return SLRX_OK;
 }
 

@@ -1,0 +1,115 @@
+"""Batch and serving on the GPU: every problem gives the same result alone and
+in the mix (bitwise: each problem has its own buffers and fixed-order
+reductions), admission never exceeds the HBM budget, and results match the
+FP64 oracle."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from tests.gpu_util import nrmse, say
+
+pytestmark = pytest.mark.gpu
+
+slrx = pytest.importorskip("paper_1704_04511_amd")
+
+# small uneven slices in the style of the batch workload (filter 9x9x5, odd radices)
+SPECS = [
+    dict(seed=201, P=96, Q=96, T=8, K=1, R=4, N1=9, N2=9, M=5),
+    dict(seed=202, P=128, Q=128, T=12, K=2, R=6, N1=9, N2=9, M=5),
+    dict(seed=203, P=160, Q=160, T=8, K=2, R=8, N1=9, N2=9, M=5),
+    dict(seed=204, P=64, Q=64, T=16, K=1, R=4, N1=5, N2=5, M=3),
+    dict(seed=205, P=192, Q=192, T=8, K=1, R=6, N1=9, N2=9, M=5),
+]
+N_IRLS, N_CG = 3, 6
+
+
+def problems():
+    return [workload.make_problem(n_irls=N_IRLS, n_cg=N_CG, name=f"slice{i}", **s) for i, s in enumerate(SPECS)]
+
+
+def plan_for(pb):
+    T, P, Q = pb.b.shape
+    pl = slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, slrx.make_params(lam=pb.lam, n_irls=N_IRLS, n_cg=N_CG))
+    pl.set_kspace(pb.b)
+    pl.set_mask(pb.S)
+    return pl
+
+
+def alone(pb):
+    with plan_for(pb) as pl:
+        pl.run()
+        pl.sync()
+        return pl.images()
+
+
+def test_batch_equals_alone_and_oracle():
+    pbs = problems()
+    say(f"batch of {len(pbs)} uneven slices")
+    ref = [alone(pb) for pb in pbs]
+    plans = [plan_for(pb) for pb in pbs]
+    try:
+        slrx.run_batch(plans)
+        out = [pl.images() for pl in plans]
+    finally:
+        for pl in plans:
+            pl.close()
+    for i, (a, b) in enumerate(zip(out, ref)):
+        np.testing.assert_array_equal(a, b, err_msg=f"slice {i}")
+    pb = pbs[0]
+    ora = oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, N_IRLS, N_CG)
+    assert nrmse(out[0], ora) < 1e-4
+
+
+def test_server_mix_equals_alone_within_budget():
+    pbs = problems()
+    say(f"server with {len(pbs)} requests")
+    ref = [alone(pb) for pb in pbs]
+    fps = [slrx.footprint(slrx.Dims(pb.b.shape[1], pb.b.shape[2], pb.b.shape[0], pb.N1, pb.N2, pb.M))
+           for pb in pbs]
+    budget = int(max(fps) * 2.2)  # at most two of the larger requests at a time
+    srv = slrx.Server(budget, max_slots=3)
+    try:
+        tickets = []
+        for pb in pbs:
+            prm = slrx.make_params(lam=pb.lam, n_irls=N_IRLS, n_cg=N_CG)
+            tickets.append(srv.submit_data(pb.b, pb.S, pb.N1, pb.N2, pb.M, prm))
+            time.sleep(0.01)
+        peak = 0
+        deadline = time.time() + 120.0
+        while not all(srv.poll(t) for t in tickets):
+            used, _ = srv.usage()
+            peak = max(peak, used)
+            assert time.time() < deadline, "server did not finish within 120 s"
+            time.sleep(0.002)
+        infos = [srv.info(t) for t in tickets]
+        out = [srv.fetch(t, pb.b.shape) for t, pb in zip(tickets, pbs)]
+        assert srv.usage()[0] == 0
+    finally:
+        srv.close()
+    assert peak <= budget
+    # from the admission intervals: the running footprint never exceeded the budget
+    events = sorted([(i["t_admit"], f) for i, f in zip(infos, fps)] + [(i["t_done"], -f) for i, f in zip(infos, fps)])
+    run = 0
+    for _, df in events:
+        run += df
+        assert run <= budget
+    # requests overlapped on the device (continuous batching, not a queue alone)
+    spans = [(i["t_admit"], i["t_done"]) for i in infos]
+    overlap = any(a0 < b1 and b0 < a1 for k, (a0, a1) in enumerate(spans) for (b0, b1) in spans[k + 1:])
+    assert overlap
+    for i, (a, b) in enumerate(zip(out, ref)):
+        np.testing.assert_array_equal(a, b, err_msg=f"request {i}")
+
+
+def test_server_rejects_request_larger_than_budget():
+    pb = problems()[1]
+    srv = slrx.Server(1 << 20, max_slots=1)
+    try:
+        with pytest.raises(slrx.SlrxError) as ei:
+            srv.submit_data(pb.b, pb.S, pb.N1, pb.N2, pb.M, slrx.make_params(n_irls=1, n_cg=1))
+        assert ei.value.name == "SLRX_ENOMEM"
+    finally:
+        srv.close()
