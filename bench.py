@@ -103,7 +103,8 @@ def cpu_baseline(pb, n_outer: int = 1) -> dict:
 
 
 def bench_batch(args) -> int:
-    """32 independent slices of uneven sizes: batched (concurrent streams) vs one at a time."""
+    """32 independent slices of uneven sizes: lock-step batch (shared batched
+    eigen-decompositions) vs one plan at a time."""
     import numpy as np
     import torch
 
@@ -138,7 +139,12 @@ def bench_batch(args) -> int:
         pl.sync()
     torch.cuda.synchronize()
     dt_seq = time.perf_counter() - t0
-    same = all(np.array_equal(a, pl.images()) for a, pl in zip(batch_imgs, plans))
+    seq_nrmse = max(float(np.linalg.norm(a - pl.images()) / np.linalg.norm(pl.images()))
+                    for a, pl in zip(batch_imgs, plans))
+    same = True  # a slice in the batch gives the bits of the same slice as a batch of one
+    for a, pl in list(zip(batch_imgs, plans))[:4]:
+        slrx.run_batch([pl])
+        same = same and bool(np.array_equal(a, pl.images()))
     out = {
         "metric": "slices/s, batch of 32 uneven slices (batched vs one at a time)",
         "value": round(len(plans) / dt_batch, 3), "unit": "slices/s", "n_gpus": 1, "steps": args.steps,
@@ -149,7 +155,8 @@ def bench_batch(args) -> int:
         "irls_iters_per_s": round(irls_total / dt_batch, 2),
         "one_at_a_time_slices_per_s": round(len(plans) / dt_seq, 3),
         "batch_speedup": round(dt_seq / dt_batch, 3),
-        "batch_equals_alone_bitwise": bool(same),
+        "batch_equals_batch_of_one_bitwise": bool(same),
+        "batch_vs_single_run_max_nrmse": float(f"{seq_nrmse:.3e}"),
     }
     if not args.no_cpu_baseline:
         pb = pbs[0]
@@ -192,7 +199,7 @@ def bench_serve(args) -> int:
     fps = [slrx.footprint(slrx.Dims(pb.b.shape[1], pb.b.shape[2], pb.b.shape[0], pb.N1, pb.N2, pb.M))
            for pb in reqs]
     budget = 16 * (1 << 30)
-    srv = slrx.Server(budget, max_slots=8)
+    srv = slrx.Server(budget, max_slots=16)
     # warm-up: one request of each shape class
     for pb in (reqs[0], next(p for p in reqs if p.b.shape[1] == 256 and p.N1 == 15) if any(
             p.N1 == 15 for p in reqs) else reqs[0]):
@@ -222,7 +229,7 @@ def bench_serve(args) -> int:
         "warmup": 2, "ms_per_step": round(span / len(infos) * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
         "config": {"workload": f"{n} requests, exponential gaps mean 20 ms (seed 7); 90% batch-style slices "
-                               "(9x9x5, 15x10), 10% 256x256x20 (15x15x5, 20x15)", "max_slots": 8,
+                               "(9x9x5, 15x10), 10% 256x256x20 (15x15x5, 20x15)", "max_slots": 16,
                    "budget_bytes": budget},
         "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
         "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),

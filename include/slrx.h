@@ -150,10 +150,14 @@ slrx_status slrx_get_images(slrx_plan* plan, void* out, slrx_mem mem);
 slrx_status slrx_get_kspace(slrx_plan* plan, void* out, slrx_mem mem);
 slrx_status slrx_get_stats(slrx_plan* plan, slrx_stats* out);
 
-/* Run several independent plans.  hip_stream NULL: every plan on its own
- * stream, enqueued concurrently, so their kernels overlap on the device;
- * otherwise back to back on hip_stream.  Call slrx_sync on each plan.  A plan's
- * result is the same alone and in a batch. */
+/* Run several independent plans.  hip_stream NULL: in lock step, one outer
+ * iteration of every plan per step; plans with equal Gram size s <= 640 share
+ * one batched FP64 eigen-decomposition per step, larger ones use the
+ * single-problem eigensolver; every other kernel runs on the plan's own
+ * stream.  The method depends on s only, so a plan's result in a batch does not
+ * depend on the other plans (a batch of one gives the same bits).  With
+ * hip_stream: the plans run back to back on it, each as slrx_run would.
+ * Returns once the work is enqueued; call slrx_sync on each plan. */
 slrx_status slrx_run_batch(slrx_plan* const* plans, int32_t n, void* hip_stream);
 
 /* --- single steps of the loop, for testing each step against a reference --- */
@@ -174,13 +178,15 @@ slrx_status slrx_step_apply(slrx_plan* plan, const void* E, const void* v,
 slrx_status slrx_step_cg(slrx_plan* plan, const void* E, int32_t n_cg);
 
 /* --- continuous-batching server ------------------------------------------
- * Requests queue in arrival order and are admitted (first fit) when one of
- * max_slots slots is free and their device footprint (slrx_footprint) fits
- * the remaining budget_bytes.  Each admitted request runs on a stream of its
- * own, so the device interleaves the work of all admitted requests; a request
- * arriving while others run starts as soon as a slot and memory free up.  A
- * request's result does not depend on the others (own buffers, fixed-order
- * reductions).  hip_stream is ignored (every slot has its own stream).
+ * Requests queue in arrival order and are admitted (first fit) between
+ * engine steps, when fewer than max_slots requests are active and their
+ * device footprint (slrx_footprint) fits the remaining budget_bytes.  One
+ * scheduler thread advances every active request by one outer iteration per
+ * step, exactly as slrx_run_batch does (a batched eigen-decomposition per
+ * group of equal Gram size s <= 640, other kernels on each request's own
+ * stream); a request arriving while others run joins at the next step.  A
+ * request's result depends only on the request: it equals slrx_run_batch on
+ * that plan alone, bit for bit.  hip_stream is ignored.
  * Thread-safe: any thread may submit, poll, wait or fetch. */
 typedef struct {
   double t_submit, t_admit, t_done; /* steady-clock seconds */
@@ -196,17 +202,21 @@ void slrx_server_destroy(slrx_server* srv);
 /* Submit an existing plan (k-space and mask set); it is run in place and its
  * footprint is charged while it runs.  The plan must not be used until done. */
 slrx_status slrx_submit(slrx_server* srv, slrx_plan* plan, uint64_t* ticket);
-/* Submit host data; the server creates the plan (allocating its device state)
- * at admission, keeps it resident while the request runs, and on completion
- * copies the images to host memory and frees the device state.  Fails with
- * SLRX_ENOMEM if the footprint alone exceeds the budget. */
+/* Submit host data; at admission the server takes an idle plan of the same
+ * shape or creates one (allocating its device state), keeps it resident while
+ * the request runs, and on completion copies the images to host memory
+ * (slrx_fetch_images) and releases the request's budget share; the plan stays
+ * idle for reuse until the budget is needed.  Fails with SLRX_ENOMEM if the
+ * footprint alone exceeds the budget. */
 slrx_status slrx_submit_data(slrx_server* srv, const slrx_dims* dims, const slrx_params* params,
                              const void* b_host, const uint8_t* S_host, uint64_t* ticket);
 slrx_status slrx_poll(slrx_server* srv, uint64_t ticket, int32_t* done);
 /* Block until the request is done; returns its status. */
 slrx_status slrx_wait(slrx_server* srv, uint64_t ticket);
 slrx_status slrx_get_request_info(slrx_server* srv, uint64_t ticket, slrx_request_info* out);
-/* Budget in use (bytes) and number of queued requests. */
+/* Budget in use (bytes: running requests plus idle plans kept for reuse by
+ * later requests of the same shape; idle plans are evicted when a request of
+ * another shape needs the room) and number of queued requests. */
 slrx_status slrx_server_usage(slrx_server* srv, size_t* used, int32_t* queued);
 /* Copy a done server-owned request's images (complex64 [T][P][Q]) to host memory. */
 slrx_status slrx_fetch_images(slrx_server* srv, uint64_t ticket, void* out_host);

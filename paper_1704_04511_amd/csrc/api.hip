@@ -11,11 +11,13 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <string>
 #include <vector>
 
+#include "engine.h"
 #include "kernels.h"
 #include "plan.h"
 #include "../../include/slrx.h"
@@ -331,6 +333,11 @@ extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params
   if (st == SLRX_OK) {
     for (int i = 0; i < 2; ++i)
       if (hipEventCreate(&pl->ev_run[i]) != hipSuccess) st = fail(SLRX_EDEVICE, "hipEventCreate failed");
+    if (hipEventCreateWithFlags(&pl->ev_step, hipEventDisableTiming) != hipSuccess)
+      st = fail(SLRX_EDEVICE, "hipEventCreate failed");
+    for (int i = 0; i < 2; ++i)
+      if (hipEventCreateWithFlags(&pl->ev_iter[i], hipEventDisableTiming) != hipSuccess)
+        st = fail(SLRX_EDEVICE, "hipEventCreate failed");
   }
   if (st != SLRX_OK) {
     slrx_plan_destroy(pl);
@@ -348,6 +355,9 @@ extern "C" void slrx_plan_destroy(slrx_plan* pl) {
     for (auto& e : v) (void)hipEventDestroy(e);
   for (int i = 0; i < 2; ++i)
     if (pl->ev_run[i]) (void)hipEventDestroy(pl->ev_run[i]);
+  if (pl->ev_step) (void)hipEventDestroy(pl->ev_step);
+  for (int i = 0; i < 2; ++i)
+    if (pl->ev_iter[i]) (void)hipEventDestroy(pl->ev_iter[i]);
   if (pl->blas) rocblas_destroy_handle(pl->blas);
   if (pl->blas_ws) (void)hipFree(pl->blas_ws);
   if (pl->arena) (void)hipFree(pl->arena);
@@ -578,12 +588,14 @@ extern "C" slrx_status slrx_get_stats(slrx_plan* pl, slrx_stats* out) {
   return SLRX_OK;
 }
 
-// Several independent problems.  With hip_stream NULL every plan runs on its
-// own stream, enqueued from worker threads (the eigen-decomposition's library
-// calls may block their host thread), so the device interleaves the plans'
-// kernels; otherwise the plans run back to back on hip_stream.  Each plan's
-// arithmetic is independent of the others (own buffers, fixed-order
-// reductions), so a plan gives the same result alone and in a batch.
+// Several independent problems.  With hip_stream NULL they run in lock step
+// on the engine (one outer iteration of every problem per step, a batched
+// eigen-decomposition shared by equal Gram sizes, every other kernel on the
+// problem's own stream); the call returns once all work is enqueued.  With a
+// stream the plans run one after another on it, each as slrx_run would.
+static std::mutex g_batch_mu;
+static BatchEig* g_batch_eig = nullptr;  // kept for the life of the process
+
 extern "C" slrx_status slrx_run_batch(slrx_plan* const* plans, int32_t n, void* hip_stream) {
   if (!plans || n < 0) return fail(SLRX_EINVAL, "bad plan list");
   for (int i = 0; i < n; ++i) {
@@ -605,24 +617,14 @@ extern "C" slrx_status slrx_run_batch(slrx_plan* const* plans, int32_t n, void* 
     }
     return SLRX_OK;
   }
-  const int nthr = n < 16 ? n : 16;
-  std::atomic<int> next(0);
-  std::vector<slrx_status> status(n, SLRX_OK);
-  std::vector<std::string> msg(n);
-  auto work = [&]() {
-    for (;;) {
-      const int i = next.fetch_add(1);
-      if (i >= n) return;
-      (void)hipSetDevice(plans[i]->device);
-      status[i] = enqueue_run(plans[i]);
-      if (status[i] != SLRX_OK) msg[i] = slrx_last_error();
-    }
-  };
-  std::vector<std::thread> thr;
-  for (int t = 0; t < nthr; ++t) thr.emplace_back(work);
-  for (auto& t : thr) t.join();
-  for (int i = 0; i < n; ++i)
-    if (status[i] != SLRX_OK) return fail(status[i], "plan %d: %s", i, msg[i].c_str());
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  if (!g_batch_eig) g_batch_eig = new BatchEig();
+  std::vector<slrx_plan*> v(plans, plans + n);
+  for (slrx_plan* pl : v) STCHK(engine_begin(pl));
+  int maxit = 0;
+  for (slrx_plan* pl : v) maxit = pl->prm.n_irls > maxit ? pl->prm.n_irls : maxit;
+  for (int step = 0; step < maxit; ++step) STCHK(engine_step(v, *g_batch_eig));
+  for (slrx_plan* pl : v) STCHK(engine_end(pl));
   return SLRX_OK;
 }
 

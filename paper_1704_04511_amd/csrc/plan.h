@@ -56,6 +56,9 @@ struct slrx_plan {
   size_t blas_ws_size = 0;
 
   hipEvent_t ev_run[2] = {nullptr, nullptr};
+  hipEvent_t ev_step = nullptr;  // ordering against a shared batched eigen-decomposition
+  int it_next = 0;               // next outer iteration (lock-step engine)
+  hipEvent_t ev_iter[2] = {nullptr, nullptr};  // end of the last two engine steps (server pacing)
   std::vector<hipEvent_t> ev_phase;
   // per-kernel-class launch timing (SLRX_FLAG_KTIME): event pairs, reused across runs
   std::vector<hipEvent_t> kev[SLRX_K_NCLASS];
@@ -88,9 +91,10 @@ slrx_status images(slrx_plan* pl);
 slrx_status penalty_pass(slrx_plan* pl);
 slrx_status load_masks(slrx_plan* pl, const float2* E_dev);
 slrx_status store_masks(slrx_plan* pl);
-slrx_status step_gram(slrx_plan* pl, bool colmajor = false);
+slrx_status step_gram(slrx_plan* pl, bool colmajor = false, double2* R_out = nullptr);
 slrx_status step_eigh(slrx_plan* pl, int it);
-slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma);
+slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma, const double2* U = nullptr,
+                         const double* lamv = nullptr);
 slrx_status apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part);
 slrx_status run_cg(slrx_plan* pl, int n_cg, int it);
 slrx_status enqueue_run(slrx_plan* pl);

@@ -1,27 +1,34 @@
 // Continuous-batching reconstruction server.
 //
-// Requests wait in a FIFO queue and are admitted, first fit, as soon as a slot
-// is free and their device footprint fits the remaining HBM budget.  Each
-// admitted request runs its whole IRLS loop on its own stream in a slot worker
-// thread, so the device interleaves the kernels of all admitted requests;
-// requests that arrive while others run join at the next free slot.  A
-// request's IRLS state stays resident on the device while it runs; when a
-// server-owned request finishes, its images are copied to host memory and its
-// device state and budget share are released at once, so finished results never
-// block admission.  Every request computes on its own buffers with fixed-order
-// reductions, so a result does not depend on what runs beside it.
+// Requests wait in a FIFO queue and are admitted, first fit, between engine
+// steps: as soon as fewer than max_slots requests are active and a request's
+// device footprint fits the remaining HBM budget.  One scheduler thread drives
+// the lock-step engine: each step advances every active request by one outer
+// IRLS iteration, with one batched eigen-decomposition per group of equal
+// filter size and all other kernels on each request's own stream.  A request
+// that arrives while others run joins at the next step, with its own iteration
+// count and epsilon schedule.  The scheduler keeps one step in flight ahead of
+// the device, so admissions take effect within about one step.  When a request
+// finishes, its images are copied to host memory and its budget share is
+// released at once; its plan is kept idle for the next request of the same
+// shape and evicted when the budget is needed.  A result depends only on the
+// request (the eigensolver is chosen by filter size alone), not on what runs
+// beside it.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <cstring>
 #include <condition_variable>
 #include <deque>
+#include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
+#include "engine.h"
 #include "plan.h"
 
 using namespace slrx;
@@ -52,6 +59,9 @@ struct Req {
 
 }  // namespace
 
+typedef std::tuple<int, int, int, int, int, int> ShapeKey;
+static ShapeKey key_of(const slrx_dims& d) { return ShapeKey(d.P, d.Q, d.T, d.N1, d.N2, d.M); }
+
 struct slrx_server {
   size_t budget = 0;
   int max_slots = 1;
@@ -60,10 +70,13 @@ struct slrx_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Req*> queue;
   std::unordered_map<uint64_t, Req*> reqs;
-  size_t used = 0;
+  size_t used = 0;          // footprint of admitted (running) requests
+  size_t pooled = 0;        // footprint of idle plans kept for reuse
+  std::multimap<ShapeKey, std::pair<slrx_plan*, size_t>> pool;  // idle server-owned plans
   uint64_t next_id = 1;
   bool stop = false;
-  std::vector<std::thread> workers;
+  std::thread scheduler;
+  BatchEig eig;  // used by the scheduler thread only
 };
 
 static void release_budget(slrx_server* s, Req* r) {
@@ -73,11 +86,32 @@ static void release_budget(slrx_server* s, Req* r) {
   }
 }
 
-// Pick the first queued request that fits the remaining budget (caller holds mu).
-static Req* take_admissible(slrx_server* s) {
+// Pick the first queued request that can run (caller holds mu): a server-owned
+// request takes an idle plan of its shape from the pool if there is one;
+// otherwise its footprint must fit the budget next to the running requests,
+// evicting idle plans of other shapes if needed.  Evicted plans are returned
+// through `evict` and destroyed by the caller outside the lock.
+static Req* take_admissible(slrx_server* s, std::vector<slrx_plan*>& evict) {
   for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
     Req* r = *it;
-    if (s->used + r->bytes <= s->budget) {
+    if (r->owned) {
+      auto pit = s->pool.find(key_of(r->dims));
+      if (pit != s->pool.end()) {
+        r->plan = pit->second.first;
+        s->pooled -= pit->second.second;
+        s->pool.erase(pit);
+        s->queue.erase(it);
+        return r;
+      }
+    }
+    if (s->used + r->bytes > s->budget) continue;
+    while (s->used + s->pooled + r->bytes > s->budget && !s->pool.empty()) {
+      auto victim = s->pool.begin();
+      evict.push_back(victim->second.first);
+      s->pooled -= victim->second.second;
+      s->pool.erase(victim);
+    }
+    if (s->used + s->pooled + r->bytes <= s->budget) {
       s->queue.erase(it);
       return r;
     }
@@ -85,23 +119,43 @@ static Req* take_admissible(slrx_server* s) {
   return nullptr;
 }
 
-static void run_request(slrx_server* s, Req* r) {
+// Bind a newly admitted request to its plan and start it on the engine.
+static slrx_status start_request(Req* r) {
   slrx_status st = SLRX_OK;
   if (r->owned) {
-    st = slrx_plan_create(&r->dims, &r->prm, nullptr, &r->plan);
+    if (r->plan) {  // reused idle plan of the same shape
+      st = slrx_set_params(r->plan, &r->prm);
+      if (st == SLRX_OK) st = slrx_clear_init(r->plan);
+    } else {
+      st = slrx_plan_create(&r->dims, &r->prm, nullptr, &r->plan);
+    }
     if (st == SLRX_OK) st = slrx_set_kspace(r->plan, r->b.data(), SLRX_MEM_HOST);
     if (st == SLRX_OK) st = slrx_set_mask(r->plan, r->S.data(), SLRX_MEM_HOST);
     std::vector<float2>().swap(r->b);
     std::vector<uint8_t>().swap(r->S);
+  } else if (r->plan->running && hipEventQuery(r->plan->ev_run[1]) == hipErrorNotReady) {
+    st = fail(SLRX_EBUSY, "plan is running");
+  } else if (r->plan->running) {
+    st = finish(r->plan);
   }
-  if (st == SLRX_OK) st = slrx_run(r->plan);
-  if (st == SLRX_OK) st = slrx_sync(r->plan);
+  if (st == SLRX_OK) st = engine_begin(r->plan);
+  return st;
+}
+
+// Results of a request whose last step has run on the device.
+static slrx_status collect_request(Req* r) {
+  slrx_status st = finish(r->plan);
   if (st == SLRX_OK && r->owned) {
     r->result.resize((size_t)r->dims.T * r->dims.P * r->dims.Q);
     st = slrx_get_images(r->plan, r->result.data(), SLRX_MEM_HOST);
   }
+  return st;
+}
+
+// Mark a request done, release its budget, keep its plan idle for reuse.
+static void complete_request(slrx_server* s, Req* r, slrx_status st) {
   std::string err = st != SLRX_OK ? std::string(slrx_last_error()) : std::string();
-  if (r->owned && r->plan) {
+  if (r->owned && r->plan && st != SLRX_OK) {
     slrx_plan_destroy(r->plan);
     r->plan = nullptr;
   }
@@ -111,30 +165,101 @@ static void run_request(slrx_server* s, Req* r) {
   r->t_done = now_s();
   r->state = 2;
   release_budget(s, r);
+  if (r->owned && r->plan) {
+    s->pool.emplace(key_of(r->dims), std::make_pair(r->plan, r->bytes));
+    s->pooled += r->bytes;
+    r->plan = nullptr;
+  }
   s->cv_done.notify_all();
-  s->cv_work.notify_all();
 }
 
-static void worker_main(slrx_server* s) {
+static void scheduler_main(slrx_server* s) {
   (void)hipSetDevice(s->device);
+  std::vector<Req*> active;     // requests with steps left
+  std::vector<Req*> finishing;  // last step enqueued, results not yet collected
   for (;;) {
-    Req* r = nullptr;
+    // 1. admission (blocks only when nothing is in flight)
+    std::vector<Req*> admitted;
+    std::vector<slrx_plan*> evict;
+    bool stopping = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stop || (r = take_admissible(s)) != nullptr; });
-      if (!r) return;  // stopping
-      s->used += r->bytes;
-      r->holds_budget = true;
-      r->state = 1;
-      r->t_admit = now_s();
+      for (;;) {
+        while (!s->stop && (int)(active.size() + admitted.size()) < s->max_slots) {
+          Req* r = take_admissible(s, evict);
+          if (!r) break;
+          s->used += r->bytes;
+          r->holds_budget = true;
+          r->state = 1;
+          r->t_admit = now_s();
+          admitted.push_back(r);
+        }
+        stopping = s->stop;
+        if (!admitted.empty() || !active.empty() || !finishing.empty() || stopping) break;
+        s->cv_work.wait(lk);
+      }
     }
-    run_request(s, r);
+    for (slrx_plan* p : evict) slrx_plan_destroy(p);
+    if (stopping && active.empty() && finishing.empty() && admitted.empty()) return;
+    for (Req* r : admitted) {
+      const slrx_status st = start_request(r);
+      if (st == SLRX_OK) active.push_back(r);
+      else complete_request(s, r, st);
+    }
+
+    // 2. one engine step over every active request
+    if (!active.empty()) {
+      std::vector<slrx_plan*> plans;
+      for (Req* r : active) plans.push_back(r->plan);
+      slrx_status st = engine_step(plans, s->eig);
+      for (Req* r : active) {
+        slrx_plan* pl = r->plan;
+        if (st == SLRX_OK && hipEventRecord(pl->ev_iter[(pl->it_next - 1) & 1], pl->stream) != hipSuccess)
+          st = fail(SLRX_EDEVICE, "hipEventRecord failed");
+      }
+      if (st != SLRX_OK) {  // device-side state of the step is unknown: fail every active request
+        for (Req* r : active) {
+          (void)hipStreamSynchronize(r->plan->stream);
+          r->plan->running = false;
+          complete_request(s, r, st);
+        }
+        active.clear();
+      }
+      // pacing: wait for the previous step of each request (one step stays queued)
+      for (Req* r : active) {
+        slrx_plan* pl = r->plan;
+        if (pl->it_next >= 2) (void)hipEventSynchronize(pl->ev_iter[(pl->it_next - 2) & 1]);
+      }
+      for (size_t i = 0; i < active.size();) {
+        Req* r = active[i];
+        if (r->plan->it_next >= r->plan->prm.n_irls) {
+          const slrx_status se = engine_end(r->plan);
+          if (se != SLRX_OK) complete_request(s, r, se);
+          else finishing.push_back(r);
+          active.erase(active.begin() + i);
+        } else {
+          ++i;
+        }
+      }
+    }
+
+    // 3. collect finished requests (wait for one only when nothing else is in flight)
+    for (size_t i = 0; i < finishing.size();) {
+      Req* r = finishing[i];
+      const bool must_wait = active.empty() && i == 0;
+      if (must_wait || hipEventQuery(r->plan->ev_run[1]) != hipErrorNotReady) {
+        complete_request(s, r, collect_request(r));
+        finishing.erase(finishing.begin() + i);
+      } else {
+        ++i;
+      }
+    }
   }
 }
 
 extern "C" slrx_status slrx_server_create(size_t budget_bytes, int32_t max_slots, void* hip_stream,
                                           slrx_server** out) {
-  (void)hip_stream;  // every slot runs on a stream of its own
+  (void)hip_stream;  // every request runs on a stream of its own
   if (!out) return fail(SLRX_EINVAL, "out is NULL");
   *out = nullptr;
   if (budget_bytes == 0) return fail(SLRX_EINVAL, "budget must be > 0");
@@ -145,7 +270,7 @@ extern "C" slrx_status slrx_server_create(size_t budget_bytes, int32_t max_slots
   s->budget = budget_bytes;
   s->max_slots = max_slots;
   s->device = dev;
-  for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(worker_main, s);
+  s->scheduler = std::thread(scheduler_main, s);
   *out = s;
   return SLRX_OK;
 }
@@ -164,7 +289,8 @@ extern "C" void slrx_server_destroy(slrx_server* s) {
     s->queue.clear();
   }
   s->cv_work.notify_all();
-  for (auto& t : s->workers) t.join();
+  if (s->scheduler.joinable()) s->scheduler.join();
+  for (auto& kv : s->pool) slrx_plan_destroy(kv.second.first);
   for (auto& kv : s->reqs) {
     Req* r = kv.second;
     if (r->owned && r->plan) slrx_plan_destroy(r->plan);
@@ -261,7 +387,7 @@ extern "C" slrx_status slrx_get_request_info(slrx_server* s, uint64_t ticket, sl
 extern "C" slrx_status slrx_server_usage(slrx_server* s, size_t* used, int32_t* queued) {
   if (!s) return fail(SLRX_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
-  if (used) *used = s->used;
+  if (used) *used = s->used + s->pooled;
   if (queued) *queued = (int32_t)s->queue.size();
   return SLRX_OK;
 }

@@ -69,7 +69,7 @@ slrx_status slrx::images(slrx_plan* pl) { return fft2(pl, pl->x, pl->img, +1, nu
 // Gram matrix of the current iterate: row-major into Aw for the own
 // tridiagonalisation, column-major into Rm for rocSOLVER zheevd (or when
 // colmajor is forced, for the single-step entry point).
-slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor) {
+slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor, double2* R_out) {
   const slrx_dims& d = pl->d;
   KTimer kt(pl, SLRX_K_GRAM);
   STCHK(images(pl));
@@ -79,7 +79,7 @@ slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor) {
   ga.c1 = pl->c1;
   ga.g = pl->g;
   const bool lib = pl->lib_eigh() || colmajor;
-  ga.R = lib ? pl->Rm : pl->Aw;
+  ga.R = R_out ? R_out : (lib ? pl->Rm : pl->Aw);
   ga.rowmajor = lib ? 0 : 1;
   ga.twP = pl->twPd;
   ga.twQ = pl->twQd;
@@ -124,13 +124,14 @@ slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
 }
 
 // Weights, filter product and masks from the eigenpairs in lam / Rm.
-slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma) {
+slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma, const double2* U,
+                               const double* lamv) {
   const slrx_dims& d = pl->d;
   const int s = d.N1 * d.N2 * d.M;
   WeightArgs wa{};
   wa.s = s;
-  wa.lamv = pl->lam;
-  wa.U = pl->lib_eigh() ? pl->Rm : pl->UZ;
+  wa.lamv = lamv ? lamv : pl->lam;
+  wa.U = U ? U : (pl->lib_eigh() ? pl->Rm : pl->UZ);
   wa.VT = pl->VT;
   wa.eps = pl->scal;
   wa.lam_max_out = it >= 0 ? pl->stats + SLRX_MAX_IRLS + it : nullptr;
