@@ -183,6 +183,7 @@ static Layout plan_layout(const slrx_dims& d) {
   sz[B_TAU] = s * 16;
   sz[B_TRIV] = 2 * s * 16;
   sz[B_TRIP] = 2 * s * 16;
+  sz[B_BTS] = bt_scratch_elems(s) * 16;
   Layout L;
   size_t o = 0;
   for (int i = 0; i < kNumBuf; ++i) {
@@ -236,9 +237,6 @@ static slrx_status setup_eigensolver(slrx_plan* pl) {
                    (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework, pl->info);
   rocsolver_zstedc(pl->blas, rocblas_evect_tridiagonal, s, pl->lam, pl->ework, (rocblas_double_complex*)pl->UZ,
                    s, pl->info);
-  rocsolver_zunmtr(pl->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, s, s,
-                   (rocblas_double_complex*)pl->Rm, s, (rocblas_double_complex*)pl->tau,
-                   (rocblas_double_complex*)pl->UZ, s);
   rocblas_stop_device_memory_size_query(pl->blas, &ws);
   if (ws < 1024) ws = 1024;
   if (hipMalloc(&pl->blas_ws, ws) != hipSuccess) return fail(SLRX_ENOMEM, "eigensolver workspace (%zu bytes)", ws);
@@ -289,6 +287,7 @@ static void assign_buffers(slrx_plan* pl, const Layout& L) {
   pl->tau = (double2*)at(B_TAU);
   pl->triv = (double2*)at(B_TRIV);
   pl->trip = (double2*)at(B_TRIP);
+  pl->bts = (double2*)at(B_BTS);
 }
 
 extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params* params, void* hip_stream,

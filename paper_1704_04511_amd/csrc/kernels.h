@@ -135,6 +135,18 @@ struct TriArgs {
 hipError_t launch_tridiag(const TriArgs& a, int nbatch, hipStream_t s);
 int tri_max_n();
 
+// U = Q Z from the reflectors of launch_tridiag (all column-major n x n).
+struct BackTrArgs {
+  int n;
+  double2* V;           // reflectors as stored by launch_tridiag; made explicit in place
+  double2* Y;           // workspace, n x n
+  double2* Z;           // in: tridiagonal eigenvectors; out: eigenvectors of the Hermitian matrix
+  const double2* tau;   // n
+  double2* scratch;     // bt_scratch_elems(n)
+};
+hipError_t launch_backtransform(const BackTrArgs& a, hipStream_t s);
+size_t bt_scratch_elems(int n);
+
 // H = V V^H on FP64 MFMA: Hre, Him row-major s x s.
 hipError_t launch_filter_product(int s, const double* VT, double* Hre, double* Him, hipStream_t st);
 

@@ -17,7 +17,7 @@ enum Buf {
   B_TWPF, B_TWQF, B_TWPD, B_TWQD,
   B_C1, B_G, B_RM, B_LAM, B_EWORK, B_VT, B_HRE, B_HIM, B_WSUM, B_S1,
   B_PARTA, B_PARTB, B_RRH, B_SCAL, B_STATS, B_INFO, B_FLAG,
-  B_AW, B_UZ, B_TAU, B_TRIV, B_TRIP,
+  B_AW, B_UZ, B_TAU, B_TRIV, B_TRIP, B_BTS,
   kNumBuf
 };
 
@@ -47,6 +47,7 @@ struct slrx_plan {
   double *lam = nullptr, *ework = nullptr, *VT = nullptr, *Hre = nullptr, *Him = nullptr;
   double2 *wsum = nullptr, *s1 = nullptr;
   double2 *Aw = nullptr, *UZ = nullptr, *tau = nullptr, *triv = nullptr, *trip = nullptr;
+  double2* bts = nullptr;  // back-transformation scratch
   double *partA = nullptr, *partB = nullptr, *rr_hist = nullptr, *scal = nullptr, *stats = nullptr;
   rocblas_int* info = nullptr;
   int* flag = nullptr;

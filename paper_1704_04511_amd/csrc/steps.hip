@@ -88,8 +88,9 @@ slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor, double2* R_out) {
 }
 
 // Eigen-decomposition of the Gram matrix: own Householder tridiagonalisation,
-// rocSOLVER divide-and-conquer on the tridiagonal and back-transformation
-// (eigenvectors into UZ); or rocSOLVER zheevd on Rm (SLRX_FLAG_LIBEIGH).
+// rocSOLVER divide-and-conquer on the real tridiagonal, own blocked
+// back-transformation (eigenvectors into UZ); or rocSOLVER zheevd on Rm
+// (SLRX_FLAG_LIBEIGH).
 slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
   const int s = pl->s();
   rocblas_int* info = pl->info + (it < 0 ? SLRX_MAX_IRLS : it);
@@ -116,10 +117,14 @@ slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
   rocblas_status rs = rocsolver_zstedc(pl->blas, rocblas_evect_tridiagonal, s, pl->lam, pl->ework,
                                        (rocblas_double_complex*)pl->UZ, s, info);
   if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zstedc failed (status %d)", (int)rs);
-  rs = rocsolver_zunmtr(pl->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, s, s,
-                        (rocblas_double_complex*)pl->Rm, s, (rocblas_double_complex*)pl->tau,
-                        (rocblas_double_complex*)pl->UZ, s);
-  if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zunmtr failed (status %d)", (int)rs);
+  BackTrArgs bt{};
+  bt.n = s;
+  bt.V = pl->Rm;
+  bt.Y = pl->Aw;  // free once the reduction is done
+  bt.Z = pl->UZ;
+  bt.tau = pl->tau;
+  bt.scratch = pl->bts;
+  HIPCHK(launch_backtransform(bt, pl->stream));
   return SLRX_OK;
 }
 
