@@ -5,8 +5,9 @@ FP64 eigen-decomposition, weights, filter product, masks, CG) of the
 256 x 256 x 20-echo workload with filter 15 x 15 x 5, 20 outer x 15 CG
 iterations, on seeded synthetic data already resident in HBM.
 
-Prints one JSON line: IRLS iterations/s, the HBM roofline of the dominant
-hand-written kernel (algorithmic bytes per launch / measured launch time), and
+Prints one JSON line: IRLS iterations/s, the roofline of the dominant
+hand-written kernel (algorithmic bytes or flops per launch / measured launch
+time, HIP events on the plan's stream), and
 the FP64 CPU oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
@@ -53,21 +54,46 @@ def algorithmic_bytes(kind: str, T: int, P: int, Q: int, M: int, N1: int, N2: in
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix
 
 
+def tri_bytes(n: int) -> float:
+    """Bytes of one Householder tridiagonalisation (n launches): launch k reads and
+    writes the trailing block ((n-k-1)^2 complex128 each way) and moves five
+    vectors of length n-k (row k, v and p in; v and p out)."""
+    return float(sum(16 * (2 * (n - k - 1) ** 2 + 5 * (n - k)) for k in range(n)))
+
+
+def backtr_flop(n: int, nb: int = 64) -> float:
+    """Flops of the blocked back-transformation (complex MAC = 8 flop): per block
+    of nr reflectors acting on m = n - nb g - 1 rows, V^H V and V T (nr^2 m each),
+    then V^H Z and Z - Y W (nr m n each)."""
+    tot = 0.0
+    for g in range((n - 2) // nb + 1 if n > 1 else 0):
+        nr = min(nb, n - 1 - nb * g)
+        m = n - nb * g - 1
+        tot += 8.0 * (2 * nr * nr * m + 2 * nr * m * n)
+    return tot
+
+
 def roofline(kind, avg_ms, T, P, Q, M, N1, N2):
-    """Roofline entry of one kernel class: the filter product is an FP64 MFMA
-    contraction (8 s^3 flop per launch); every other class is bound by HBM."""
-    if kind == "filter":
-        s = N1 * N2 * M
-        flop = 8.0 * s ** 3
+    """Roofline entry of one kernel class.  The filter product and the
+    back-transformation are FP64 MFMA contractions; the tridiagonalisation is
+    reported per launch (one launch per column) against HBM; every other class is
+    bound by HBM."""
+    s = N1 * N2 * M
+    if kind in ("filter", "backtr"):
+        flop = 8.0 * s ** 3 if kind == "filter" else backtr_flop(s)
         ach = flop / (avg_ms * 1e-3) / 1e12
         return {"bound": "mfma", "kernel": kind, "achieved": round(ach, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
                 "flop_per_launch": flop, "avg_launch_ms": round(avg_ms, 5)}
-    nbytes = algorithmic_bytes(kind, T, P, Q, M, N1, N2)
+    if kind == "tri":  # per column launch
+        nbytes = tri_bytes(s) / s
+        avg_ms = avg_ms / s
+    else:
+        nbytes = algorithmic_bytes(kind, T, P, Q, M, N1, N2)
     ach = nbytes / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": kind, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes,
-            "avg_launch_ms": round(avg_ms, 5)}
+            "avg_launch_ms": round(avg_ms, 6)}
 
 
 def measured_traffic(kind: str):
@@ -159,15 +185,18 @@ def bench_batch(args) -> int:
         "batch_vs_single_run_max_nrmse": float(f"{seq_nrmse:.3e}"),
     }
     if not args.no_cpu_baseline:
-        pb = pbs[0]
+        # whole slices of the same batch through the oracle until about 10 s have passed
         cores = len(os.sched_getaffinity(0))
         t0 = time.perf_counter()
-        oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, 1, pb.n_cg)
+        done = 0
+        while done < len(pbs) and time.perf_counter() - t0 < 10.0:
+            pb = pbs[done]
+            oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, pb.n_irls, pb.n_cg)
+            done += 1
         dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": 1.0 / (dt * pb.n_irls), "unit": "slices/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": f"1 of 15 outer iterations of slice 0 ({pb.b.shape}), {dt:.1f} s wall, "
-                                         "scaled to a whole slice"}
+        out["cpu_baseline"] = {"value": done / dt, "unit": "slices/s", "cores": cores, "kind": "oracle",
+                               "sample": f"slices 0..{done - 1} of the same batch, whole (all outer "
+                                         f"iterations), NumPy/SciPy FP64, {dt:.1f} s wall"}
     for pl in plans:
         pl.close()
     print(json.dumps(out))
@@ -246,7 +275,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-outer", type=int, default=1)
+    ap.add_argument("--cpu-outer", type=int, default=3, help="outer iterations in the CPU oracle sample")
     ap.add_argument("--n-irls", type=int, default=None,
                     help="override the outer iteration count (profiling runs only; changes the workload)")
     ap.add_argument("--workload", choices=("c3", "batch", "serve"), default="c3",
@@ -296,7 +325,7 @@ def main() -> int:
     value = pb.n_irls * args.steps / dt
 
     kms, kcnt = st["kernel_ms"], st["kernel_count"]
-    own = [k for k in ("rows", "cols", "fin", "update", "gram", "filter", "masks") if kcnt[k] > 0]
+    own = [k for k in ("rows", "cols", "fin", "update", "gram", "tri", "backtr", "filter", "masks") if kcnt[k] > 0]
     dom = max(own, key=lambda k: kms[k])
     roofs = {k: roofline(k, kms[k] / kcnt[k], T, P, Q, pb.M, pb.N1, pb.N2) for k in own}
     for k in own:

@@ -89,10 +89,13 @@ enum {
   SLRX_K_FIN = 2,     /* inverse row pass + penalty G + combine + dot */
   SLRX_K_UPDATE = 3,  /* CG vector update + residual norm */
   SLRX_K_GRAM = 4,    /* Gram matrix (lagged products, pruned DFT, window) */
-  SLRX_K_EIGH = 5,    /* FP64 Hermitian eigen-decomposition */
-  SLRX_K_FILTER = 6,  /* weights + filter product H = U diag(alpha) U^H */
-  SLRX_K_MASKS = 7,   /* diagonal sums + mask synthesis */
-  SLRX_K_NCLASS = 8
+  SLRX_K_TRI = 5,     /* Householder tridiagonalisation (one launch per column) */
+  SLRX_K_TDEIG = 6,   /* eigenpairs of the real tridiagonal (rocSOLVER zstedc), or the
+                         whole library eigen-decomposition with SLRX_FLAG_LIBEIGH */
+  SLRX_K_BACKTR = 7,  /* blocked back-transformation U = Q Z */
+  SLRX_K_FILTER = 8,  /* weights + filter product H = U diag(alpha) U^H */
+  SLRX_K_MASKS = 9,   /* diagonal sums + mask synthesis */
+  SLRX_K_NCLASS = 10
 };
 
 /* Per-run statistics, filled by slrx_get_stats after a completed run. */
@@ -104,8 +107,8 @@ typedef struct {
   double cg_rr_final[SLRX_MAX_IRLS];/* squared CG residual norm after each LS step */
   double ms_total;                  /* device time of the whole run (ms) */
   double ms_gram, ms_eigh, ms_weights, ms_cg; /* per phase, SLRX_FLAG_TIMING */
-  double kt_ms[SLRX_K_NCLASS];      /* summed launch durations per class, SLRX_FLAG_KTIME */
-  int32_t kt_count[SLRX_K_NCLASS];  /* launches per class */
+  double kt_ms[16];      /* summed durations per class (index SLRX_K_*), SLRX_FLAG_KTIME */
+  int32_t kt_count[16];  /* timed regions per class (a region may hold several launches) */
 } slrx_stats;
 
 typedef struct slrx_plan slrx_plan;

@@ -36,7 +36,7 @@ SLRX_FLAG_TIMING = 1
 SLRX_FLAG_KTIME = 2
 SLRX_FLAG_LIBEIGH = 4
 MAX_IRLS = 256
-KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "eigh", "filter", "masks")
+KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "tri", "tdeig", "backtr", "filter", "masks")
 
 STATUS = {0: "SLRX_OK", -1: "SLRX_EINVAL", -2: "SLRX_ENOMEM", -3: "SLRX_EDEVICE", -4: "SLRX_ESTATE",
           -5: "SLRX_ENUMERIC", -6: "SLRX_EBUSY", -7: "SLRX_ENOTREADY"}
@@ -67,7 +67,7 @@ class Stats(ctypes.Structure):
                 ("cg_rr_final", ctypes.c_double * MAX_IRLS),
                 ("ms_total", ctypes.c_double), ("ms_gram", ctypes.c_double), ("ms_eigh", ctypes.c_double),
                 ("ms_weights", ctypes.c_double), ("ms_cg", ctypes.c_double),
-                ("kt_ms", ctypes.c_double * 8), ("kt_count", ctypes.c_int32 * 8)]
+                ("kt_ms", ctypes.c_double * 16), ("kt_count", ctypes.c_int32 * 16)]
 
     def as_dict(self) -> dict:
         n = self.n_irls_done

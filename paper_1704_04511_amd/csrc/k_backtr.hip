@@ -34,7 +34,7 @@ enum BtKind { BT_GRAM = 0, BT_YMAT = 1, BT_APPLY_W = 2, BT_APPLY_Z = 3 };
 //   GRAM:    G_g = V_g^H V_g        (nr x nr, K = m), partial z -> Gp[(z * ng + g) nb^2]
 //   YMAT:    Y_g = V_g T_g          (m x nr, K = nr)  -> Yx, column-major n x n, rows r0..
 //   APPLY_W: W   = V_g^H Z(r0:, :)  (nr x n, K = m),  partial z -> Wp[z nb n]
-//   APPLY_Z: Z(r0:, :) -= Y_g W     (m x n, K = nr),  W summed over the partials.
+//   APPLY_Z: Z(r0:, :) -= Y_g W     (m x n, K = nr),  W = the partials summed (k_bt_wsum).
 struct BtArgs {
   int n, ng, nsplit, g;
   const double2* Vx;  // reflectors, column-major n x n, explicit zeros and unit entries
@@ -79,52 +79,68 @@ __global__ __launch_bounds__(256) void k_bt_gemm(BtArgs a) {
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   v4d accR = v4d{0.0, 0.0, 0.0, 0.0}, accI = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int kc = kb; kc < ke; kc += kKC) {
-    // A tile: rows i0.., k kc..
-    for (int e = tid; e < kTM * kKC; e += 256) {
-      int i, kk;
+  // global loads of one K chunk into registers (4 A elements and 1 B element per thread)
+  constexpr int kAE = kTM * kKC / 256;
+  double2 ra[kAE], rb;
+  auto load_chunk = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < kAE; ++u) {
+      const int e = tid + 256 * u;
       double2 v = make_double2(0.0, 0.0);
       if (KIND == BT_GRAM || KIND == BT_APPLY_W) {  // A(i, r) = conj(V(r0 + r, k0 + i))
-        i = e / kKC;
-        kk = e % kKC;
-        const int r = kc + kk;
+        const int i = e / kKC, r = kc + e % kKC;
         if (i0 + i < M && r < ke) {
           v = a.Vx[(long)(r0 + r) + (long)(k0 + i0 + i) * n];
           v.y = -v.y;
         }
       } else {  // A(r, l) column-major: V for YMAT, Y for APPLY_Z
-        kk = e / kTM;
-        i = e % kTM;
-        const int l = kc + kk;
+        const int i = e % kTM, l = kc + e / kTM;
         if (i0 + i < M && l < ke) {
           const double2* src = KIND == BT_YMAT ? a.Vx : a.Yx;
           v = src[(long)(r0 + i0 + i) + (long)(k0 + l) * n];
         }
       }
-      Lar[kk][i] = v.x;
-      Lai[kk][i] = v.y;
+      ra[u] = v;
     }
-    // B tile: k kc.., columns j0..
-    {
-      const int j = tid / kKC, kk = tid % kKC;
-      const int k = kc + kk, c = j0 + j;
-      double2 v = make_double2(0.0, 0.0);
-      if (k < ke && c < N) {
-        if (KIND == BT_GRAM) v = a.Vx[(long)(r0 + k) + (long)(k0 + c) * n];
-        else if (KIND == BT_YMAT) v = a.Tb[(long)g * kBtNb * kBtNb + k + (long)c * kBtNb];
-        else if (KIND == BT_APPLY_W) v = a.Z[(long)(r0 + k) + (long)c * n];
-        else {
-          for (int p = 0; p < a.nsplit; ++p) {
-            const double2 w = a.Wp[(long)p * kBtNb * n + k + (long)c * kBtNb];
-            v.x += w.x;
-            v.y += w.y;
-          }
-        }
+    const int j = tid / kKC, k = kc + tid % kKC, c = j0 + j;
+    rb = make_double2(0.0, 0.0);
+    if (k < ke && c < N) {
+      if (KIND == BT_GRAM) rb = a.Vx[(long)(r0 + k) + (long)(k0 + c) * n];
+      else if (KIND == BT_YMAT) rb = a.Tb[(long)g * kBtNb * kBtNb + k + (long)c * kBtNb];
+      else if (KIND == BT_APPLY_W) rb = a.Z[(long)(r0 + k) + (long)c * n];
+      else rb = a.Wp[(long)a.nsplit * kBtNb * n + k + (long)c * kBtNb];  // summed W
+    }
+  };
+  // APPLY_Z: this lane's Z elements, loaded before the product
+  double2 zold[4];
+  if (KIND == BT_APPLY_Z) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + wave * 16 + (lane >> 4) + 4 * v;
+      const int c = j0 + (lane & 15);
+      zold[v] = (i < M && c < N) ? a.Z[(long)(r0 + i) + (long)c * n] : make_double2(0.0, 0.0);
+    }
+  }
+  if (kb < ke) load_chunk(kb);
+  for (int kc = kb; kc < ke; kc += kKC) {
+#pragma unroll
+    for (int u = 0; u < kAE; ++u) {
+      const int e = tid + 256 * u;
+      int i, kk;
+      if (KIND == BT_GRAM || KIND == BT_APPLY_W) {
+        i = e / kKC;
+        kk = e % kKC;
+      } else {
+        kk = e / kTM;
+        i = e % kTM;
       }
-      Lbr[kk][j] = v.x;
-      Lbi[kk][j] = v.y;
+      Lar[kk][i] = ra[u].x;
+      Lai[kk][i] = ra[u].y;
     }
+    Lbr[tid % kKC][tid / kKC] = rb.x;
+    Lbi[tid % kKC][tid / kKC] = rb.y;
     __syncthreads();
+    if (kc + kKC < ke) load_chunk(kc + kKC);  // next chunk in flight during the products
 #pragma unroll
     for (int kq = 0; kq < kKC; kq += 4) {
       const int kl = kq + (lane >> 4);
@@ -153,10 +169,24 @@ __global__ __launch_bounds__(256) void k_bt_gemm(BtArgs a) {
     } else if (KIND == BT_APPLY_W) {
       a.Wp[(long)z * kBtNb * n + i + (long)c * kBtNb] = r;
     } else {
-      double2* dst = a.Z + (long)(r0 + i) + (long)c * n;
-      *dst = make_double2(dst->x - r.x, dst->y - r.y);
+      a.Z[(long)(r0 + i) + (long)c * n] = make_double2(zold[v].x - r.x, zold[v].y - r.y);
     }
   }
+}
+
+// W = sum of the split-K partials of V^H Z, in a fixed order, into the slot
+// after the partials.
+__global__ void k_bt_wsum(BtArgs a) {
+  const long o = (long)blockIdx.x * 256 + threadIdx.x;
+  const long len = (long)kBtNb * a.n;
+  if (o >= len) return;
+  double2 v = make_double2(0.0, 0.0);
+  for (int p = 0; p < a.nsplit; ++p) {
+    const double2 w = a.Wp[(long)p * len + o];
+    v.x += w.x;
+    v.y += w.y;
+  }
+  a.Wp[(long)a.nsplit * len + o] = v;
 }
 
 // Reflectors in explicit form, in place: column k of the n x n column-major
@@ -169,37 +199,84 @@ __global__ void k_bt_explicit(int n, double2* V) {
   else if (R == k + 1) V[o] = make_double2(1.0, 0.0);
 }
 
-// T of each block from its Gram matrix (summed over the partials) and tau.
-// T is upper triangular, kept packed by columns in LDS: T(l, q) at q(q+1)/2 + l.
-__global__ __launch_bounds__(64) void k_bt_tmat(BtArgs a, const double2* tau) {
+// T of each block by recursive doubling: for adjacent index blocks A, B (B after
+// A), the product of their block reflectors has T = [T_A, -T_A G_AB T_B; 0, T_B]
+// with G_AB = V_A^H V_B; blocks of 1, 2, 4, .., 32 are joined level by level,
+// every entry of a level in parallel.  T is packed by columns (T(l, q) at
+// q(q+1)/2 + l, l <= q); G's strict upper triangle likewise (l < i at
+// i(i-1)/2 + l) and is overwritten level by level with X = G_AB T_B.  Indices
+// beyond the block's reflectors get tau = 0 and G = 0, so their rows and
+// columns of T are zero.
+__global__ __launch_bounds__(256) void k_bt_tmat(BtArgs a, const double2* tau) {
   __shared__ double2 T[kBtNb * (kBtNb + 1) / 2];
-  __shared__ double2 t[kBtNb];
-  const int g = blockIdx.x, l = threadIdx.x;
+  __shared__ double2 G[kBtNb * (kBtNb - 1) / 2];
+  const int g = blockIdx.x, tid = threadIdx.x;
   const int k0 = kBtNb * g, nr = min(kBtNb, a.n - 1 - k0);
-  for (int i = 0; i < nr; ++i) {
-    const double2 ti = tau[k0 + i];
-    if (l < i) {
-      double2 gsum = make_double2(0.0, 0.0);
+  auto tix = [](int l, int q) { return q * (q + 1) / 2 + l; };
+  auto gix = [](int l, int i) { return i * (i - 1) / 2 + l; };
+  for (int e = tid; e < kBtNb * (kBtNb - 1) / 2; e += 256) {
+    int i = 1;
+    while ((i + 1) * i / 2 <= e) ++i;  // e = i(i-1)/2 + l, l < i
+    const int l = e - i * (i - 1) / 2;
+    double2 gsum = make_double2(0.0, 0.0);
+    if (i < nr)
       for (int p = 0; p < a.nsplit; ++p) {
         const double2 gv = a.Gp[((long)p * a.ng + g) * kBtNb * kBtNb + l + (long)i * kBtNb];
         gsum.x += gv.x;
         gsum.y += gv.y;
       }
-      // t_l = -tau_i (v_l^H v_i)
-      t[l] = make_double2(-(ti.x * gsum.x - ti.y * gsum.y), -(ti.x * gsum.y + ti.y * gsum.x));
+    G[e] = gsum;
+  }
+  for (int e = tid; e < kBtNb * (kBtNb + 1) / 2; e += 256) T[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  if (tid < nr) T[tix(tid, tid)] = tau[k0 + tid];
+  __syncthreads();
+  for (int bs = 1; bs < kBtNb; bs *= 2) {
+    const int per_pair = bs * bs, total = (kBtNb / (2 * bs)) * per_pair;  // = 32 bs <= 1024
+    double2 x[4];
+    // X(p, c) = sum_{q in B, q <= c} G(p, q) T(q, c), p in A, c in B
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
+      x[u] = make_double2(0.0, 0.0);
+      if (e < total) {
+        const int pr = e / per_pair, r = e % per_pair;
+        const int a0 = 2 * bs * pr, b0 = a0 + bs;
+        const int p = a0 + r / bs, c = b0 + r % bs;
+        for (int q = b0; q <= c; ++q) x[u] = dadd(x[u], dmul(G[gix(p, q)], T[tix(q, c)]));
+      }
     }
     __syncthreads();
-    if (l < i) {
-      double2 acc = make_double2(0.0, 0.0);
-      for (int q = l; q < i; ++q) acc = dadd(acc, dmul(T[q * (q + 1) / 2 + l], t[q]));
-      T[i * (i + 1) / 2 + l] = acc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
+      if (e < total) {
+        const int pr = e / per_pair, r = e % per_pair;
+        const int a0 = 2 * bs * pr, b0 = a0 + bs;
+        G[gix(a0 + r / bs, b0 + r % bs)] = x[u];
+      }
     }
-    if (l == i) T[i * (i + 1) / 2 + i] = ti;
+    __syncthreads();
+    // T(r, c) = -sum_{p in A, p >= r} T(r, p) X(p, c), r in A, c in B
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
+      if (e < total) {
+        const int pr = e / per_pair, rr = e % per_pair;
+        const int a0 = 2 * bs * pr, b0 = a0 + bs;
+        const int r = a0 + rr / bs, c = b0 + rr % bs;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int p = r; p < b0; ++p) acc = dadd(acc, dmul(T[tix(r, p)], G[gix(p, c)]));
+        T[tix(r, c)] = make_double2(-acc.x, -acc.y);
+      }
+    }
     __syncthreads();
   }
   double2* out = a.Tb + (long)g * kBtNb * kBtNb;
-  for (int c = 0; c < kBtNb; ++c)
-    out[l + (long)c * kBtNb] = (l <= c && c < nr) ? T[c * (c + 1) / 2 + l] : make_double2(0.0, 0.0);
+  for (int e = tid; e < kBtNb * kBtNb; e += 256) {
+    const int r = e % kBtNb, c = e / kBtNb;
+    out[e] = r <= c ? T[tix(r, c)] : make_double2(0.0, 0.0);
+  }
 }
 
 }  // namespace
@@ -208,7 +285,7 @@ static int bt_nblocks(int n) { return n > 1 ? (n - 2) / kBtNb + 1 : 0; }
 
 size_t bt_scratch_elems(int n) {
   const int ng = bt_nblocks(n);
-  return (size_t)ng * kBtNb * kBtNb * (1 + kBtSplitG) + (size_t)kBtSplitW * kBtNb * n;
+  return (size_t)ng * kBtNb * kBtNb * (1 + kBtSplitG) + (size_t)(kBtSplitW + 1) * kBtNb * n;
 }
 
 hipError_t launch_backtransform(const BackTrArgs& b, hipStream_t s) {
@@ -228,7 +305,7 @@ hipError_t launch_backtransform(const BackTrArgs& b, hipStream_t s) {
   const int mt = (n - 1 + kTM - 1) / kTM;  // row tiles of the largest block (m = n - 1)
   a.nsplit = kBtSplitG;
   k_bt_gemm<BT_GRAM><<<dim3(kBtNb / kTN, 1, ng * kBtSplitG), 256, 0, s>>>(a);
-  k_bt_tmat<<<ng, 64, 0, s>>>(a, b.tau);
+  k_bt_tmat<<<ng, 256, 0, s>>>(a, b.tau);
   a.nsplit = 1;
   k_bt_gemm<BT_YMAT><<<dim3(kBtNb / kTN, mt, ng), 256, 0, s>>>(a);
   const int nt = (n + kTN - 1) / kTN;
@@ -237,6 +314,7 @@ hipError_t launch_backtransform(const BackTrArgs& b, hipStream_t s) {
     a.g = g;
     const int m = n - (kBtNb * g + 1);
     k_bt_gemm<BT_APPLY_W><<<dim3(nt, 1, kBtSplitW), 256, 0, s>>>(a);
+    k_bt_wsum<<<(unsigned)(((long)kBtNb * n + 255) / 256), 256, 0, s>>>(a);
     k_bt_gemm<BT_APPLY_Z><<<dim3(nt, (m + kTM - 1) / kTM, 1), 256, 0, s>>>(a);
   }
   return hipGetLastError();

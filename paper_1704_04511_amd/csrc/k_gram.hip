@@ -201,13 +201,28 @@ hipError_t launch_weights(const WeightArgs& a, hipStream_t s) {
 // i.e. [Hre; Him] = [A; B] A^T with B = [Im; -Re] (real form of V V^H).
 // Block: 64 x 64 output tile, 4 waves in 2 x 2, each 32 x 32 = 2 x 2 MFMA
 // 16x16x4 f64 tiles; K staged through LDS in chunks of 16.
+// Only tiles on or above the diagonal are computed (Hre is symmetric, Him
+// antisymmetric); an off-diagonal tile is also stored mirrored.  Workgroups are
+// dispatched to the XCDs in turn, so consecutive tiles of the row-major tile
+// order are given to the same XCD (its L2 then holds the shared row panel).
 __global__ __launch_bounds__(256) void k_filter_product(int s, const double* __restrict__ VT,
                                                         double* __restrict__ Hre, double* __restrict__ Him) {
-  constexpr int TB = 64, KC = 16;
+  constexpr int TB = 64, KC = 16, NXCD = 8;
   __shared__ double Lre[KC][TB];
   __shared__ double Lim[KC][TB];
   __shared__ double Rt[KC][TB];
-  const int i0 = blockIdx.y * TB, j0 = blockIdx.x * TB;
+  const int nt = (s + TB - 1) / TB;
+  const int ntiles = nt * (nt + 1) / 2;
+  const int per = (ntiles + NXCD - 1) / NXCD;
+  const int lin = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+  if (lin >= ntiles) return;
+  int bi = 0, rem = lin;
+  while (rem >= nt - bi) {
+    rem -= nt - bi;
+    ++bi;
+  }
+  const int bj = bi + rem;
+  const int i0 = bi * TB, j0 = bj * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   const int K = 2 * s;
@@ -269,12 +284,17 @@ __global__ __launch_bounds__(256) void k_filter_product(int s, const double* __r
         if (ii < s && jj < s) {
           Hre[(long)ii * s + jj] = accR[a][b][v];
           Him[(long)ii * s + jj] = accI[a][b][v];
+          if (bi != bj) {
+            Hre[(long)jj * s + ii] = accR[a][b][v];
+            Him[(long)jj * s + ii] = -accI[a][b][v];
+          }
         }
       }
 }
 
 hipError_t launch_filter_product(int s, const double* VT, double* Hre, double* Him, hipStream_t st) {
-  dim3 grid((s + 63) / 64, (s + 63) / 64);
+  const int nt = (s + 63) / 64, ntiles = nt * (nt + 1) / 2;
+  const int grid = (ntiles + 7) / 8 * 8;  // whole rounds over the 8 XCDs
   k_filter_product<<<grid, 256, 0, st>>>(s, VT, Hre, Him);
   return hipGetLastError();
 }

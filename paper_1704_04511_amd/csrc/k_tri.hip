@@ -24,7 +24,8 @@ namespace slrx {
 
 constexpr int kTriNT = 256;
 constexpr int kTriRows = 4;  // rows of the trailing block per workgroup: one per wave
-constexpr int kTriUnroll = 4;  // row elements in flight per lane
+constexpr int kTriUnroll = 4;  // row elements in flight per lane beyond the prefetched part
+constexpr int kTriCrit = 5;    // elements of row k / v / p per thread loaded up front
 
 SLRX_DEV double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 SLRX_DEV double2 dscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
@@ -49,6 +50,10 @@ SLRX_DEV double2 block_sum2(double2 v, double2* red) {
   return v;
 }
 
+// NU: row elements per lane loaded at kernel entry (the whole row when the
+// trailing block is at most 64 NU wide), so the row's load latency overlaps
+// the reflector computation.
+template <int NU>
 __global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
   extern __shared__ double2 sm[];
   __shared__ double2 red[kTriNT / 64 + 1];
@@ -62,52 +67,53 @@ __global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool pending = k > 0;
 
-  // 0. issue every independent global load first: the first elements of this
-  //    wave's row of the trailing block, and v_{k-1}, p_{k-1}, row k.
+  // 0. issue every independent global load first: v_{k-1}, p_{k-1} and row k
+  //    (needed at once), then this wave's row of the trailing block (needed last).
   const int my_row = k + 1 + blockIdx.x * kTriRows + wave;  // one row per wave
   const bool has_row = my_row < n;
   double2* row = Aw + (size_t)(has_row ? my_row : 0) * n;
-  double2 xpre[kTriUnroll];
-#pragma unroll
-  for (int u = 0; u < kTriUnroll; ++u) {
-    const int j = k + 1 + lane + 64 * u;
-    xpre[u] = (has_row && j < n) ? row[j] : make_double2(0.0, 0.0);
-  }
   const double2 t = pending ? a.tau[(size_t)b * n + (k - 1)] : make_double2(0.0, 0.0);
   const double2* rowk = Aw + (size_t)k * n;
   const double2* vprev = a.vbuf[(k + 1) & 1] + (size_t)b * n;  // written by launch k-1
   const double2* pprev = a.pbuf[(k + 1) & 1] + (size_t)b * n;
-  double2 d = make_double2(0.0, 0.0);
-  for (int j0 = k + tid; j0 < n; j0 += kTriNT * 4) {
-    double2 kv[4], rv[4], pv[4];
+  double2 kv[kTriCrit], rv[kTriCrit], pv[kTriCrit];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = j0 + kTriNT * u;
-      if (j < n) {
-        kv[u] = rowk[j];
-        if (pending) {
-          rv[u] = vprev[j];
-          pv[u] = pprev[j];
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = j0 + kTriNT * u;
-      if (j < n) {
-        col[j] = dconj(kv[u]);  // A(j, k) = conj(A(k, j))
-        if (pending) {
-          vp[j] = rv[u];
-          wp[j] = pv[u];
-          d = dadd(d, dcmul(pv[u], rv[u]));
-          if (j == k) {
-            at_k[0] = pv[u];
-            at_k[1] = rv[u];
-          }
-        }
+  for (int u = 0; u < kTriCrit; ++u) {
+    const int j = k + tid + kTriNT * u;
+    if (j < n) {
+      kv[u] = rowk[j];
+      if (pending) {
+        rv[u] = vprev[j];
+        pv[u] = pprev[j];
       }
     }
   }
+  double2 xpre[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int j = k + 1 + lane + 64 * u;
+    xpre[u] = (has_row && j < n) ? row[j] : make_double2(0.0, 0.0);
+  }
+  double2 d = make_double2(0.0, 0.0);
+  auto stage = [&](int j, double2 kj, double2 rj, double2 pj) {
+    col[j] = dconj(kj);  // A(j, k) = conj(A(k, j))
+    if (pending) {
+      vp[j] = rj;
+      wp[j] = pj;
+      d = dadd(d, dcmul(pj, rj));
+      if (j == k) {
+        at_k[0] = pj;
+        at_k[1] = rj;
+      }
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < kTriCrit; ++u) {
+    const int j = k + tid + kTriNT * u;
+    if (j < n) stage(j, kv[u], rv[u], pv[u]);
+  }
+  for (int j = k + tid + kTriNT * kTriCrit; j < n; j += kTriNT)  // n - k > kTriCrit * kTriNT only
+    stage(j, rowk[j], pending ? vprev[j] : make_double2(0.0, 0.0), pending ? pprev[j] : make_double2(0.0, 0.0));
 
   // 1. pending reflector k-1: w = tau p + c v, c = -|tau|^2/2 (p^H v); apply it to
   //    column k: A(j,k) - v_j conj(w_k) - w_j conj(v_k); partial norm for step 3.
@@ -177,13 +183,24 @@ __global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
   const double2 vpi = pending ? vp[my_row] : make_double2(0.0, 0.0);
   const double2 wpi = pending ? wp[my_row] : make_double2(0.0, 0.0);
   double2 acc = make_double2(0.0, 0.0);
-  for (int j0 = k + 1 + lane; j0 < n; j0 += 64 * kTriUnroll) {
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int j = k + 1 + lane + 64 * u;
+    if (j < n) {
+      double2 x = xpre[u];
+      if (pending) {
+        x = dsub(x, dadd(dmul(vpi, dconj(wp[j])), dmul(wpi, dconj(vp[j]))));
+        row[j] = x;
+      }
+      acc = dadd(acc, dmul(x, col[j]));
+    }
+  }
+  for (int j0 = k + 1 + lane + 64 * NU; j0 < n; j0 += 64 * kTriUnroll) {
     double2 x[kTriUnroll];
-    const bool first = j0 == k + 1 + lane;
 #pragma unroll
     for (int u = 0; u < kTriUnroll; ++u) {
       const int j = j0 + 64 * u;
-      x[u] = first ? xpre[u] : (j < n ? row[j] : make_double2(0.0, 0.0));
+      x[u] = j < n ? row[j] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int u = 0; u < kTriUnroll; ++u) {
@@ -206,13 +223,23 @@ __global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
 
 int tri_max_n() { return 3000; }
 
+template <int NU>
+static hipError_t tri_attr() {
+  return hipFuncSetAttribute((const void*)k_tri_step<NU>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)((size_t)3 * tri_max_n() * sizeof(double2)));
+}
+
 hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s) {
   const int n = base.n;
   const size_t lds = (size_t)3 * n * sizeof(double2);
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_tri_step, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)((size_t)3 * tri_max_n() * sizeof(double2)));
+    hipError_t e = tri_attr<1>();
+    if (e == hipSuccess) e = tri_attr<2>();
+    if (e == hipSuccess) e = tri_attr<4>();
+    if (e == hipSuccess) e = tri_attr<8>();
+    if (e == hipSuccess) e = tri_attr<12>();
+    if (e == hipSuccess) e = tri_attr<16>();
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -221,7 +248,14 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s) {
     a.k = k;
     const int rows = n - k - 1;
     const int gx = rows > 0 ? (rows + kTriRows - 1) / kTriRows : 1;
-    k_tri_step<<<dim3(gx, nbatch), kTriNT, lds, s>>>(a);
+    const dim3 grid(gx, nbatch);
+    const int chunks = (rows + 63) / 64;  // row elements per lane
+    if (chunks <= 1) k_tri_step<1><<<grid, kTriNT, lds, s>>>(a);
+    else if (chunks <= 2) k_tri_step<2><<<grid, kTriNT, lds, s>>>(a);
+    else if (chunks <= 4) k_tri_step<4><<<grid, kTriNT, lds, s>>>(a);
+    else if (chunks <= 8) k_tri_step<8><<<grid, kTriNT, lds, s>>>(a);
+    else if (chunks <= 12) k_tri_step<12><<<grid, kTriNT, lds, s>>>(a);
+    else k_tri_step<16><<<grid, kTriNT, lds, s>>>(a);
   }
   return hipGetLastError();
 }

@@ -94,37 +94,46 @@ slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor, double2* R_out) {
 slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
   const int s = pl->s();
   rocblas_int* info = pl->info + (it < 0 ? SLRX_MAX_IRLS : it);
-  KTimer kt(pl, SLRX_K_EIGH);
   if (pl->lib_eigh()) {
+    KTimer kt(pl, SLRX_K_TDEIG);
     rocblas_status rs = rocsolver_zheevd(pl->blas, rocblas_evect_original, rocblas_fill_lower, s,
                                          (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework, info);
     if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zheevd failed (status %d)", (int)rs);
     return SLRX_OK;
   }
-  TriArgs ta{};
-  ta.n = s;
-  ta.Aw = pl->Aw;
-  ta.Vst = pl->Rm;
-  ta.strideA = (long)s * s;
-  ta.D = pl->lam;
-  ta.E = pl->ework;
-  ta.tau = pl->tau;
-  ta.vbuf[0] = pl->triv;
-  ta.vbuf[1] = pl->triv + s;
-  ta.pbuf[0] = pl->trip;
-  ta.pbuf[1] = pl->trip + s;
-  HIPCHK(launch_tridiag(ta, 1, pl->stream));
-  rocblas_status rs = rocsolver_zstedc(pl->blas, rocblas_evect_tridiagonal, s, pl->lam, pl->ework,
-                                       (rocblas_double_complex*)pl->UZ, s, info);
-  if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zstedc failed (status %d)", (int)rs);
-  BackTrArgs bt{};
-  bt.n = s;
-  bt.V = pl->Rm;
-  bt.Y = pl->Aw;  // free once the reduction is done
-  bt.Z = pl->UZ;
-  bt.tau = pl->tau;
-  bt.scratch = pl->bts;
-  HIPCHK(launch_backtransform(bt, pl->stream));
+  {
+    KTimer kt(pl, SLRX_K_TRI);
+    TriArgs ta{};
+    ta.n = s;
+    ta.Aw = pl->Aw;
+    ta.Vst = pl->Rm;
+    ta.strideA = (long)s * s;
+    ta.D = pl->lam;
+    ta.E = pl->ework;
+    ta.tau = pl->tau;
+    ta.vbuf[0] = pl->triv;
+    ta.vbuf[1] = pl->triv + s;
+    ta.pbuf[0] = pl->trip;
+    ta.pbuf[1] = pl->trip + s;
+    HIPCHK(launch_tridiag(ta, 1, pl->stream));
+  }
+  {
+    KTimer kt(pl, SLRX_K_TDEIG);
+    rocblas_status rs = rocsolver_zstedc(pl->blas, rocblas_evect_tridiagonal, s, pl->lam, pl->ework,
+                                         (rocblas_double_complex*)pl->UZ, s, info);
+    if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zstedc failed (status %d)", (int)rs);
+  }
+  {
+    KTimer kt(pl, SLRX_K_BACKTR);
+    BackTrArgs bt{};
+    bt.n = s;
+    bt.V = pl->Rm;
+    bt.Y = pl->Aw;  // free once the reduction is done
+    bt.Z = pl->UZ;
+    bt.tau = pl->tau;
+    bt.scratch = pl->bts;
+    HIPCHK(launch_backtransform(bt, pl->stream));
+  }
   return SLRX_OK;
 }
 

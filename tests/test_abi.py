@@ -111,3 +111,14 @@ def test_plan_create_without_device_fails_cleanly():
     with pytest.raises(slrx.SlrxError) as ei:
         slrx.Plan(64, 64, 8, 5, 5, 3)
     assert ei.value.name == "SLRX_EDEVICE"
+
+
+def test_kernel_classes_match_header():
+    import re
+    src = open(HEADER).read()
+    enum = {m.group(1).lower(): int(m.group(2)) for m in re.finditer(r"SLRX_K_([A-Z]+)\s*=\s*(\d+)", src)}
+    n = enum.pop("nclass")
+    assert [k for k, _ in sorted(enum.items(), key=lambda kv: kv[1])] == list(slrx.KERNEL_CLASSES)
+    assert n == len(slrx.KERNEL_CLASSES) <= 16
+    # int32 + pad, three FP64 histories, five timings, 16 class times, 16 class counts
+    assert ctypes.sizeof(slrx.Stats) == 8 + 3 * 8 * slrx.MAX_IRLS + 5 * 8 + 16 * 8 + 16 * 4
