@@ -1,0 +1,48 @@
+"""Mutation check of the oracle's pins: a plausible mistake planted in a copy of
+the oracle (a conjugate on the wrong factor, a sign, an index, an exponent, a
+dropped term, a wrong schedule) must make the pin suite fail.  Runs on the CPU
+only; the repository's own oracle is never modified."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (original text, planted mistake) in oracle/slr.py
+MUTATIONS = {
+    "gram_conj_swap": ("c += np.conj(rho[n - m]) * rho[n - mp]", "c += rho[n - m] * np.conj(rho[n - mp])"),
+    "gram_lag_sign": ("d1 = (a1[:, None] - a1[None, :]) % P", "d1 = (a1[None, :] - a1[:, None]) % P"),
+    "gram_range": ("for n in range(M - 1, T):\n                c +=", "for n in range(M, T):\n                c +="),
+    "spectra_sign": ("return scipy.fft.ifft2(frames, workers=-1) * (P * Q)", "return scipy.fft.fft2(frames, workers=-1)"),
+    "alpha_exponent": ("alpha = (np.maximum(lam, 0.0) + eps) ** (p / 2.0 - 1.0)",
+                       "alpha = (np.maximum(lam, 0.0) + eps) ** (p / 2.0 - 0.5)"),
+    "mask_conj": ('E[m, mp] += np.einsum("ir,ir->r", cmu[:, m], mu[:, mp])',
+                  'E[m, mp] += np.einsum("ir,ir->r", mu[:, m], cmu[:, mp])'),
+    "penalty_swap": ("out[n - m] += E[m, mp] * rho[n - mp]", "out[n - mp] += E[m, mp] * rho[n - m]"),
+    "normal_transform_order": ("return S * xhat + lam * dft2(penalty_apply(idft2(xhat), E))",
+                               "return S * xhat + lam * idft2(penalty_apply(dft2(xhat), E))"),
+    "cg_beta": ("p = r + (rr_new / rr) * p", "p = r + (rr / rr_new) * p"),
+    "eps_schedule": ("eps = eps / gamma", "eps = eps * gamma"),
+    "eps_start": ("eps = eps0_frac * float(lamR.max())", "eps = eps0_frac * float(lamR.min() + lamR.max()/2)"),
+    "lift_shift": ("vals = xhat[n - m][(w1 - a1[ia]) % P, (w2 - a2[ia]) % Q]",
+                   "vals = xhat[n - m][(w1 + a1[ia]) % P, (w2 - a2[ia]) % Q]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    src = open(os.path.join(ROOT, "oracle", "slr.py")).read()
+    orig, planted = MUTATIONS[name]
+    assert orig in src, f"mutation site of {name} not found in the oracle"
+    for d in ("oracle", "workload", "tests"):
+        shutil.copytree(os.path.join(ROOT, d), tmp_path / d, ignore=shutil.ignore_patterns("__pycache__"))
+    shutil.copy(os.path.join(ROOT, "pytest.ini"), tmp_path)
+    (tmp_path / "oracle" / "slr.py").write_text(src.replace(orig, planted))
+    env = dict(os.environ, PYTHONDONTWRITEBYTECODE="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        "tests/test_oracle_pins.py"], cwd=tmp_path, capture_output=True, text=True, env=env,
+                       timeout=600)
+    assert r.returncode != 0, f"pins did not catch {name}:\n{r.stdout[-2000:]}"
