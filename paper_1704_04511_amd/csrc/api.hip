@@ -184,6 +184,9 @@ static Layout plan_layout(const slrx_dims& d) {
   sz[B_TRIV] = 2 * s * 16;
   sz[B_TRIP] = 2 * s * 16;
   sz[B_BTS] = bt_scratch_elems(s) * 16;
+  sz[B_DCTREE] = (size_t)4 * s * sizeof(int);
+  sz[B_DCWSI] = dc_ws_ints(s) * sizeof(int);
+  sz[B_DCWSD] = dc_ws_doubles(s) * sizeof(double);
   Layout L;
   size_t o = 0;
   for (int i = 0; i < kNumBuf; ++i) {
@@ -235,8 +238,6 @@ static slrx_status setup_eigensolver(slrx_plan* pl) {
   // sizes for every s up to the capacity are bounded by the capacity's
   rocsolver_zheevd(pl->blas, rocblas_evect_original, rocblas_fill_lower, s,
                    (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework, pl->info);
-  rocsolver_zstedc(pl->blas, rocblas_evect_tridiagonal, s, pl->lam, pl->ework, (rocblas_double_complex*)pl->UZ,
-                   s, pl->info);
   rocblas_stop_device_memory_size_query(pl->blas, &ws);
   if (ws < 1024) ws = 1024;
   if (hipMalloc(&pl->blas_ws, ws) != hipSuccess) return fail(SLRX_ENOMEM, "eigensolver workspace (%zu bytes)", ws);
@@ -288,6 +289,9 @@ static void assign_buffers(slrx_plan* pl, const Layout& L) {
   pl->triv = (double2*)at(B_TRIV);
   pl->trip = (double2*)at(B_TRIP);
   pl->bts = (double2*)at(B_BTS);
+  pl->dc_tree = (int*)at(B_DCTREE);
+  pl->dc_wsi = (int*)at(B_DCWSI);
+  pl->dc_wsd = (double*)at(B_DCWSD);
 }
 
 extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params* params, void* hip_stream,
@@ -329,6 +333,7 @@ extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params
   slrx_status st = setup_eigensolver(pl);
   if (st == SLRX_OK && hipMemset(pl->arena, 0, L.total) != hipSuccess) st = fail(SLRX_EDEVICE, "hipMemset failed");
   if (st == SLRX_OK) st = make_twiddles(pl);
+  if (st == SLRX_OK) st = dc_prepare(pl);
   if (st == SLRX_OK) {
     for (int i = 0; i < 2; ++i)
       if (hipEventCreate(&pl->ev_run[i]) != hipSuccess) st = fail(SLRX_EDEVICE, "hipEventCreate failed");
@@ -443,7 +448,7 @@ extern "C" slrx_status slrx_set_filter(slrx_plan* pl, int32_t N1, int32_t N2, in
                 pl->cap.N2, pl->cap.M);
   pl->d = d;
   pl->ran = false;
-  return SLRX_OK;
+  return dc_prepare(pl);
 }
 
 extern "C" slrx_status slrx_set_params(slrx_plan* pl, const slrx_params* prm) {

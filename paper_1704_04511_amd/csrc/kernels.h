@@ -1,6 +1,7 @@
 // Launch wrappers of the libslrx kernels (host side).  All launches are
 // asynchronous on the given stream and return hipGetLastError().
 #pragma once
+#include <vector>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -146,6 +147,29 @@ struct BackTrArgs {
 };
 hipError_t launch_backtransform(const BackTrArgs& a, hipStream_t s);
 size_t bt_scratch_elems(int n);
+
+// Eigenpairs of the real symmetric tridiagonal (D, E) by divide and conquer:
+// D gets the ascending eigenvalues, Z (column-major n x n complex) the
+// eigenvectors with imaginary part 0.
+struct TdArgs {
+  int n;
+  double* D;                     // n: diagonal in, eigenvalues out
+  const double* E;               // n - 1 off-diagonal entries
+  double2* Z;                    // n x n output
+  double* Q;                     // n x n workspace
+  double* Qs;                    // n x n workspace
+  double* U;                     // n x n workspace
+  const int* nodes;              // device copy of the tree from dc_build_tree
+  std::vector<int> level_start;  // from dc_build_tree
+  std::vector<int> node_sizes;   // size of every node, host copy
+  int* ws_i;                     // dc_ws_ints(n)
+  double* ws_d;                  // dc_ws_doubles(n)
+};
+void dc_build_tree(int n, std::vector<int>& nodes, std::vector<int>& level_start);
+size_t dc_ws_ints(int n);
+size_t dc_ws_doubles(int n);
+int dc_max_n();
+hipError_t launch_tdeig(const TdArgs& a, hipStream_t s);
 
 // H = V V^H on FP64 MFMA: Hre, Him row-major s x s.
 hipError_t launch_filter_product(int s, const double* VT, double* Hre, double* Him, hipStream_t st);

@@ -17,7 +17,7 @@ enum Buf {
   B_TWPF, B_TWQF, B_TWPD, B_TWQD,
   B_C1, B_G, B_RM, B_LAM, B_EWORK, B_VT, B_HRE, B_HIM, B_WSUM, B_S1,
   B_PARTA, B_PARTB, B_RRH, B_SCAL, B_STATS, B_INFO, B_FLAG,
-  B_AW, B_UZ, B_TAU, B_TRIV, B_TRIP, B_BTS,
+  B_AW, B_UZ, B_TAU, B_TRIV, B_TRIP, B_BTS, B_DCTREE, B_DCWSI, B_DCWSD,
   kNumBuf
 };
 
@@ -48,6 +48,11 @@ struct slrx_plan {
   double2 *wsum = nullptr, *s1 = nullptr;
   double2 *Aw = nullptr, *UZ = nullptr, *tau = nullptr, *triv = nullptr, *trip = nullptr;
   double2* bts = nullptr;  // back-transformation scratch
+  int* dc_tree = nullptr;  // divide-and-conquer tree (4 ints per internal node)
+  int* dc_wsi = nullptr;
+  double* dc_wsd = nullptr;
+  int dc_tree_n = 0;       // size the tree was built for
+  std::vector<int> dc_level_start, dc_node_sizes;
   double *partA = nullptr, *partB = nullptr, *rr_hist = nullptr, *scal = nullptr, *stats = nullptr;
   rocblas_int* info = nullptr;
   int* flag = nullptr;
@@ -94,6 +99,7 @@ slrx_status load_masks(slrx_plan* pl, const float2* E_dev);
 slrx_status store_masks(slrx_plan* pl);
 slrx_status step_gram(slrx_plan* pl, bool colmajor = false, double2* R_out = nullptr);
 slrx_status step_eigh(slrx_plan* pl, int it);
+slrx_status dc_prepare(slrx_plan* pl);
 slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma, const double2* U = nullptr,
                          const double* lamv = nullptr);
 slrx_status apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part);

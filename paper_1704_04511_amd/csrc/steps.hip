@@ -87,10 +87,23 @@ slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor, double2* R_out) {
   return SLRX_OK;
 }
 
-// Eigen-decomposition of the Gram matrix: own Householder tridiagonalisation,
-// rocSOLVER divide-and-conquer on the real tridiagonal, own blocked
-// back-transformation (eigenvectors into UZ); or rocSOLVER zheevd on Rm
-// (SLRX_FLAG_LIBEIGH).
+// Eigen-decomposition of the Gram matrix: Householder tridiagonalisation,
+// divide and conquer on the real tridiagonal, blocked back-transformation
+// (eigenvectors into UZ); or rocSOLVER zheevd on Rm (SLRX_FLAG_LIBEIGH).
+// Tree of the divide-and-conquer solver for the current s (host table copied
+// to the device; called while the plan is idle).
+slrx_status slrx::dc_prepare(slrx_plan* pl) {
+  const int s = pl->s();
+  if (s > dc_max_n() || s == pl->dc_tree_n) return SLRX_OK;
+  std::vector<int> nodes;
+  dc_build_tree(s, nodes, pl->dc_level_start);
+  pl->dc_node_sizes.resize(nodes.size() / 4);
+  for (size_t q = 0; q < nodes.size() / 4; ++q) pl->dc_node_sizes[q] = nodes[4 * q + 1];
+  if (!nodes.empty()) HIPCHK(hipMemcpy(pl->dc_tree, nodes.data(), nodes.size() * sizeof(int), hipMemcpyHostToDevice));
+  pl->dc_tree_n = s;
+  return SLRX_OK;
+}
+
 slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
   const int s = pl->s();
   rocblas_int* info = pl->info + (it < 0 ? SLRX_MAX_IRLS : it);
@@ -119,9 +132,21 @@ slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
   }
   {
     KTimer kt(pl, SLRX_K_TDEIG);
-    rocblas_status rs = rocsolver_zstedc(pl->blas, rocblas_evect_tridiagonal, s, pl->lam, pl->ework,
-                                         (rocblas_double_complex*)pl->UZ, s, info);
-    if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zstedc failed (status %d)", (int)rs);
+    if (pl->dc_tree_n != s) return fail(SLRX_ESTATE, "divide-and-conquer tree not built for s = %d", s);
+    TdArgs td;
+    td.n = s;
+    td.D = pl->lam;
+    td.E = pl->ework;
+    td.Z = pl->UZ;
+    td.Q = pl->VT;  // VT and Hre are free until the weights are formed
+    td.Qs = pl->VT + (size_t)s * s;
+    td.U = pl->Hre;
+    td.nodes = pl->dc_tree;
+    td.level_start = pl->dc_level_start;
+    td.node_sizes = pl->dc_node_sizes;
+    td.ws_i = pl->dc_wsi;
+    td.ws_d = pl->dc_wsd;
+    HIPCHK(launch_tdeig(td, pl->stream));
   }
   {
     KTimer kt(pl, SLRX_K_BACKTR);
