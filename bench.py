@@ -269,6 +269,94 @@ def bench_serve(args) -> int:
     return 0
 
 
+def t2_map(img, te_ms, mask):
+    """Mono-exponential T2 per pixel: least-squares line through log|rho_t| against TE."""
+    import numpy as np
+    y = np.log(np.maximum(np.abs(img[:, mask]), 1e-30))  # [T][pixels]
+    t = np.asarray(te_ms, dtype=np.float64)
+    tc = t - t.mean()
+    slope = (tc[:, None] * (y - y.mean(axis=0))).sum(axis=0) / (tc * tc).sum()
+    with np.errstate(divide="ignore"):
+        return -1.0 / slope
+
+
+def bench_c2(args) -> int:
+    """128x128x16 (filter 9x9x5, 15 x 10): IRLS iterations/s, NRMSE against the oracle, and
+    mono-exponential T2 maps fitted the same way to the GPU result, the oracle and the truth."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1704_04511_amd as slrx
+    import workload
+
+    torch.cuda.set_device(0)
+    pb = workload.config_problem("c2")
+    T, P, Q = pb.b.shape
+    prm = slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg, p=pb.p, gamma=pb.gamma,
+                           eps0_frac=pb.eps0_frac)
+    plan = slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, prm)
+    plan.set_kspace(pb.b)
+    plan.set_mask(pb.S)
+    for _ in range(args.warmup):
+        plan.run()
+        plan.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run()
+        plan.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    img = plan.images()
+    plan.close()
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ora = oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, pb.n_irls, pb.n_cg, p=pb.p, gamma=pb.gamma,
+                      eps0_frac=pb.eps0_frac)
+    dto = time.perf_counter() - t0
+    te = 10.0 * (np.arange(T) + 1)
+    mask = np.abs(pb.truth[0]) > 0.1 * np.abs(pb.truth[0]).max()
+    t2g, t2o, t2t = (t2_map(v, te, mask) for v in (img, ora, pb.truth))
+    rel = lambda a, b: float(np.median(np.abs(a - b) / np.abs(b)))
+    out = {
+        "metric": "IRLS iters/s (128x128x16, filter 9x9x5)", "value": round(pb.n_irls * args.steps / dt, 3),
+        "unit": "IRLS iter/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": "128x128 x 16 echoes, K=2, R=6, filter 9x9x5 (s=405), 15 IRLS x 10 CG",
+                   "n_irls": pb.n_irls, "n_cg": pb.n_cg},
+        "nrmse_vs_oracle": float(f"{np.linalg.norm(img - ora) / np.linalg.norm(ora):.3e}"),
+        "t2_pixels": int(mask.sum()),
+        "t2_median_rel_err_gpu_vs_truth": round(rel(t2g, t2t), 5),
+        "t2_median_rel_err_oracle_vs_truth": round(rel(t2o, t2t), 5),
+        "t2_median_rel_diff_gpu_vs_oracle": float(f"{rel(t2g, t2o):.3e}"),
+        "cpu_baseline": {"value": pb.n_irls / dto, "unit": "IRLS iter/s", "cores": cores, "kind": "oracle",
+                         "sample": f"the whole reconstruction ({pb.n_irls} outer iterations), {dto:.1f} s wall"},
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def copy_bandwidth_gbs() -> float:
+    """Device-to-device copy of 1 GiB (read + write counted), best of 5, torch's copy kernel."""
+    import torch
+    n = 1 << 27  # doubles
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    best = 1e9
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return round(2.0 * n * 8 / (best * 1e-3) / 1e9, 1)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,9 +366,9 @@ def main() -> int:
     ap.add_argument("--cpu-outer", type=int, default=3, help="outer iterations in the CPU oracle sample")
     ap.add_argument("--n-irls", type=int, default=None,
                     help="override the outer iteration count (profiling runs only; changes the workload)")
-    ap.add_argument("--workload", choices=("c3", "batch", "serve"), default="c3",
-                    help="c3: the 256x256x20 headline line (default); batch: 32 uneven slices; "
-                         "serve: Poisson request stream")
+    ap.add_argument("--workload", choices=("c3", "c2", "batch", "serve"), default="c3",
+                    help="c3: the 256x256x20 headline line (default); c2: 128x128x16 with T2 maps; "
+                         "batch: 32 uneven slices; serve: Poisson request stream")
     ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -289,6 +377,8 @@ def main() -> int:
         return 2
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "c2":
+        return bench_c2(args)
     if args.workload == "serve":
         return bench_serve(args)
 
@@ -300,6 +390,7 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    copy_gbs = copy_bandwidth_gbs()
     pb = workload.config_problem("c3")
     if args.n_irls is not None:
         pb.n_irls = args.n_irls
@@ -351,7 +442,7 @@ def main() -> int:
                                "lambda=1e-3, p=0.6",
                    "P": P, "Q": Q, "T": T, "filter": [pb.N1, pb.N2, pb.M], "n_irls": pb.n_irls,
                    "n_cg": pb.n_cg, "parallelism": "single GPU"},
-        "roofline": roofs[dom],
+        "roofline": dict(roofs[dom], measured_copy_gbs=copy_gbs),
         "roofline_by_kernel": {k: {kk: v for kk, v in r.items() if kk in ("bound", "achieved", "unit", "frac")}
                                for k, r in roofs.items()},
         "phases_ms_per_step": {k: round(kms[k], 3) for k in kms},

@@ -73,14 +73,26 @@ __global__ __launch_bounds__(kNT) void k_rows_t(RowArgs a) {
     }
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.rr_hist[a.k] = rr;
     const float fb = (float)beta;
-    for (int e = threadIdx.x; e < nel; e += kNT) {
-      float2 v = a.src[g0 + e];
-      if (a.k > 0) {
-        const float2 po = a.pvec[g0 + e];
-        v = make_float2(v.x + fb * po.x, v.y + fb * po.y);
+    constexpr int U = 8;  // loads in flight per thread
+    for (int e0 = threadIdx.x; e0 < nel; e0 += kNT * U) {
+      float2 v[U], po[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kNT;
+        if (e < nel) {
+          v[u] = a.src[g0 + e];
+          po[u] = a.k > 0 ? a.pvec[g0 + e] : make_float2(0.f, 0.f);
+        }
       }
-      a.pvec[g0 + e] = v;
-      lds[e] = v;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kNT;
+        if (e < nel) {
+          const float2 pv = make_float2(v[u].x + fb * po[u].x, v[u].y + fb * po[u].y);
+          a.pvec[g0 + e] = pv;
+          lds[e] = pv;
+        }
+      }
     }
   } else if (a.mode == ROW_MASKED) {
     for (int e = threadIdx.x; e < nel; e += kNT) {
@@ -115,21 +127,28 @@ __global__ __launch_bounds__(kNT) void k_cols_pen(PenArgs a) {
   const int c0 = blockIdx.x * CB;
   const long fs = (long)P * Q;
   for (int i = threadIdx.x; i < N; i += kNT) tw[i] = a.tw[i];
-  const int per_t = CB * N;
-  for (int e = threadIdx.x; e < T * per_t; e += kNT) {
-    const int t = e / per_t, rem = e % per_t;  // rem = cc * N + r
-    lds[e] = a.buf[(long)t * fs + (long)c0 * P + rem];
+  const int per_t = CB * N;  // <= kNT: one pixel per thread
+  const int pix = threadIdx.x;
+  const bool has_pix = pix < per_t;
+  const long po = (long)c0 * P + pix;  // pixel (row pix % N, column c0 + pix / N) in a frame
+  {
+    float2 v[kTMax];
+#pragma unroll
+    for (int t = 0; t < kTMax; ++t) v[t] = (has_pix && t < T) ? a.buf[(long)t * fs + po] : make_float2(0.f, 0.f);
+    if (has_pix)
+#pragma unroll
+      for (int t = 0; t < kTMax; ++t)
+        if (t < T) lds[t * per_t + pix] = v[t];
   }
+  // this pixel's masks, stored [w][c][r]; loaded now so they arrive during the transform
+  float2 e[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) e[w] = has_pix ? a.Et[(long)w * fs + po] : make_float2(0.f, 0.f);
   __syncthreads();
   fft_lds<N, +1, MAXB, kNT, 1, N, false>(lds, tw, T * CB);
 
   const float sc = a.scale;  // lam / (P Q)
-  for (int pix = threadIdx.x; pix < per_t; pix += kNT) {
-    // pixel (row r = pix % N, column c0 + pix / N); E stored [w][c][r]
-    const long eo = (long)c0 * P + pix;
-    float2 e[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) e[w] = a.Et[(long)w * fs + eo];
+  if (has_pix) {
     float2 z[M], acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -165,10 +184,8 @@ __global__ __launch_bounds__(kNT) void k_cols_pen(PenArgs a) {
   }
   __syncthreads();
   fft_lds<N, -1, MAXB, kNT, 1, N, false>(lds, tw, T * CB);
-  for (int e = threadIdx.x; e < T * per_t; e += kNT) {
-    const int t = e / per_t, rem = e % per_t;
-    a.buf[(long)t * fs + (long)c0 * P + rem] = lds[e];
-  }
+  if (has_pix)
+    for (int t = 0; t < T; ++t) a.buf[(long)t * fs + po] = lds[t * per_t + pix];
 }
 
 // Plain column DFT of up to 16 columns of one frame: transposed in, row-major out.
@@ -210,21 +227,43 @@ __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
   const long fo = (long)t * P * Q;
   const int nel = RB * N;
   for (int i = threadIdx.x; i < N; i += kNT) tw[i] = a.tw[i];
-  for (int e = threadIdx.x; e < nel; e += kNT) {
-    const int i = e % RB, c = e / RB;
-    lds[i * N + c] = a.t[fo + (long)c * P + r0 + i];
+  constexpr int UR = RBMAX * N / kNT < 16 ? RBMAX * N / kNT : 16;
+  constexpr int U = UR < 1 ? 1 : UR;  // elements per thread held in registers
+  const long g0 = fo + (long)r0 * Q;
+  {
+    float2 tv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + u * kNT;
+      if (e < nel) tv[u] = a.t[fo + (long)(e / RB) * P + r0 + e % RB];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + u * kNT;
+      if (e < nel) lds[(e % RB) * N + e / RB] = tv[u];
+    }
+    for (int e = threadIdx.x + U * kNT; e < nel; e += kNT) lds[(e % RB) * N + e / RB] = a.t[fo + (long)(e / RB) * P + r0 + e % RB];
+  }
+  // the operands of the combine step, loaded before the transform
+  float2 vv[U], yv[U];
+  uint8_t sv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * kNT;
+    if (e < nel) {
+      vv[u] = a.v[g0 + e];
+      sv[u] = a.S[g0 + e];
+      yv[u] = a.init ? a.y[g0 + e] : make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
   fft_lds<N, -1, RBMAX, kNT, 1, N, false>(lds, tw, RB);
-  const long g0 = fo + (long)r0 * Q;
   double dot = 0.0;
-  for (int e = threadIdx.x; e < nel; e += kNT) {
+  auto combine = [&](int e, float2 v, uint8_t sm, float2 bv) {
     const long g = g0 + e;
-    const float2 v = a.v[g];
     const float2 pen = lds[e];
-    const float2 av = a.S[g] ? make_float2(v.x + pen.x, v.y + pen.y) : pen;
+    const float2 av = sm ? make_float2(v.x + pen.x, v.y + pen.y) : pen;
     if (a.init) {
-      const float2 bv = a.y[g];
       const float2 rv = make_float2(bv.x - av.x, bv.y - av.y);
       a.out[g] = rv;
       dot += (double)rv.x * rv.x + (double)rv.y * rv.y;
@@ -232,7 +271,14 @@ __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
       a.out[g] = av;
       dot += (double)v.x * av.x + (double)v.y * av.y;
     }
+  };
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * kNT;
+    if (e < nel) combine(e, vv[u], sv[u], yv[u]);
   }
+  for (int e = threadIdx.x + U * kNT; e < nel; e += kNT)
+    combine(e, a.v[g0 + e], a.S[g0 + e], a.init ? a.y[g0 + e] : make_float2(0.f, 0.f));
   dot = block_sum<kNT>(dot, red);
   if (threadIdx.x == 0) {
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
@@ -242,25 +288,49 @@ __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
 }
 
 // --------------------------------------------------------------- update
+// Two complex elements per 16-byte access, kUpdU accesses per thread in flight.
+constexpr int kUpdU = 4;
 __global__ __launch_bounds__(kNT) void k_update(UpdArgs a) {
   __shared__ double red[kNT / 64];
   const double pq = reduce_partials<kNT>(a.partA, a.nA, red);
   const double rr = a.rr_hist[a.k];
   const bool stop = (*a.flag != 0) || !(rr > 0.0) || !(pq > 0.0);
   const float al = stop ? 0.f : (float)(rr / pq);
+  const long n4 = a.n / 2;  // float4 count (the volume has an even element count)
+  float4* x4 = (float4*)a.x;
+  float4* r4 = (float4*)a.r;
+  const float4* p4 = (const float4*)a.p;
+  const float4* q4 = (const float4*)a.q;
   double acc = 0.0;
   const long stride = (long)gridDim.x * kNT;
-  for (long i = (long)blockIdx.x * kNT + threadIdx.x; i < a.n; i += stride) {
-    float2 ri = a.r[i];
-    if (!stop) {
-      const float2 pi = a.p[i], qi = a.q[i];
-      float2 xi = a.x[i];
-      xi = make_float2(xi.x + al * pi.x, xi.y + al * pi.y);
-      ri = make_float2(ri.x - al * qi.x, ri.y - al * qi.y);
-      a.x[i] = xi;
-      a.r[i] = ri;
+  for (long b = (long)blockIdx.x * kNT + threadIdx.x; b < n4; b += stride * kUpdU) {
+    float4 rv[kUpdU], xv[kUpdU], pv[kUpdU], qv[kUpdU];
+#pragma unroll
+    for (int u = 0; u < kUpdU; ++u) {
+      const long i = b + u * stride;
+      if (i < n4) {
+        rv[u] = r4[i];
+        if (!stop) {
+          xv[u] = x4[i];
+          pv[u] = p4[i];
+          qv[u] = q4[i];
+        }
+      }
     }
-    acc += (double)ri.x * ri.x + (double)ri.y * ri.y;
+#pragma unroll
+    for (int u = 0; u < kUpdU; ++u) {
+      const long i = b + u * stride;
+      if (i >= n4) continue;
+      float4 ri = rv[u];
+      if (!stop) {
+        const float4 xi = make_float4(xv[u].x + al * pv[u].x, xv[u].y + al * pv[u].y, xv[u].z + al * pv[u].z,
+                                      xv[u].w + al * pv[u].w);
+        ri = make_float4(ri.x - al * qv[u].x, ri.y - al * qv[u].y, ri.z - al * qv[u].z, ri.w - al * qv[u].w);
+        x4[i] = xi;
+        r4[i] = ri;
+      }
+      acc += (double)ri.x * ri.x + (double)ri.y * ri.y + (double)ri.z * ri.z + (double)ri.w * ri.w;
+    }
   }
   acc = block_sum<kNT>(acc, red);
   if (threadIdx.x == 0) {
@@ -372,7 +442,7 @@ hipError_t launch_fin(const FinArgs& a, hipStream_t s) { SLRX_DISPATCH_N(a.Q, fi
 int fin_blocks(int P, int T) { return (P / row_block(P)) * T; }
 
 int update_blocks(long n) {
-  long b = (n + kNT - 1) / kNT;
+  long b = (n / 2 + (long)kNT * kUpdU - 1) / ((long)kNT * kUpdU);
   if (b > 1024) b = 1024;
   if (b < 1) b = 1;
   return (int)b;
