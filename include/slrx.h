@@ -173,6 +173,13 @@ slrx_status slrx_step_gram(slrx_plan* plan, void* R_out, slrx_mem mem);
  * pairs m <= m' in row-major upper-triangle order).  Any output may be NULL. */
 slrx_status slrx_step_weights(slrx_plan* plan, double eps, double* lam_out,
                               void* H_out, void* E_out, slrx_mem mem);
+/* Eigenpairs of the real symmetric tridiagonal matrix with diagonal D (s
+ * doubles) and off-diagonal E (s - 1 doubles), s = N1 N2 M of the plan, by the
+ * divide-and-conquer stage of the weight update: lam_out gets the s
+ * eigenvalues ascending, Z_out the eigenvectors as complex128, column-major
+ * s x s, imaginary parts 0.  SLRX_EINVAL if s > 3000. */
+slrx_status slrx_step_tdeig(slrx_plan* plan, const double* D, const double* E, double* lam_out,
+                            void* Z_out, slrx_mem mem);
 /* Apply the normal operator to k-space v with masks E (complex64 [W][P][Q]):
  * out = S o v + lam F G F^H v, complex64 k-space. */
 slrx_status slrx_step_apply(slrx_plan* plan, const void* E, const void* v,

@@ -106,6 +106,7 @@ _SIGS = {
     "slrx_run_batch": (_I, [ctypes.POINTER(_P), ctypes.c_int32, _P]),
     "slrx_step_gram": (_I, [_P, _P, _I]),
     "slrx_step_weights": (_I, [_P, ctypes.c_double, _P, _P, _P, _I]),
+    "slrx_step_tdeig": (_I, [_P, _P, _P, _P, _P, _I]),
     "slrx_step_apply": (_I, [_P, _P, _P, _P, _I]),
     "slrx_step_cg": (_I, [_P, _P, ctypes.c_int32]),
     "slrx_server_create": (_I, [ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
@@ -308,6 +309,21 @@ class Plan:
                                        H.ctypes.data_as(ctypes.c_void_p), E.ctypes.data_as(ctypes.c_void_p),
                                        SLRX_MEM_HOST))
         return lam, H, E
+
+    def step_tdeig(self, D, E):
+        """Eigenpairs of the real symmetric tridiagonal (D, E) of size s (divide and conquer)."""
+        s = self.s
+        D = np.ascontiguousarray(D, np.float64)
+        E = np.ascontiguousarray(E, np.float64)
+        if D.shape != (s,) or E.shape != (max(s - 1, 0),):
+            raise ValueError(f"expected D of {s} and E of {max(s - 1, 0)} entries")
+        lam = np.empty(s, np.float64)
+        Z = np.empty((s, s), np.complex128)  # column-major: Z[c] is eigenvector c
+        Ep = E.ctypes.data_as(ctypes.c_void_p) if s > 1 else None
+        _check(lib().slrx_step_tdeig(self._h, D.ctypes.data_as(ctypes.c_void_p), Ep,
+                                     lam.ctypes.data_as(ctypes.c_void_p), Z.ctypes.data_as(ctypes.c_void_p),
+                                     SLRX_MEM_HOST))
+        return lam, Z.T
 
     def step_apply(self, E, v):
         d = self.dims

@@ -688,6 +688,34 @@ extern "C" slrx_status slrx_step_weights(slrx_plan* pl, double eps, double* lam_
   return SLRX_OK;
 }
 
+extern "C" slrx_status slrx_step_tdeig(slrx_plan* pl, const double* D, const double* E, double* lam_out, void* Z_out,
+                                       slrx_mem mem) {
+  STCHK(check_idle(pl));
+  if (!D || (!E && pl->s() > 1) || !lam_out || !Z_out) return fail(SLRX_EINVAL, "NULL argument");
+  const int s = pl->s();
+  if (s > dc_max_n()) return fail(SLRX_EINVAL, "s = %d exceeds the divide-and-conquer limit %d", s, dc_max_n());
+  STCHK(copy_in(pl, pl->lam, D, (size_t)s * sizeof(double), mem));
+  if (s > 1) STCHK(copy_in(pl, pl->ework, E, (size_t)(s - 1) * sizeof(double), mem));
+  TdArgs td;
+  td.n = s;
+  td.D = pl->lam;
+  td.E = pl->ework;
+  td.Z = pl->UZ;
+  td.Q = pl->VT;
+  td.Qs = pl->VT + (size_t)s * s;
+  td.U = pl->Hre;
+  td.nodes = pl->dc_tree;
+  td.level_start = pl->dc_level_start;
+  td.node_sizes = pl->dc_node_sizes;
+  td.ws_i = pl->dc_wsi;
+  td.ws_d = pl->dc_wsd;
+  HIPCHK(launch_tdeig(td, pl->stream));
+  STCHK(copy_out(pl, lam_out, pl->lam, (size_t)s * sizeof(double), mem));
+  STCHK(copy_out(pl, Z_out, pl->UZ, (size_t)s * s * sizeof(double2), mem));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  return SLRX_OK;
+}
+
 extern "C" slrx_status slrx_step_apply(slrx_plan* pl, const void* E, const void* v, void* out, slrx_mem mem) {
   STCHK(ensure_prepared(pl));
   const slrx_dims& d = pl->d;
