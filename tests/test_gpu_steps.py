@@ -19,9 +19,11 @@ pytestmark = pytest.mark.gpu
 slrx = pytest.importorskip("paper_1704_04511_amd")
 
 # (T, P, Q, N1, N2, M): several tiles, odd radices (96 = 16*3*2, 160 = 16*5*2,
-# 192 = 16*4*3), even/odd filters, M = 1 and M = T.
+# 192 = 16*4*3), even/odd filters, M = 1 and M = T, the largest frame count
+# (T = 32) with the largest tap count (M = 8).
 STEP_SHAPES = [
     (5, 16, 16, 3, 3, 2),
+    (32, 16, 16, 2, 2, 8),
     (8, 64, 64, 5, 5, 3),
     (6, 32, 96, 4, 5, 3),
     (4, 160, 32, 3, 2, 4),
