@@ -165,8 +165,9 @@ def bench_batch(args) -> int:
         pl.sync()
     torch.cuda.synchronize()
     dt_seq = time.perf_counter() - t0
-    seq_nrmse = max(float(np.linalg.norm(a - pl.images()) / np.linalg.norm(pl.images()))
-                    for a, pl in zip(batch_imgs, plans))
+    seq_imgs = [pl.images() for pl in plans]
+    seq_nrmse = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(batch_imgs, seq_imgs))
+    seq_same = all(np.array_equal(a, b) for a, b in zip(batch_imgs, seq_imgs))
     same = True  # a slice in the batch gives the bits of the same slice as a batch of one
     for a, pl in list(zip(batch_imgs, plans))[:4]:
         slrx.run_batch([pl])
@@ -183,6 +184,7 @@ def bench_batch(args) -> int:
         "batch_speedup": round(dt_seq / dt_batch, 3),
         "batch_equals_batch_of_one_bitwise": bool(same),
         "batch_vs_single_run_max_nrmse": float(f"{seq_nrmse:.3e}"),
+        "batch_equals_single_run_bitwise": bool(seq_same),
     }
     if not args.no_cpu_baseline:
         # whole slices of the same batch through the oracle until about 10 s have passed

@@ -154,11 +154,11 @@ slrx_status slrx_get_kspace(slrx_plan* plan, void* out, slrx_mem mem);
 slrx_status slrx_get_stats(slrx_plan* plan, slrx_stats* out);
 
 /* Run several independent plans.  hip_stream NULL: in lock step, one outer
- * iteration of every plan per step; plans with equal Gram size s <= 640 share
- * one batched FP64 eigen-decomposition per step, larger ones use the
- * single-problem eigensolver; every other kernel runs on the plan's own
- * stream.  The method depends on s only, so a plan's result in a batch does not
- * depend on the other plans (a batch of one gives the same bits).  With
+ * iteration of every plan per step; plans with equal Gram size s share one
+ * launch sequence of the eigen-decomposition (every kernel covers all of them,
+ * each with the arithmetic of a single plan), every other kernel runs on the
+ * plan's own stream.  A plan's result is bit-identical to slrx_run on that
+ * plan (plans using the library eigensolver take their own path).  With
  * hip_stream: the plans run back to back on it, each as slrx_run would.
  * Returns once the work is enqueued; call slrx_sync on each plan. */
 slrx_status slrx_run_batch(slrx_plan* const* plans, int32_t n, void* hip_stream);
@@ -192,11 +192,11 @@ slrx_status slrx_step_cg(slrx_plan* plan, const void* E, int32_t n_cg);
  * engine steps, when fewer than max_slots requests are active and their
  * device footprint (slrx_footprint) fits the remaining budget_bytes.  One
  * scheduler thread advances every active request by one outer iteration per
- * step, exactly as slrx_run_batch does (a batched eigen-decomposition per
- * group of equal Gram size s <= 640, other kernels on each request's own
- * stream); a request arriving while others run joins at the next step.  A
- * request's result depends only on the request: it equals slrx_run_batch on
- * that plan alone, bit for bit.  hip_stream is ignored.
+ * step, exactly as slrx_run_batch does; a request arriving while others run
+ * joins at the next step.  A request's result is bit-identical to slrx_run on
+ * the same data.  The engine's shared eigen-decomposition buffers (about
+ * 72 s^2 bytes per active request of Gram size s) are not charged to the
+ * budget.  hip_stream is ignored.
  * Thread-safe: any thread may submit, poll, wait or fetch. */
 typedef struct {
   double t_submit, t_admit, t_done; /* steady-clock seconds */

@@ -341,8 +341,8 @@ class Plan:
 
 def run_batch(plans, stream=None, sync=True):
     """Run independent plans: in lock step on the engine when stream is None
-    (batched eigen-decompositions per Gram size, other kernels on each plan's
-    own stream), else one after another on the given stream."""
+    (one eigen-decomposition launch sequence per Gram size, other kernels on
+    each plan's own stream), else one after another on the given stream."""
     arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
     st = None if stream is None else ctypes.c_void_p(int(stream))
     _check(lib().slrx_run_batch(arr, len(plans), st))

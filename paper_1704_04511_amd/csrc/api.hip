@@ -593,8 +593,8 @@ extern "C" slrx_status slrx_get_stats(slrx_plan* pl, slrx_stats* out) {
 }
 
 // Several independent problems.  With hip_stream NULL they run in lock step
-// on the engine (one outer iteration of every problem per step, a batched
-// eigen-decomposition shared by equal Gram sizes, every other kernel on the
+// on the engine (one outer iteration of every problem per step, one launch
+// sequence of the eigen-decomposition per Gram size, every other kernel on the
 // problem's own stream); the call returns once all work is enqueued.  With a
 // stream the plans run one after another on it, each as slrx_run would.
 static std::mutex g_batch_mu;
@@ -696,20 +696,7 @@ extern "C" slrx_status slrx_step_tdeig(slrx_plan* pl, const double* D, const dou
   if (s > dc_max_n()) return fail(SLRX_EINVAL, "s = %d exceeds the divide-and-conquer limit %d", s, dc_max_n());
   STCHK(copy_in(pl, pl->lam, D, (size_t)s * sizeof(double), mem));
   if (s > 1) STCHK(copy_in(pl, pl->ework, E, (size_t)(s - 1) * sizeof(double), mem));
-  TdArgs td;
-  td.n = s;
-  td.D = pl->lam;
-  td.E = pl->ework;
-  td.Z = pl->UZ;
-  td.Q = pl->VT;
-  td.Qs = pl->VT + (size_t)s * s;
-  td.U = pl->Hre;
-  td.nodes = pl->dc_tree;
-  td.level_start = pl->dc_level_start;
-  td.node_sizes = pl->dc_node_sizes;
-  td.ws_i = pl->dc_wsi;
-  td.ws_d = pl->dc_wsd;
-  HIPCHK(launch_tdeig(td, pl->stream));
+  HIPCHK(eigh_tdeig(plan_eigh_bufs(pl), pl->stream));
   STCHK(copy_out(pl, lam_out, pl->lam, (size_t)s * sizeof(double), mem));
   STCHK(copy_out(pl, Z_out, pl->UZ, (size_t)s * s * sizeof(double2), mem));
   HIPCHK(hipStreamSynchronize(pl->stream));

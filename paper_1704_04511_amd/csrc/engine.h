@@ -1,28 +1,32 @@
 // Lock-step engine for many reconstructions (see engine.hip).
 #pragma once
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
+#include <map>
 #include <vector>
 
 #include "../../include/slrx.h"
+#include "plan.h"
 
 namespace slrx {
 
-// Workspace of the batched eigen-decomposition (own stream and handle).
+// Eigen-decomposition buffers for up to `cap` problems of size n, strided.
+struct EigGroup {
+  int n = 0, cap = 0;
+  void* mem = nullptr;  // one allocation holding every buffer below
+  EighBufs bufs;        // pointers into mem, strides for problem b
+  int* tree = nullptr;  // divide-and-conquer tree for n (device)
+  std::vector<int> level_start, node_sizes;
+  ~EigGroup();
+};
+
+// Shared state of the batched eigen-decompositions (own stream and events).
 struct BatchEig {
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;       // eigenpairs ready
-  hipEvent_t ev_free = nullptr;  // every consumer of the eigenpairs has run
+  hipEvent_t ev_free = nullptr;  // every reader of the group buffers has run
   bool have_free = false;
-  rocblas_handle handle = nullptr;
-  int cap_nb = 0;                // capacity in matrices
-  long cap_ss = 0;               // capacity in matrix elements (sum of s*s)
-  long cap_s = 0;                // capacity in eigenvalues (sum of s)
-  double2* A = nullptr;          // Gram matrices, then eigenvectors (column-major, one region per group)
-  double* D = nullptr;           // eigenvalues, ascending
-  double* E = nullptr;           // solver workspace
-  rocblas_int* info = nullptr;
+  std::map<int, EigGroup> groups;
   ~BatchEig();
 };
 

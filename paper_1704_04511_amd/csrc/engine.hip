@@ -1,18 +1,18 @@
 // Lock-step execution of many reconstructions (batch and continuous serving).
 //
 // Every active problem advances by one outer IRLS iteration per engine step.
-// Problems whose Gram matrices have the same size s <= kBatchEigMaxS share one
-// batched FP64 eigen-decomposition (rocSOLVER zheevd, strided batched over a
-// shared buffer); larger problems take the single-problem path (own Householder
-// tridiagonalisation).  The choice depends on s only, and the batched solver
-// treats every matrix independently, so each problem's result is the same
-// whatever else is in the batch.  The Gram matrix, weights, masks and CG of each
-// problem run on the problem's own stream, ordered against the shared
-// eigen-decomposition by events.  Problems may join between steps (each keeps
-// its own iteration index and epsilon schedule), which is what the server does.
+// Problems whose Gram matrices have the same size s share one launch sequence
+// of the eigen-decomposition chain (tridiagonalisation, divide and conquer,
+// back-transformation), each kernel covering all of them at once; the kernels
+// treat every problem independently with the same arithmetic as for a single
+// problem, so a result is bit-identical alone, in a batch and in the server.
+// The Gram matrix, weights, masks and CG of each problem run on the problem's
+// own stream, ordered against the shared eigen-decomposition by events.
+// Problems may join between steps (each keeps its own iteration index and
+// epsilon schedule), which is what the server does.  Problems that use the
+// library eigensolver take the single-problem path.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <map>
 #include <vector>
@@ -23,8 +23,6 @@
 
 using namespace slrx;
 
-// Largest Gram size solved in the batched eigen-decomposition.
-constexpr int kBatchEigMaxS = 640;
 
 #define HIPCHK(expr)                                                                         \
   do {                                                                                       \
@@ -40,48 +38,88 @@ constexpr int kBatchEigMaxS = 640;
     if (_s != SLRX_OK) return _s; \
   } while (0)
 
+slrx::EigGroup::~EigGroup() {
+  if (mem) (void)hipFree(mem);
+  if (tree) (void)hipFree(tree);
+}
+
 slrx::BatchEig::~BatchEig() {
   if (stream) (void)hipStreamSynchronize(stream);
-  if (handle) rocblas_destroy_handle(handle);
-  if (A) (void)hipFree(A);
-  if (D) (void)hipFree(D);
-  if (E) (void)hipFree(E);
-  if (info) (void)hipFree(info);
+  groups.clear();
   if (ev) (void)hipEventDestroy(ev);
   if (ev_free) (void)hipEventDestroy(ev_free);
   if (stream) (void)hipStreamDestroy(stream);
 }
 
-// Room for nb matrices of total size ss_total (elements) and s_total eigenvalues.
-static slrx_status be_reserve(BatchEig& be, int nb, long ss_total, long s_total) {
+static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Buffers for nb problems of size n (grown, never shrunk).
+static slrx_status group_reserve(BatchEig& be, int n, int nb, EigGroup*& out) {
   if (!be.stream) {
     HIPCHK(hipStreamCreateWithFlags(&be.stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&be.ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&be.ev_free, hipEventDisableTiming));
-    if (rocblas_create_handle(&be.handle) != rocblas_status_success)
-      return fail(SLRX_EDEVICE, "rocblas_create_handle failed");
-    if (rocblas_set_stream(be.handle, be.stream) != rocblas_status_success)
-      return fail(SLRX_EDEVICE, "rocblas_set_stream failed");
   }
-  if (nb > be.cap_nb || ss_total > be.cap_ss || s_total > be.cap_s) {
-    // every reader of the old buffers is ordered before be.stream's last work
-    HIPCHK(hipStreamSynchronize(be.stream));
-    if (be.A) (void)hipFree(be.A);
-    if (be.D) (void)hipFree(be.D);
-    if (be.E) (void)hipFree(be.E);
-    if (be.info) (void)hipFree(be.info);
-    be.A = nullptr; be.D = nullptr; be.E = nullptr; be.info = nullptr;
-    be.cap_nb = nb > be.cap_nb ? nb : be.cap_nb;
-    be.cap_ss = ss_total > be.cap_ss ? ss_total : be.cap_ss;
-    be.cap_s = s_total > be.cap_s ? s_total : be.cap_s;
-    if (hipMalloc(&be.A, (size_t)be.cap_ss * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&be.D, (size_t)be.cap_s * sizeof(double)) != hipSuccess ||
-        hipMalloc(&be.E, (size_t)be.cap_s * sizeof(double)) != hipSuccess ||
-        hipMalloc(&be.info, be.cap_nb * sizeof(rocblas_int)) != hipSuccess) {
-      be.cap_nb = 0; be.cap_ss = 0; be.cap_s = 0;
-      return fail(SLRX_ENOMEM, "batched eigen-decomposition workspace");
-    }
+  EigGroup& G = be.groups[n];
+  if (G.n != n) {  // first use of this size: the divide-and-conquer tree
+    G.n = n;
+    std::vector<int> nodes;
+    dc_build_tree(n, nodes, G.level_start);
+    G.node_sizes.resize(nodes.size() / 4);
+    for (size_t q = 0; q < nodes.size() / 4; ++q) G.node_sizes[q] = nodes[4 * q + 1];
+    if (hipMalloc(&G.tree, std::max<size_t>(nodes.size(), 4) * sizeof(int)) != hipSuccess)
+      return fail(SLRX_ENOMEM, "divide-and-conquer tree");
+    if (!nodes.empty())
+      HIPCHK(hipMemcpy(G.tree, nodes.data(), nodes.size() * sizeof(int), hipMemcpyHostToDevice));
   }
+  if (nb > G.cap) {
+    HIPCHK(hipStreamSynchronize(be.stream));  // every reader of the old buffers has finished
+    if (G.mem) (void)hipFree(G.mem);
+    G.mem = nullptr;
+    G.cap = 0;
+    const size_t nn = (size_t)n * n;
+    const size_t sA = al(nn * sizeof(double2)), sQ = al(3 * nn * sizeof(double));
+    const size_t sWi = al(dc_ws_ints(n) * sizeof(int)), sWd = al(dc_ws_doubles(n) * sizeof(double));
+    const size_t sB = al(bt_scratch_elems(n) * sizeof(double2));
+    const size_t sv = al((size_t)nb * n * sizeof(double2)), sd = al((size_t)nb * n * sizeof(double));
+    const size_t total = (size_t)nb * (3 * sA + sQ + sWi + sWd + sB) + 5 * sv + 2 * sd;
+    if (hipMalloc(&G.mem, total) != hipSuccess) return fail(SLRX_ENOMEM, "eigen-decomposition buffers (%zu bytes)", total);
+    char* p = (char*)G.mem;
+    auto take = [&](size_t b) {
+      char* q = p;
+      p += b;
+      return q;
+    };
+    EighBufs& e = G.bufs;
+    e.n = n;
+    e.A = (double2*)take(nb * sA);
+    e.V = (double2*)take(nb * sA);
+    e.Z = (double2*)take(nb * sA);
+    e.Q = (double*)take(nb * sQ);
+    e.Qs = e.Q + nn;
+    e.U = e.Q + 2 * nn;
+    e.wsi = (int*)take(nb * sWi);
+    e.wsd = (double*)take(nb * sWd);
+    e.bts = (double2*)take(nb * sB);
+    e.tau = (double2*)take(sv);
+    e.triv[0] = (double2*)take(sv);
+    e.triv[1] = (double2*)take(sv);
+    e.trip[0] = (double2*)take(sv);
+    e.trip[1] = (double2*)take(sv);
+    e.D = (double*)take(sd);
+    e.E = (double*)take(sd);
+    e.sA = (long)(sA / sizeof(double2));
+    e.sZ = e.sA;
+    e.sQ = (long)(sQ / sizeof(double));
+    e.s_wsi = (long)(sWi / sizeof(int));
+    e.s_wsd = (long)(sWd / sizeof(double));
+    e.s_bts = (long)(sB / sizeof(double2));
+    G.cap = nb;
+  }
+  G.bufs.tree = G.tree;
+  G.bufs.level_start = &G.level_start;
+  G.bufs.node_sizes = &G.node_sizes;
+  out = &G;
   return SLRX_OK;
 }
 
@@ -117,63 +155,45 @@ static slrx_status step_single(slrx_plan* pl) {
 
 slrx_status slrx::engine_step(const std::vector<slrx_plan*>& plans, BatchEig& be) {
   std::map<int, std::vector<slrx_plan*>> groups;
-  for (slrx_plan* pl : plans)
-    if (pl->it_next < pl->prm.n_irls) groups[pl->s()].push_back(pl);
-  // every batched group gets its own region of the shared buffers
-  int nb_total = 0;
-  long ss_total = 0, s_total = 0;
-  for (auto& kv : groups) {
-    if (kv.first > kBatchEigMaxS) continue;
-    nb_total += (int)kv.second.size();
-    ss_total += (long)kv.second.size() * kv.first * kv.first;
-    s_total += (long)kv.second.size() * kv.first;
+  for (slrx_plan* pl : plans) {
+    if (pl->it_next >= pl->prm.n_irls) continue;
+    if (pl->lib_eigh()) STCHK(step_single(pl));
+    else groups[pl->s()].push_back(pl);
   }
-  if (nb_total > 0) STCHK(be_reserve(be, nb_total, ss_total, s_total));
-  int ib = 0;
-  long off_ss = 0, off_s = 0;
+  bool used = false;
   for (auto& kv : groups) {
-    const int s = kv.first;
+    const int n = kv.first;
     std::vector<slrx_plan*>& g = kv.second;
     const int nb = (int)g.size();
-    if (s > kBatchEigMaxS) {
-      for (slrx_plan* pl : g) STCHK(step_single(pl));
-      continue;
-    }
-    const long ss = (long)s * s;
-    double2* A = be.A + off_ss;
-    double* D = be.D + off_s;
-    double* E = be.E + off_s;
-    rocblas_int* info = be.info + ib;
-    // Gram matrices into the shared buffer once the previous step's readers are done
+    EigGroup* G = nullptr;
+    STCHK(group_reserve(be, n, nb, G));
+    EighBufs e = G->bufs;
+    e.nb = nb;
+    // Gram matrices (row-major) into the group buffer once the previous step's readers are done
     for (int i = 0; i < nb; ++i) {
       slrx_plan* pl = g[i];
       if (be.have_free) HIPCHK(hipStreamWaitEvent(pl->stream, be.ev_free, 0));
-      STCHK(step_gram(pl, true, A + (size_t)i * ss));
+      STCHK(step_gram(pl, false, e.A + (size_t)i * e.sA));
       HIPCHK(hipEventRecord(pl->ev_step, pl->stream));
       HIPCHK(hipStreamWaitEvent(be.stream, pl->ev_step, 0));
     }
-    rocblas_status rs = rocsolver_zheevd_strided_batched(
-        be.handle, rocblas_evect_original, rocblas_fill_lower, s, (rocblas_double_complex*)A, s, ss, D, s, E, s,
-        info, nb);
-    if (rs != rocblas_status_success)
-      return fail(SLRX_EDEVICE, "rocsolver_zheevd_strided_batched failed (status %d)", (int)rs);
+    HIPCHK(eigh_tri(e, be.stream));
+    HIPCHK(eigh_tdeig(e, be.stream));
+    HIPCHK(eigh_backtr(e, be.stream));
     HIPCHK(hipEventRecord(be.ev, be.stream));
     for (int i = 0; i < nb; ++i) {
       slrx_plan* pl = g[i];
       const int it = pl->it_next;
       HIPCHK(hipStreamWaitEvent(pl->stream, be.ev, 0));
-      HIPCHK(hipMemcpyAsync(pl->info + it, info + i, sizeof(rocblas_int), hipMemcpyDeviceToDevice, pl->stream));
-      STCHK(step_weights(pl, it, it == 0, pl->prm.gamma, A + (size_t)i * ss, D + (size_t)i * s));
+      STCHK(step_weights(pl, it, it == 0, pl->prm.gamma, e.Z + (size_t)i * e.sZ, e.D + (size_t)i * n));
       HIPCHK(hipEventRecord(pl->ev_step, pl->stream));
       HIPCHK(hipStreamWaitEvent(be.stream, pl->ev_step, 0));
       STCHK(run_cg(pl, pl->prm.n_cg, it));
       pl->it_next = it + 1;
     }
-    ib += nb;
-    off_ss += (long)nb * ss;
-    off_s += (long)nb * s;
+    used = true;
   }
-  if (nb_total > 0) {
+  if (used) {
     HIPCHK(hipEventRecord(be.ev_free, be.stream));
     be.have_free = true;
   }

@@ -43,23 +43,40 @@ struct BtArgs {
   double2* Gp;        // Gram partials of the blocks
   double2* Tb;        // T of the blocks, column-major nb x nb each
   double2* Wp;        // V^H Z partials, column-major nb x n each
+  const double2* tau; // reflector scalars, n
+  long sV, sY, sZ, sW;  // strides between the problems of a batch (sW: scratch)
 };
 
+// The arguments of problem b of a batch.
+SLRX_DEV BtArgs bt_at(BtArgs a, int b) {
+  a.Vx += b * a.sV;
+  a.Yx += b * a.sY;
+  a.Z += b * a.sZ;
+  a.Gp += b * a.sW;
+  a.Tb += b * a.sW;
+  a.Wp += b * a.sW;
+  a.tau += (long)b * a.n;
+  return a;
+}
+
 template <int KIND>
-__global__ __launch_bounds__(256) void k_bt_gemm(BtArgs a) {
+__global__ __launch_bounds__(256) void k_bt_gemm(BtArgs a0, int zper) {
+  // blockIdx.z = problem * zper + (split / block index within the problem)
+  const BtArgs a = bt_at(a0, blockIdx.z / zper);
+  const int bz = blockIdx.z % zper;
   __shared__ double Lar[kKC][kTM + 1], Lai[kKC][kTM + 1];  // padded against bank conflicts
   __shared__ double Lbr[kKC][kTN + 1], Lbi[kKC][kTN + 1];
   const int n = a.n;
   int g, z;
   if (KIND == BT_GRAM) {
-    g = blockIdx.z / a.nsplit;
-    z = blockIdx.z % a.nsplit;
+    g = bz / a.nsplit;
+    z = bz % a.nsplit;
   } else if (KIND == BT_YMAT) {
-    g = blockIdx.z;
+    g = bz;
     z = 0;
   } else {
     g = a.g;
-    z = blockIdx.z;
+    z = bz;
   }
   const int k0 = kBtNb * g, r0 = k0 + 1, m = n - r0;
   const int nr = min(kBtNb, n - 1 - k0);
@@ -176,7 +193,8 @@ __global__ __launch_bounds__(256) void k_bt_gemm(BtArgs a) {
 
 // W = sum of the split-K partials of V^H Z, in a fixed order, into the slot
 // after the partials.
-__global__ void k_bt_wsum(BtArgs a) {
+__global__ void k_bt_wsum(BtArgs a0) {
+  const BtArgs a = bt_at(a0, blockIdx.y);
   const long o = (long)blockIdx.x * 256 + threadIdx.x;
   const long len = (long)kBtNb * a.n;
   if (o >= len) return;
@@ -191,7 +209,8 @@ __global__ void k_bt_wsum(BtArgs a) {
 
 // Reflectors in explicit form, in place: column k of the n x n column-major
 // matrix becomes v_k (zero above row k+1, one at row k+1; the last column is zero).
-__global__ void k_bt_explicit(int n, double2* V) {
+__global__ void k_bt_explicit(int n, double2* V0, long sV) {
+  double2* V = V0 + blockIdx.y * sV;
   const long o = (long)blockIdx.x * 256 + threadIdx.x;
   if (o >= (long)n * n) return;
   const int R = (int)(o % n), k = (int)(o / n);
@@ -207,7 +226,9 @@ __global__ void k_bt_explicit(int n, double2* V) {
 // i(i-1)/2 + l) and is overwritten level by level with X = G_AB T_B.  Indices
 // beyond the block's reflectors get tau = 0 and G = 0, so their rows and
 // columns of T are zero.
-__global__ __launch_bounds__(256) void k_bt_tmat(BtArgs a, const double2* tau) {
+__global__ __launch_bounds__(256) void k_bt_tmat(BtArgs a0) {
+  const BtArgs a = bt_at(a0, blockIdx.y);
+  const double2* tau = a.tau;
   __shared__ double2 T[kBtNb * (kBtNb + 1) / 2];
   __shared__ double2 G[kBtNb * (kBtNb - 1) / 2];
   const int g = blockIdx.x, tid = threadIdx.x;
@@ -289,7 +310,7 @@ size_t bt_scratch_elems(int n) {
 }
 
 hipError_t launch_backtransform(const BackTrArgs& b, hipStream_t s) {
-  const int n = b.n;
+  const int n = b.n, nb = b.nb;
   if (n < 2) return hipSuccess;  // Q = I
   const int ng = bt_nblocks(n);
   BtArgs a{};
@@ -298,24 +319,29 @@ hipError_t launch_backtransform(const BackTrArgs& b, hipStream_t s) {
   a.Vx = b.V;
   a.Yx = b.Y;
   a.Z = b.Z;
+  a.tau = b.tau;
   a.Tb = b.scratch;
   a.Gp = b.scratch + (size_t)ng * kBtNb * kBtNb;
   a.Wp = a.Gp + (size_t)ng * kBtNb * kBtNb * kBtSplitG;
-  k_bt_explicit<<<(unsigned)(((long)n * n + 255) / 256), 256, 0, s>>>(n, b.V);
+  a.sV = b.sV;
+  a.sY = b.sY;
+  a.sZ = b.sZ;
+  a.sW = b.s_scratch;
+  k_bt_explicit<<<dim3((unsigned)(((long)n * n + 255) / 256), nb), 256, 0, s>>>(n, b.V, b.sV);
   const int mt = (n - 1 + kTM - 1) / kTM;  // row tiles of the largest block (m = n - 1)
   a.nsplit = kBtSplitG;
-  k_bt_gemm<BT_GRAM><<<dim3(kBtNb / kTN, 1, ng * kBtSplitG), 256, 0, s>>>(a);
-  k_bt_tmat<<<ng, 256, 0, s>>>(a, b.tau);
+  k_bt_gemm<BT_GRAM><<<dim3(kBtNb / kTN, 1, nb * ng * kBtSplitG), 256, 0, s>>>(a, ng * kBtSplitG);
+  k_bt_tmat<<<dim3(ng, nb), 256, 0, s>>>(a);
   a.nsplit = 1;
-  k_bt_gemm<BT_YMAT><<<dim3(kBtNb / kTN, mt, ng), 256, 0, s>>>(a);
+  k_bt_gemm<BT_YMAT><<<dim3(kBtNb / kTN, mt, nb * ng), 256, 0, s>>>(a, ng);
   const int nt = (n + kTN - 1) / kTN;
   a.nsplit = kBtSplitW;
   for (int g = ng - 1; g >= 0; --g) {
     a.g = g;
     const int m = n - (kBtNb * g + 1);
-    k_bt_gemm<BT_APPLY_W><<<dim3(nt, 1, kBtSplitW), 256, 0, s>>>(a);
-    k_bt_wsum<<<(unsigned)(((long)kBtNb * n + 255) / 256), 256, 0, s>>>(a);
-    k_bt_gemm<BT_APPLY_Z><<<dim3(nt, (m + kTM - 1) / kTM, 1), 256, 0, s>>>(a);
+    k_bt_gemm<BT_APPLY_W><<<dim3(nt, 1, nb * kBtSplitW), 256, 0, s>>>(a, kBtSplitW);
+    k_bt_wsum<<<dim3((unsigned)(((long)kBtNb * n + 255) / 256), nb), 256, 0, s>>>(a);
+    k_bt_gemm<BT_APPLY_Z><<<dim3(nt, (m + kTM - 1) / kTM, nb), 256, 0, s>>>(a, 1);
   }
   return hipGetLastError();
 }

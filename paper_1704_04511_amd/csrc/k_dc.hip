@@ -54,7 +54,25 @@ struct DcArgs {
   double* ws_d;       // 7 n doubles: dl, zl, rot_c, rot_s, tau, zhat, (spare)
   int* ws_node;       // 4 ints per node: k, nrot, 0, 0
   int* ws_orig;       // n ints: pole each root is measured from
+  double2* Z;         // output eigenvectors, complex column-major n x n
+  int count;          // nodes in the level being merged
+  long sQ, sZ, s_wsi, s_wsd;  // strides between the problems of a batch
 };
+
+// The arguments of problem b of a batch (D, E have stride n).
+SLRX_DEV DcArgs dc_at(DcArgs a, int b) {
+  a.D += (long)b * a.n;
+  a.E += (long)b * a.n;
+  a.Q += b * a.sQ;
+  a.Qs += b * a.sQ;
+  a.U += b * a.sQ;
+  a.ws_i += b * a.s_wsi;
+  a.ws_node += b * a.s_wsi;
+  a.ws_orig += b * a.s_wsi;
+  a.ws_d += b * a.s_wsd;
+  a.Z += b * a.sZ;
+  return a;
+}
 
 SLRX_DEV double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -70,7 +88,8 @@ SLRX_DEV double wave_max(double v) {
 }
 
 // Tear every coupling off the diagonal; leaves (single entries) start with Q = 1.
-__global__ void k_dc_init(DcArgs a) {
+__global__ void k_dc_init(DcArgs a0) {
+  const DcArgs a = dc_at(a0, blockIdx.y);
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= a.n) return;
   double d = a.D[i];
@@ -82,7 +101,8 @@ __global__ void k_dc_init(DcArgs a) {
 
 // Sort, z, deflation of one merge (one workgroup per node).
 constexpr int kDefNT = 1024;
-__global__ __launch_bounds__(kDefNT) void k_dc_deflate(DcArgs a) {
+__global__ __launch_bounds__(kDefNT) void k_dc_deflate(DcArgs a0) {
+  const DcArgs a = dc_at(a0, blockIdx.y);
   extern __shared__ double lds[];
   const int4 nd = a.nodes[a.node0 + blockIdx.x];
   const int s = nd.x, m = nd.y, n1 = nd.z, n = a.n;
@@ -241,7 +261,8 @@ __global__ __launch_bounds__(kDefNT) void k_dc_deflate(DcArgs a) {
 
 // Columns of diag(Q1, Q2) in sorted order, deflation rotations, then the final
 // column order (non-deflated first); one wave per row of the node.
-__global__ __launch_bounds__(256) void k_dc_gather(DcArgs a, int mmax) {
+__global__ __launch_bounds__(256) void k_dc_gather(DcArgs a0, int mmax) {
+  const DcArgs a = dc_at(a0, blockIdx.z);
   extern __shared__ double lds[];
   const int node = a.node0 + blockIdx.y;
   const int4 nd = a.nodes[node];
@@ -325,7 +346,8 @@ SLRX_DEV double bit_mid(double x0, double x1, double sign) {
 // takes the model's root; a step that leaves the bracket or does not halve the
 // previous step is replaced by bisection of the bit patterns, so the iteration
 // always ends.  It stops when |f| is within the rounding of its terms.
-__global__ __launch_bounds__(256) void k_dc_secular(DcArgs a) {
+__global__ __launch_bounds__(256) void k_dc_secular(DcArgs a0) {
+  const DcArgs a = dc_at(a0, blockIdx.z);
   const int node = a.node0 + blockIdx.y;
   const int4 nd = a.nodes[node];
   const int s = nd.x, n = a.n;
@@ -421,7 +443,8 @@ __global__ __launch_bounds__(256) void k_dc_secular(DcArgs a) {
 }
 
 // z_hat_i^2 = (lambda_i - d_i) / rho * prod_{j != i} (lambda_j - d_i) / (d_j - d_i); one wave per i.
-__global__ __launch_bounds__(256) void k_dc_zhat(DcArgs a) {
+__global__ __launch_bounds__(256) void k_dc_zhat(DcArgs a0) {
+  const DcArgs a = dc_at(a0, blockIdx.z);
   const int node = a.node0 + blockIdx.y;
   const int4 nd = a.nodes[node];
   const int s = nd.x, n = a.n;
@@ -444,7 +467,8 @@ __global__ __launch_bounds__(256) void k_dc_zhat(DcArgs a) {
 }
 
 // u_j = z_hat / (d - lambda_j), normalised; one wave per column j (column-major U block).
-__global__ __launch_bounds__(256) void k_dc_vectors(DcArgs a) {
+__global__ __launch_bounds__(256) void k_dc_vectors(DcArgs a0) {
+  const DcArgs a = dc_at(a0, blockIdx.z);
   const int node = a.node0 + blockIdx.y;
   const int4 nd = a.nodes[node];
   const int s = nd.x, n = a.n;
@@ -468,11 +492,12 @@ __global__ __launch_bounds__(256) void k_dc_vectors(DcArgs a) {
 
 // Q_node(:, 0:k) = Qs(:, 0:k) U, Q_node(:, k:m) = Qs(:, k:m): 64 x 64 tiles,
 // four waves of 32 x 32, f64 16x16x4 MFMA, K staged through LDS in chunks of 16.
-__global__ __launch_bounds__(256) void k_dc_gemm(DcArgs a) {
+__global__ __launch_bounds__(256) void k_dc_gemm(DcArgs a0) {
   constexpr int TB = 64, KC = 16;
   __shared__ double La[KC][TB + 1];
   __shared__ double Lb[KC][TB + 1];
-  const int node = a.node0 + blockIdx.z;
+  const DcArgs a = dc_at(a0, blockIdx.z / a0.count);
+  const int node = a.node0 + blockIdx.z % a0.count;
   const int4 nd = a.nodes[node];
   const int s = nd.x, m = nd.y, n = a.n;
   const int k = a.ws_node[4 * node];
@@ -536,7 +561,8 @@ __global__ __launch_bounds__(256) void k_dc_gemm(DcArgs a) {
 }
 
 // Ascending eigenvalues and their permutation (one workgroup).
-__global__ __launch_bounds__(1024) void k_dc_sort(DcArgs a) {
+__global__ __launch_bounds__(1024) void k_dc_sort(DcArgs a0) {
+  const DcArgs a = dc_at(a0, blockIdx.x);
   extern __shared__ double lds[];
   const int n = a.n;
   for (int i = threadIdx.x; i < n; i += 1024) lds[i] = a.D[i];
@@ -559,7 +585,9 @@ __global__ __launch_bounds__(1024) void k_dc_sort(DcArgs a) {
 }
 
 // Z(r, c) = Q(r, perm(c)) as complex, column-major; 64 x 64 tiles through LDS.
-__global__ __launch_bounds__(256) void k_dc_convert(DcArgs a, double2* Z) {
+__global__ __launch_bounds__(256) void k_dc_convert(DcArgs a0) {
+  const DcArgs a = dc_at(a0, blockIdx.z);
+  double2* Z = a.Z;
   __shared__ double tile[64][65];
   const int n = a.n;
   const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
@@ -629,12 +657,18 @@ hipError_t launch_tdeig(const TdArgs& t, hipStream_t st) {
   a.Q = t.Q;
   a.Qs = t.Qs;
   a.U = t.U;
+  a.Z = t.Z;
   a.nodes = (const int4*)t.nodes;
   a.ws_i = t.ws_i;
   a.ws_node = t.ws_i + 4 * n;
   a.ws_orig = t.ws_i + 8 * n;
   a.ws_d = t.ws_d;
-  k_dc_init<<<(n + 255) / 256, 256, 0, st>>>(a);
+  a.sQ = t.sQ;
+  a.sZ = t.sZ;
+  a.s_wsi = t.s_wsi;
+  a.s_wsd = t.s_wsd;
+  const int nb = t.nb;
+  k_dc_init<<<dim3((n + 255) / 256, nb), 256, 0, st>>>(a);
   const int nlev = (int)t.level_start.size() - 1;
   for (int L = 0; L < nlev; ++L) {
     const int first = t.level_start[L], count = t.level_start[L + 1] - first;
@@ -642,15 +676,16 @@ hipError_t launch_tdeig(const TdArgs& t, hipStream_t st) {
     int mmax = 0;
     for (int q = first; q < first + count; ++q) mmax = std::max(mmax, t.node_sizes[q]);
     a.node0 = first;
-    k_dc_deflate<<<count, kDefNT, (size_t)mmax * (4 * sizeof(double) + 3 * sizeof(int)), st>>>(a);
-    k_dc_gather<<<dim3((mmax + 3) / 4, count), 256, (size_t)4 * mmax * sizeof(double), st>>>(a, mmax);
-    k_dc_secular<<<dim3((mmax + 3) / 4, count), 256, 0, st>>>(a);
-    k_dc_zhat<<<dim3((mmax + 3) / 4, count), 256, 0, st>>>(a);
-    k_dc_vectors<<<dim3((mmax + 3) / 4, count), 256, 0, st>>>(a);
-    k_dc_gemm<<<dim3((mmax + 63) / 64, (mmax + 63) / 64, count), 256, 0, st>>>(a);
+    a.count = count;
+    k_dc_deflate<<<dim3(count, nb), kDefNT, (size_t)mmax * (4 * sizeof(double) + 3 * sizeof(int)), st>>>(a);
+    k_dc_gather<<<dim3((mmax + 3) / 4, count, nb), 256, (size_t)4 * mmax * sizeof(double), st>>>(a, mmax);
+    k_dc_secular<<<dim3((mmax + 3) / 4, count, nb), 256, 0, st>>>(a);
+    k_dc_zhat<<<dim3((mmax + 3) / 4, count, nb), 256, 0, st>>>(a);
+    k_dc_vectors<<<dim3((mmax + 3) / 4, count, nb), 256, 0, st>>>(a);
+    k_dc_gemm<<<dim3((mmax + 63) / 64, (mmax + 63) / 64, count * nb), 256, 0, st>>>(a);
   }
-  k_dc_sort<<<1, 1024, (size_t)n * sizeof(double), st>>>(a);
-  k_dc_convert<<<dim3((n + 63) / 64, (n + 63) / 64), 256, 0, st>>>(a, t.Z);
+  k_dc_sort<<<nb, 1024, (size_t)n * sizeof(double), st>>>(a);
+  k_dc_convert<<<dim3((n + 63) / 64, (n + 63) / 64, nb), 256, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -144,6 +144,8 @@ struct BackTrArgs {
   double2* Z;           // in: tridiagonal eigenvectors; out: eigenvectors of the Hermitian matrix
   const double2* tau;   // n
   double2* scratch;     // bt_scratch_elems(n)
+  int nb = 1;           // problems of equal n: problem b uses V + b sV, Y + b sY, Z + b sZ,
+  long sV = 0, sY = 0, sZ = 0, s_scratch = 0;  // tau + b n, scratch + b s_scratch
 };
 hipError_t launch_backtransform(const BackTrArgs& a, hipStream_t s);
 size_t bt_scratch_elems(int n);
@@ -164,6 +166,9 @@ struct TdArgs {
   std::vector<int> node_sizes;   // size of every node, host copy
   int* ws_i;                     // dc_ws_ints(n)
   double* ws_d;                  // dc_ws_doubles(n)
+  int nb = 1;                    // problems of equal n solved together; problem b uses
+  long sQ = 0, sZ = 0;           // D + b n, E + b n, Q/Qs/U + b sQ, Z + b sZ,
+  long s_wsi = 0, s_wsd = 0;     // ws_i + b s_wsi, ws_d + b s_wsd
 };
 void dc_build_tree(int n, std::vector<int>& nodes, std::vector<int>& level_start);
 size_t dc_ws_ints(int n);

@@ -99,6 +99,24 @@ slrx_status load_masks(slrx_plan* pl, const float2* E_dev);
 slrx_status store_masks(slrx_plan* pl);
 slrx_status step_gram(slrx_plan* pl, bool colmajor = false, double2* R_out = nullptr);
 slrx_status step_eigh(slrx_plan* pl, int it);
+// Device buffers of the own eigen-decomposition chain for nb problems of equal
+// size n (problem b at the given strides; D, E, tau, triv, trip at stride n).
+struct EighBufs {
+  int n = 0, nb = 1;
+  double2 *A = nullptr, *V = nullptr, *Z = nullptr, *tau = nullptr, *bts = nullptr;
+  double2* triv[2] = {nullptr, nullptr};
+  double2* trip[2] = {nullptr, nullptr};
+  double *D = nullptr, *E = nullptr, *Q = nullptr, *Qs = nullptr, *U = nullptr, *wsd = nullptr;
+  int* wsi = nullptr;
+  const int* tree = nullptr;
+  const std::vector<int>* level_start = nullptr;
+  const std::vector<int>* node_sizes = nullptr;
+  long sA = 0, sZ = 0, sQ = 0, s_wsi = 0, s_wsd = 0, s_bts = 0;
+};
+EighBufs plan_eigh_bufs(slrx_plan* pl);
+hipError_t eigh_tri(const EighBufs& e, hipStream_t s);     // Gram in A (row-major) -> D, E, tau, V
+hipError_t eigh_tdeig(const EighBufs& e, hipStream_t s);   // D, E -> eigenvalues D, vectors Z
+hipError_t eigh_backtr(const EighBufs& e, hipStream_t s);  // Z <- Q Z (A used as workspace)
 slrx_status dc_prepare(slrx_plan* pl);
 slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma, const double2* U = nullptr,
                          const double* lamv = nullptr);

@@ -4,16 +4,15 @@
 // steps: as soon as fewer than max_slots requests are active and a request's
 // device footprint fits the remaining HBM budget.  One scheduler thread drives
 // the lock-step engine: each step advances every active request by one outer
-// IRLS iteration, with one batched eigen-decomposition per group of equal
-// filter size and all other kernels on each request's own stream.  A request
+// IRLS iteration, with one launch sequence of the eigen-decomposition per
+// group of equal Gram size and all other kernels on each request's own stream.  A request
 // that arrives while others run joins at the next step, with its own iteration
 // count and epsilon schedule.  The scheduler keeps one step in flight ahead of
 // the device, so admissions take effect within about one step.  When a request
 // finishes, its images are copied to host memory and its budget share is
 // released at once; its plan is kept idle for the next request of the same
 // shape and evicted when the budget is needed.  A result depends only on the
-// request (the eigensolver is chosen by filter size alone), not on what runs
-// beside it.
+// request, not on what runs beside it (bit-identical to running it alone).
 #include <hip/hip_runtime.h>
 
 #include <chrono>

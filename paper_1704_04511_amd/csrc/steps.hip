@@ -104,6 +104,87 @@ slrx_status slrx::dc_prepare(slrx_plan* pl) {
   return SLRX_OK;
 }
 
+EighBufs slrx::plan_eigh_bufs(slrx_plan* pl) {
+  const int s = pl->s();
+  EighBufs e;
+  e.n = s;
+  e.nb = 1;
+  e.A = pl->Aw;
+  e.V = pl->Rm;
+  e.Z = pl->UZ;
+  e.tau = pl->tau;
+  e.triv[0] = pl->triv;
+  e.triv[1] = pl->triv + s;
+  e.trip[0] = pl->trip;
+  e.trip[1] = pl->trip + s;
+  e.bts = pl->bts;
+  e.D = pl->lam;
+  e.E = pl->ework;
+  e.Q = pl->VT;  // VT and Hre are free until the weights are formed
+  e.Qs = pl->VT + (size_t)s * s;
+  e.U = pl->Hre;
+  e.wsd = pl->dc_wsd;
+  e.wsi = pl->dc_wsi;
+  e.tree = pl->dc_tree;
+  e.level_start = &pl->dc_level_start;
+  e.node_sizes = &pl->dc_node_sizes;
+  return e;
+}
+
+hipError_t slrx::eigh_tri(const EighBufs& e, hipStream_t st) {
+  TriArgs ta{};
+  ta.n = e.n;
+  ta.Aw = e.A;
+  ta.Vst = e.V;
+  ta.strideA = e.sA;
+  ta.D = e.D;
+  ta.E = e.E;
+  ta.tau = e.tau;
+  ta.vbuf[0] = e.triv[0];
+  ta.vbuf[1] = e.triv[1];
+  ta.pbuf[0] = e.trip[0];
+  ta.pbuf[1] = e.trip[1];
+  return launch_tridiag(ta, e.nb, st);
+}
+
+hipError_t slrx::eigh_tdeig(const EighBufs& e, hipStream_t st) {
+  TdArgs td;
+  td.n = e.n;
+  td.D = e.D;
+  td.E = e.E;
+  td.Z = e.Z;
+  td.Q = e.Q;
+  td.Qs = e.Qs;
+  td.U = e.U;
+  td.nodes = e.tree;
+  td.level_start = *e.level_start;
+  td.node_sizes = *e.node_sizes;
+  td.ws_i = e.wsi;
+  td.ws_d = e.wsd;
+  td.nb = e.nb;
+  td.sQ = e.sQ;
+  td.sZ = e.sZ;
+  td.s_wsi = e.s_wsi;
+  td.s_wsd = e.s_wsd;
+  return launch_tdeig(td, st);
+}
+
+hipError_t slrx::eigh_backtr(const EighBufs& e, hipStream_t st) {
+  BackTrArgs bt{};
+  bt.n = e.n;
+  bt.V = e.V;
+  bt.Y = e.A;  // free once the reduction is done
+  bt.Z = e.Z;
+  bt.tau = e.tau;
+  bt.scratch = e.bts;
+  bt.nb = e.nb;
+  bt.sV = e.sA;
+  bt.sY = e.sA;
+  bt.sZ = e.sZ;
+  bt.s_scratch = e.s_bts;
+  return launch_backtransform(bt, st);
+}
+
 slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
   const int s = pl->s();
   rocblas_int* info = pl->info + (it < 0 ? SLRX_MAX_IRLS : it);
@@ -114,50 +195,19 @@ slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
     if (rs != rocblas_status_success) return fail(SLRX_EDEVICE, "rocsolver_zheevd failed (status %d)", (int)rs);
     return SLRX_OK;
   }
+  if (pl->dc_tree_n != s) return fail(SLRX_ESTATE, "divide-and-conquer tree not built for s = %d", s);
+  const EighBufs e = plan_eigh_bufs(pl);
   {
     KTimer kt(pl, SLRX_K_TRI);
-    TriArgs ta{};
-    ta.n = s;
-    ta.Aw = pl->Aw;
-    ta.Vst = pl->Rm;
-    ta.strideA = (long)s * s;
-    ta.D = pl->lam;
-    ta.E = pl->ework;
-    ta.tau = pl->tau;
-    ta.vbuf[0] = pl->triv;
-    ta.vbuf[1] = pl->triv + s;
-    ta.pbuf[0] = pl->trip;
-    ta.pbuf[1] = pl->trip + s;
-    HIPCHK(launch_tridiag(ta, 1, pl->stream));
+    HIPCHK(eigh_tri(e, pl->stream));
   }
   {
     KTimer kt(pl, SLRX_K_TDEIG);
-    if (pl->dc_tree_n != s) return fail(SLRX_ESTATE, "divide-and-conquer tree not built for s = %d", s);
-    TdArgs td;
-    td.n = s;
-    td.D = pl->lam;
-    td.E = pl->ework;
-    td.Z = pl->UZ;
-    td.Q = pl->VT;  // VT and Hre are free until the weights are formed
-    td.Qs = pl->VT + (size_t)s * s;
-    td.U = pl->Hre;
-    td.nodes = pl->dc_tree;
-    td.level_start = pl->dc_level_start;
-    td.node_sizes = pl->dc_node_sizes;
-    td.ws_i = pl->dc_wsi;
-    td.ws_d = pl->dc_wsd;
-    HIPCHK(launch_tdeig(td, pl->stream));
+    HIPCHK(eigh_tdeig(e, pl->stream));
   }
   {
     KTimer kt(pl, SLRX_K_BACKTR);
-    BackTrArgs bt{};
-    bt.n = s;
-    bt.V = pl->Rm;
-    bt.Y = pl->Aw;  // free once the reduction is done
-    bt.Z = pl->UZ;
-    bt.tau = pl->tau;
-    bt.scratch = pl->bts;
-    HIPCHK(launch_backtransform(bt, pl->stream));
+    HIPCHK(eigh_backtr(e, pl->stream));
   }
   return SLRX_OK;
 }
