@@ -13,6 +13,8 @@
 //     of LAPACK's zlarfg);
 //   * on its rows i > k: applies the pending rank-2 update and accumulates
 //     p_i = sum_j A_ij v_j for the next launch.
+// The last columns, once the trailing block fits in the LDS of one workgroup,
+// are reduced in a single launch (k_tri_tail).
 // The working matrix Aw is full (both triangles) and row-major; reflectors are
 // stored as LAPACK's zhetrd (lower) stores them: v(k+2:n) in column k of the
 // column-major matrix Vst below the subdiagonal, tau(k), diagonal D, real
@@ -221,7 +223,155 @@ __global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
   if (lane == 0) pout[my_row] = acc;
 }
 
+// The last kTriTail columns in one launch: the trailing block (rows and columns
+// k0..n-1) is small enough for the LDS of one workgroup, so its columns need
+// only block barriers instead of launches.  First the pending update of
+// reflector k0-1 is applied to the block, then each column is reduced as in
+// k_tri_step (same reflector convention, same outputs), the rank-2 update
+// applied to the whole block.  The outputs are kept in LDS and written at the
+// end: a barrier waits for the wave's outstanding stores.
+constexpr int kTriTail = 64;
+constexpr int kTailNT = 256;
+
+// Sum over the 64 lanes of a wave, every lane gets the total (fixed order).
+SLRX_DEV double2 wave_sum2(double2 v) {
+  for (int off = 1; off < 64; off <<= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(kTailNT) void k_tri_tail(TriArgs a, int k0) {
+  extern __shared__ double2 sm[];
+  __shared__ double2 sc[4];  // tau, scale, d; beta in sc[3].x
+  const int n = a.n, L = n - k0;
+  const int b = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double2* B = sm;           // L x L block, row-major, B[i][j] = A(k0 + i, k0 + j)
+  double2* vv = B + L * L;   // reflector
+  double2* pw = vv + L;      // A v
+  double2* Vl = pw + L;      // reflectors of the block, column kk at Vl[kk * L]
+  double2* tl = Vl + L * L;  // tau
+  double* Dl = (double*)(tl + L);
+  double* El = Dl + L;
+  const double2* Aw = a.Aw + (size_t)b * a.strideA;
+  double2* Vst = a.Vst + (size_t)b * a.strideA;
+  double* D = a.D + (size_t)b * n;
+  double* E = a.E + (size_t)b * n;
+  double2* taus = a.tau + (size_t)b * n;
+  const double2 zero = make_double2(0.0, 0.0);
+  for (int e = tid; e < L * L; e += kTailNT) B[e] = Aw[(size_t)(k0 + e / L) * n + k0 + e % L];
+  if (k0 > 0) {  // pending update of reflector k0-1: w = tau p + c (p^H v) v
+    const double2* vprev = a.vbuf[(k0 + 1) & 1] + (size_t)b * n + k0;
+    const double2* pprev = a.pbuf[(k0 + 1) & 1] + (size_t)b * n + k0;
+    const double2 t = taus[k0 - 1];
+    if (tid < L) {
+      vv[tid] = vprev[tid];
+      pw[tid] = pprev[tid];
+    }
+    if (wave == 0) {
+      const double2 d = wave_sum2(lane < L ? dcmul(pprev[lane], vprev[lane]) : zero);
+      if (lane == 0) sc[2] = d;
+    }
+    __syncthreads();
+    const double c = -0.5 * (t.x * t.x + t.y * t.y);
+    const double2 cd = dscale(sc[2], c);
+    for (int e = tid; e < L * L; e += kTailNT) {
+      const int i = e / L, j = e % L;
+      const double2 wi = dadd(dmul(t, pw[i]), dmul(cd, vv[i]));
+      const double2 wj = dadd(dmul(t, pw[j]), dmul(cd, vv[j]));
+      B[e] = dsub(B[e], dadd(dmul(vv[i], dconj(wj)), dmul(wi, dconj(vv[j]))));
+    }
+  }
+  __syncthreads();
+  for (int kk = 0; kk < L - 1; ++kk) {
+    // 1. reflector from x = column kk below the diagonal (B Hermitian: x_i = conj(B[kk][i]))
+    if (wave == 0) {
+      const int i = kk + 2 + lane;
+      double2 x = i < L ? B[kk * L + i] : zero;
+      const double xn2 = wave_sum2(make_double2(x.x * x.x + x.y * x.y, 0.0)).x;
+      if (lane == 0) {
+        const double2 alpha = dconj(B[kk * L + kk + 1]);
+        double beta;
+        double2 tau, scale;
+        if (xn2 == 0.0 && alpha.y == 0.0) {
+          tau = zero;
+          beta = alpha.x;
+          scale = zero;
+        } else {
+          const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+          beta = alpha.x >= 0.0 ? -nrm : nrm;
+          tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+          const double2 den = make_double2(alpha.x - beta, alpha.y);
+          const double dd = den.x * den.x + den.y * den.y;
+          scale = make_double2(den.x / dd, -den.y / dd);
+        }
+        sc[0] = tau;
+        sc[1] = scale;
+        sc[3] = make_double2(beta, 0.0);
+        Dl[kk] = B[kk * L + kk].x;
+        El[kk] = beta;
+        tl[kk] = tau;
+      }
+    }
+    __syncthreads();
+    const double2 tau = sc[0], scale = sc[1];
+    for (int i = kk + 1 + tid; i < L; i += kTailNT) {
+      const double2 v = (i == kk + 1) ? make_double2(1.0, 0.0) : dmul(dconj(B[kk * L + i]), scale);
+      vv[i] = v;
+      Vl[kk * L + i] = (i == kk + 1) ? sc[3] : v;
+    }
+    __syncthreads();
+    // 2. p = B v on the trailing rows: four threads per row, p_i = sum_j conj(B[j][i]) v_j
+    {
+      const int i = kk + 1 + (tid >> 2), q = tid & 3;
+      double2 acc = zero;
+      if (i < L)
+        for (int j = kk + 1 + q; j < L; j += 4) acc = dadd(acc, dmul(dconj(B[j * L + i]), vv[j]));
+      acc.x += __shfl_xor(acc.x, 1, 64);
+      acc.y += __shfl_xor(acc.y, 1, 64);
+      acc.x += __shfl_xor(acc.x, 2, 64);
+      acc.y += __shfl_xor(acc.y, 2, 64);
+      if (i < L && q == 0) pw[i] = acc;
+    }
+    __syncthreads();
+    // 3. d = p^H v, then the rank-2 update with w = tau p + c d v formed on the fly
+    if (wave == 0) {
+      const int i = kk + 1 + lane;
+      const double2 d = wave_sum2(i < L ? dcmul(pw[i], vv[i]) : zero);
+      if (lane == 0) sc[2] = d;
+    }
+    __syncthreads();
+    const double c = -0.5 * (tau.x * tau.x + tau.y * tau.y);
+    const double2 cd = dscale(sc[2], c);
+    const int T = L - kk - 1;
+    for (int e = tid; e < T * T; e += kTailNT) {
+      const int i = kk + 1 + e / T, j = kk + 1 + e % T;
+      const double2 wi = dadd(dmul(tau, pw[i]), dmul(cd, vv[i]));
+      const double2 wj = dadd(dmul(tau, pw[j]), dmul(cd, vv[j]));
+      B[i * L + j] = dsub(B[i * L + j], dadd(dmul(vv[i], dconj(wj)), dmul(wi, dconj(vv[j]))));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) Dl[L - 1] = B[(L - 1) * L + L - 1].x;
+  __syncthreads();
+  for (int e = tid; e < (L - 1) * L; e += kTailNT) {
+    const int kk = e / L, i = e % L;
+    if (i > kk) Vst[(size_t)(k0 + kk) * n + k0 + i] = Vl[kk * L + i];
+  }
+  for (int kk = tid; kk < L; kk += kTailNT) {
+    D[k0 + kk] = Dl[kk];
+    if (kk < L - 1) {
+      E[k0 + kk] = El[kk];
+      taus[k0 + kk] = tl[kk];
+    }
+  }
+}
+
 int tri_max_n() { return 3000; }
+
+static size_t tail_lds(int L) { return (size_t)(2 * L * L + 3 * L) * sizeof(double2) + 2 * (size_t)L * sizeof(double); }
 
 template <int NU>
 static hipError_t tri_attr() {
@@ -243,8 +393,16 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr = true;
   }
+  static bool tail_attr = false;
+  if (!tail_attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_tri_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)tail_lds(kTriTail));
+    if (e != hipSuccess) return e;
+    tail_attr = true;
+  }
+  const int k0 = n > kTriTail ? n - kTriTail : 0;  // columns k0.. in one launch
   TriArgs a = base;
-  for (int k = 0; k < n; ++k) {
+  for (int k = 0; k < k0; ++k) {
     a.k = k;
     const int rows = n - k - 1;
     const int gx = rows > 0 ? (rows + kTriRows - 1) / kTriRows : 1;
@@ -257,6 +415,8 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s) {
     else if (chunks <= 12) k_tri_step<12><<<grid, kTriNT, lds, s>>>(a);
     else k_tri_step<16><<<grid, kTriNT, lds, s>>>(a);
   }
+  const int L = n - k0;
+  k_tri_tail<<<dim3(1, nbatch), kTailNT, tail_lds(L), s>>>(a, k0);
   return hipGetLastError();
 }
 
