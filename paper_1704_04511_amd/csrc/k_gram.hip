@@ -207,7 +207,7 @@ hipError_t launch_weights(const WeightArgs& a, hipStream_t s) {
 // order are given to the same XCD (its L2 then holds the shared row panel).
 __global__ __launch_bounds__(256) void k_filter_product(int s, const double* __restrict__ VT,
                                                         double* __restrict__ Hre, double* __restrict__ Him) {
-  constexpr int TB = 64, KC = 16, NXCD = 8;
+  constexpr int TB = 64, KC = 32, NXCD = 8;
   __shared__ double Lre[KC][TB];
   __shared__ double Lim[KC][TB];
   __shared__ double Rt[KC][TB];
@@ -234,8 +234,13 @@ __global__ __launch_bounds__(256) void k_filter_product(int s, const double* __r
       accR[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
       accI[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
     }
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    for (int e = tid; e < KC * TB; e += 256) {
+  // the next K chunk is loaded into registers while the current one is multiplied
+  constexpr int U = KC * TB / 256;
+  double pr[U], pm[U], pl[U];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + 256 * u;
       const int kk = e / TB, c = e % TB;
       const int k = k0 + kk;
       double li = 0.0, lr = 0.0, lm = 0.0;
@@ -247,11 +252,23 @@ __global__ __launch_bounds__(256) void k_filter_product(int s, const double* __r
         }
         if (jj < s) li = VT[(long)k * s + jj];
       }
-      Lre[kk][c] = lr;
-      Lim[kk][c] = lm;
-      Rt[kk][c] = li;
+      pr[u] = lr;
+      pm[u] = lm;
+      pl[u] = li;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + 256 * u;
+      const int kk = e / TB, c = e % TB;
+      Lre[kk][c] = pr[u];
+      Lim[kk][c] = pm[u];
+      Rt[kk][c] = pl[u];
     }
     __syncthreads();
+    if (k0 + KC < K) load(k0 + KC);
 #pragma unroll
     for (int kq = 0; kq < KC; kq += 4) {
       const int kl = kq + (lane >> 4);
