@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_dc_vectors(DcArgs a0) {
 // Q_node(:, 0:k) = Qs(:, 0:k) U, Q_node(:, k:m) = Qs(:, k:m): 64 x 64 tiles,
 // four waves of 32 x 32, f64 16x16x4 MFMA, K staged through LDS in chunks of 16.
 __global__ __launch_bounds__(256) void k_dc_gemm(DcArgs a0) {
-  constexpr int TB = 64, KC = 16;
+  constexpr int TB = 64, KC = 32;
   __shared__ double La[KC][TB + 1];
   __shared__ double Lb[KC][TB + 1];
   const DcArgs a = dc_at(a0, blockIdx.z / a0.count);
@@ -513,22 +513,36 @@ __global__ __launch_bounds__(256) void k_dc_gemm(DcArgs a0) {
     }
     return;
   }
-  const double* U = a.U + (long)s * n + s;  // U(i, c) at U[c * n + i]
+  const double* Um = a.U + (long)s * n + s;  // U(i, c) at Um[c * n + i]
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   v4d acc[2][2];
 #pragma unroll
   for (int ta = 0; ta < 2; ++ta)
 #pragma unroll
     for (int tb = 0; tb < 2; ++tb) acc[ta][tb] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int kc = 0; kc < k; kc += KC) {
-    for (int e = tid; e < TB * KC; e += 256) {
-      const int rr = e / KC, kk = e % KC;
-      const int kidx = kc + kk;
+  // the next K chunk is loaded into registers while the current one is multiplied
+  constexpr int U = TB * KC / 256;
+  double ra[U], rb[U];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + 256 * u;
+      const int rr = e / KC, kidx = kc + e % KC;
       const int r = i0 + rr, c = j0 + rr;
-      La[kk][rr] = (r < m && kidx < k) ? Qs[(long)r * n + kidx] : 0.0;
-      Lb[kk][rr] = (c < k && kidx < k) ? U[(long)c * n + kidx] : 0.0;
+      ra[u] = (r < m && kidx < k) ? Qs[(long)r * n + kidx] : 0.0;
+      rb[u] = (c < k && kidx < k) ? Um[(long)c * n + kidx] : 0.0;
+    }
+  };
+  load(0);
+  for (int kc = 0; kc < k; kc += KC) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + 256 * u;
+      La[e % KC][e / KC] = ra[u];
+      Lb[e % KC][e / KC] = rb[u];
     }
     __syncthreads();
+    if (kc + KC < k) load(kc + KC);
 #pragma unroll
     for (int kq = 0; kq < KC; kq += 4) {
       const int kl = kq + (lane >> 4);
@@ -560,27 +574,43 @@ __global__ __launch_bounds__(256) void k_dc_gemm(DcArgs a0) {
       }
 }
 
-// Ascending eigenvalues and their permutation (one workgroup).
+// Ascending eigenvalues and their permutation (one workgroup): bitonic sort of
+// (value, index) pairs in LDS, padded to a power of two; ties keep index order.
 __global__ __launch_bounds__(1024) void k_dc_sort(DcArgs a0) {
   const DcArgs a = dc_at(a0, blockIdx.x);
   extern __shared__ double lds[];
   const int n = a.n;
-  for (int i = threadIdx.x; i < n; i += 1024) lds[i] = a.D[i];
+  int N = 1;
+  while (N < n) N <<= 1;
+  double* key = lds;
+  int* idx = (int*)(key + N);
+  for (int i = threadIdx.x; i < N; i += 1024) {
+    key[i] = i < n ? a.D[i] : __builtin_inf();
+    idx[i] = i;
+  }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += 1024) {
-    const double di = lds[i];
-    int r = 0;
-    int j = 0;
-    for (; j + 8 <= n; j += 8) {
-      double dj[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) dj[u] = lds[j + u];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) r += (dj[u] < di) || (dj[u] == di && j + u < i);
+  for (int size = 2; size <= N; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < N / 2; t += 1024) {
+        const int i = 2 * t - (t & (stride - 1));  // i has bit `stride` clear
+        const int j = i + stride;
+        const bool up = (i & size) == 0;
+        const double ki = key[i], kj = key[j];
+        const int ii = idx[i], ij = idx[j];
+        const bool gt = ki > kj || (ki == kj && ii > ij);
+        if (gt == up) {
+          key[i] = kj;
+          key[j] = ki;
+          idx[i] = ij;
+          idx[j] = ii;
+        }
+      }
+      __syncthreads();
     }
-    for (; j < n; ++j) r += (lds[j] < di) || (lds[j] == di && j < i);
-    a.ws_i[r] = i;
-    a.D[r] = di;
+  }
+  for (int r = threadIdx.x; r < n; r += 1024) {
+    a.ws_i[r] = idx[r];
+    a.D[r] = key[r];
   }
 }
 
@@ -646,7 +676,7 @@ hipError_t launch_tdeig(const TdArgs& t, hipStream_t st) {
   if (!attr) {
     hipError_t e = set_lds(k_dc_deflate, (size_t)kDcMaxN * (4 * sizeof(double) + 3 * sizeof(int)));
     if (e == hipSuccess) e = set_lds(k_dc_gather, (size_t)4 * kDcMaxN * sizeof(double));
-    if (e == hipSuccess) e = set_lds(k_dc_sort, (size_t)kDcMaxN * sizeof(double));
+    if (e == hipSuccess) e = set_lds(k_dc_sort, (size_t)4096 * (sizeof(double) + sizeof(int)));
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -684,7 +714,9 @@ hipError_t launch_tdeig(const TdArgs& t, hipStream_t st) {
     k_dc_vectors<<<dim3((mmax + 3) / 4, count, nb), 256, 0, st>>>(a);
     k_dc_gemm<<<dim3((mmax + 63) / 64, (mmax + 63) / 64, count * nb), 256, 0, st>>>(a);
   }
-  k_dc_sort<<<nb, 1024, (size_t)n * sizeof(double), st>>>(a);
+  int np2 = 1;
+  while (np2 < n) np2 <<= 1;
+  k_dc_sort<<<nb, 1024, (size_t)np2 * (sizeof(double) + sizeof(int)), st>>>(a);
   k_dc_convert<<<dim3((n + 63) / 64, (n + 63) / 64, nb), 256, 0, st>>>(a);
   return hipGetLastError();
 }

@@ -121,7 +121,6 @@ def test_server_mix_equals_alone_within_budget():
         for pb in pbs:
             prm = slrx.make_params(lam=pb.lam, n_irls=N_IRLS, n_cg=N_CG)
             tickets.append(srv.submit_data(pb.b, pb.S, pb.N1, pb.N2, pb.M, prm))
-            time.sleep(0.01)
         peak = 0
         deadline = time.time() + 120.0
         while not all(srv.poll(t) for t in tickets):
@@ -148,7 +147,7 @@ def test_server_mix_equals_alone_within_budget():
     for _, df in events:
         run += df
         assert run <= budget
-    # requests overlapped on the device (continuous batching, not a queue alone)
+    # requests submitted together overlapped on the device (continuous batching, not a queue)
     spans = [(i["t_admit"], i["t_done"]) for i in infos]
     overlap = any(a0 < b1 and b0 < a1 for k, (a0, a1) in enumerate(spans) for (b0, b1) in spans[k + 1:])
     assert overlap
