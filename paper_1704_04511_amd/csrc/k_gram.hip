@@ -79,24 +79,34 @@ __global__ __launch_bounds__(256) void k_gram_rows(GramArgs a) {
 
 // Pass 2: pruned DFT along r1 at lags delta1 = -(N1-1)..(N1-1).
 __global__ __launch_bounds__(256) void k_gram_cols(GramArgs a, int W) {
+  // four lanes per output, each over every fourth r1, combined in a fixed order
   const int L1 = 2 * a.N1 - 1, L2 = 2 * a.N2 - 1;
-  const int o = blockIdx.x * 256 + threadIdx.x;
-  if (o >= W * L1 * L2) return;
-  const int w = o / (L1 * L2), j1 = (o / L2) % L1, j2 = o % L2;
+  const int gt = blockIdx.x * 256 + threadIdx.x;
+  const int o = gt >> 2, q = gt & 3;
+  const bool valid = o < W * L1 * L2;
+  const int oo = valid ? o : 0;
+  const int w = oo / (L1 * L2), j1 = (oo / L2) % L1, j2 = oo % L2;
   const int P = a.P;
   const int d1 = j1 - (a.N1 - 1);
   const int dp = ((d1 % P) + P) % P;
   double sx = 0.0, sy = 0.0;
-  int idx = 0;
-  for (int r1 = 0; r1 < P; ++r1) {
-    const double2 c = a.c1[((size_t)w * P + r1) * L2 + j2];
-    const double2 t = a.twP[idx];
-    sx += c.x * t.x - c.y * t.y;
-    sy += c.x * t.y + c.y * t.x;
-    idx += dp;
-    if (idx >= P) idx -= P;
+  if (valid) {
+    int idx = (int)(((long)q * dp) % P);
+    const int step = (int)(((long)4 * dp) % P);
+    for (int r1 = q; r1 < P; r1 += 4) {
+      const double2 c = a.c1[((size_t)w * P + r1) * L2 + j2];
+      const double2 t = a.twP[idx];
+      sx += c.x * t.x - c.y * t.y;
+      sy += c.x * t.y + c.y * t.x;
+      idx += step;
+      if (idx >= P) idx -= P;
+    }
   }
-  a.g[o] = make_double2(sx, sy);
+  sx += __shfl_xor(sx, 1, 64);
+  sy += __shfl_xor(sy, 1, 64);
+  sx += __shfl_xor(sx, 2, 64);
+  sy += __shfl_xor(sy, 2, 64);
+  if (valid && q == 0) a.g[o] = make_double2(sx, sy);
 }
 
 // Pass 3: window extraction into R (column-major, full Hermitian matrix).
@@ -154,7 +164,7 @@ hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int W = a.M * (a.M + 1) / 2;
   const int n2 = W * (2 * a.N1 - 1) * (2 * a.N2 - 1);
-  k_gram_cols<<<(n2 + 255) / 256, 256, 0, s>>>(a, W);
+  k_gram_cols<<<(4 * n2 + 255) / 256, 256, 0, s>>>(a, W);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const long sN = (long)a.N1 * a.N2 * a.M;
   k_gram_assemble<<<(unsigned)((sN * sN + 255) / 256), 256, 0, s>>>(a);
@@ -332,12 +342,14 @@ __global__ __launch_bounds__(256) void k_diagsum(MaskArgs a, int W, int s) {
   double sx = 0.0, sy = 0.0;
   const int i1lo = d1 < 0 ? -d1 : 0, i1hi = d1 > 0 ? N1 - d1 : N1;
   const int i2lo = d2 < 0 ? -d2 : 0, i2hi = d2 > 0 ? N2 - d2 : N2;
+  // H(row, col) read as conj(H(col, row)): consecutive threads (consecutive d2)
+  // then touch consecutive addresses
   for (int i1 = i1lo; i1 < i1hi; ++i1)
     for (int i2 = i2lo; i2 < i2hi; ++i2) {
       const long row = (long)mp * NN + (i1 + d1) * N2 + (i2 + d2);  // (m', a')
       const long col = (long)m * NN + i1 * N2 + i2;                  // (m, a)
-      sx += a.Hre[row * s + col];
-      sy += a.Him[row * s + col];
+      sx += a.Hre[col * s + row];
+      sy -= a.Him[col * s + row];
     }
   a.wsum[o] = make_double2(sx, sy);
 }
