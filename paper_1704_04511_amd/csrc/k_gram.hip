@@ -329,11 +329,15 @@ hipError_t launch_filter_product(int s, const double* VT, double* Hre, double* H
 // ------------------------------------------------------------------ masks
 // w_{m',m}[Delta] for pairs (m <= m'), Delta = a' - a.
 __global__ __launch_bounds__(256) void k_diagsum(MaskArgs a, int W, int s) {
+  // four lanes per output (16 outputs per wave, lane = 16 q + output), each over
+  // every fourth term, combined in a fixed order
   const int N1 = a.N1, N2 = a.N2, M = a.M, NN = N1 * N2;
   const int L1 = 2 * N1 - 1, L2 = 2 * N2 - 1;
-  const int o = blockIdx.x * 256 + threadIdx.x;
-  if (o >= W * L1 * L2) return;
-  const int w = o / (L1 * L2), j1 = (o / L2) % L1, j2 = o % L2;
+  const int gt = blockIdx.x * 256 + threadIdx.x;
+  const int q = (gt & 63) >> 4, o = (gt >> 6) * 16 + (gt & 15);
+  const bool valid = o < W * L1 * L2;
+  const int oo = valid ? o : 0;
+  const int w = oo / (L1 * L2), j1 = (oo / L2) % L1, j2 = oo % L2;
   int m = 0, mp = 0;
   for (int mm = 0; mm < M; ++mm)
     for (int nn = mm; nn < M; ++nn)
@@ -342,16 +346,20 @@ __global__ __launch_bounds__(256) void k_diagsum(MaskArgs a, int W, int s) {
   double sx = 0.0, sy = 0.0;
   const int i1lo = d1 < 0 ? -d1 : 0, i1hi = d1 > 0 ? N1 - d1 : N1;
   const int i2lo = d2 < 0 ? -d2 : 0, i2hi = d2 > 0 ? N2 - d2 : N2;
-  // H(row, col) read as conj(H(col, row)): consecutive threads (consecutive d2)
-  // then touch consecutive addresses
-  for (int i1 = i1lo; i1 < i1hi; ++i1)
-    for (int i2 = i2lo; i2 < i2hi; ++i2) {
-      const long row = (long)mp * NN + (i1 + d1) * N2 + (i2 + d2);  // (m', a')
-      const long col = (long)m * NN + i1 * N2 + i2;                  // (m, a)
-      sx += a.Hre[col * s + row];
-      sy -= a.Him[col * s + row];
-    }
-  a.wsum[o] = make_double2(sx, sy);
+  const int w2 = i2hi - i2lo, cnt = valid ? (i1hi - i1lo) * w2 : 0;
+  // H(row, col) read as conj(H(col, row)) for coalesced access across d2
+  for (int t = q; t < cnt; t += 4) {
+    const int i1 = i1lo + t / w2, i2 = i2lo + t % w2;
+    const long row = (long)mp * NN + (i1 + d1) * N2 + (i2 + d2);  // (m', a')
+    const long col = (long)m * NN + i1 * N2 + i2;                  // (m, a)
+    sx += a.Hre[col * s + row];
+    sy -= a.Him[col * s + row];
+  }
+  sx += __shfl_xor(sx, 16, 64);
+  sy += __shfl_xor(sy, 16, 64);
+  sx += __shfl_xor(sx, 32, 64);
+  sy += __shfl_xor(sy, 32, 64);
+  if (valid && q == 0) a.wsum[o] = make_double2(sx, sy);
 }
 
 // s1[w][j1][r2] = sum_{j2} w[w][j1][j2] e^{+2 pi i Delta2 r2 / Q}
@@ -399,7 +407,7 @@ hipError_t launch_masks(const MaskArgs& a, hipStream_t s) {
   const int sN = a.N1 * a.N2 * a.M;
   const int L1 = 2 * a.N1 - 1, L2 = 2 * a.N2 - 1;
   const int n1 = W * L1 * L2;
-  k_diagsum<<<(n1 + 255) / 256, 256, 0, s>>>(a, W, sN);
+  k_diagsum<<<(4 * n1 + 255) / 256, 256, 0, s>>>(a, W, sN);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long n2 = (long)W * L1 * a.Q;
