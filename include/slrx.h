@@ -79,8 +79,11 @@ typedef struct {
 #define SLRX_FLAG_TIMING 1u /* record per-phase device times (hipEvents) */
 #define SLRX_FLAG_KTIME 2u  /* record every launch of each kernel class (hipEvents) */
 #define SLRX_FLAG_LIBEIGH 4u /* eigen-decomposition entirely by rocSOLVER zheevd (reference
-                                path); default: own Householder tridiagonalisation on the GPU,
-                                then rocSOLVER's divide-and-conquer and back-transformation */
+                                path); default: own Householder tridiagonalisation, divide
+                                and conquer and back-transformation on the GPU */
+/* With SLRX_FLAG_KTIME: time only the classes whose bits are set here (none set:
+ * every class).  Each timed region adds two events to the stream. */
+#define SLRX_FLAG_KTIME_CLASS(c) (1u << (16 + (c)))
 
 /* Kernel classes timed under SLRX_FLAG_KTIME. */
 enum {

@@ -161,9 +161,12 @@ def default_params() -> Params:
 
 
 def make_params(lam=1e-3, n_irls=15, n_cg=10, p=0.6, gamma=1.4, eps0_frac=0.01, timing=False,
-                ktime=False, lib_eigh=False) -> Params:
+                ktime=False, lib_eigh=False, ktime_classes=None) -> Params:
+    """ktime_classes: names from KERNEL_CLASSES to time (default: all, when ktime is set)."""
     flags = ((SLRX_FLAG_TIMING if timing else 0) | (SLRX_FLAG_KTIME if ktime else 0)
              | (SLRX_FLAG_LIBEIGH if lib_eigh else 0))
+    for c in ktime_classes or ():
+        flags |= 1 << (16 + KERNEL_CLASSES.index(c))
     return Params(float(lam), float(p), float(gamma), float(eps0_frac), int(n_irls), int(n_cg), flags)
 
 

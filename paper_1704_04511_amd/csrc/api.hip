@@ -53,6 +53,8 @@ slrx_status slrx::fail(slrx_status st, const char* fmt, ...) {
 
 slrx::KTimer::KTimer(slrx_plan* p, int c) : pl(p), cls(c) {
   if (!pl->ktime) return;
+  const uint32_t mask = pl->prm.flags >> 16;
+  if (mask != 0 && !((mask >> cls) & 1u)) return;
   auto& v = pl->kev[cls];
   const int i = pl->kused[cls];
   while ((int)v.size() < 2 * (i + 1)) {
