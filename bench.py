@@ -55,9 +55,9 @@ FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix
 
 
 def tri_bytes(n: int) -> float:
-    """Bytes of one Householder tridiagonalisation (n launches): launch k reads and
-    writes the trailing block ((n-k-1)^2 complex128 each way) and moves five
-    vectors of length n-k (row k, v and p in; v and p out)."""
+    """Bytes of one Householder tridiagonalisation: column k reads and writes the
+    trailing block ((n-k-1)^2 complex128 each way) and moves five vectors of
+    length n-k (row k, v and p in; v and p out)."""
     return float(sum(16 * (2 * (n - k - 1) ** 2 + 5 * (n - k)) for k in range(n)))
 
 
@@ -85,9 +85,10 @@ def roofline(kind, avg_ms, T, P, Q, M, N1, N2):
         return {"bound": "mfma", "kernel": kind, "achieved": round(ach, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
                 "flop_per_launch": flop, "avg_launch_ms": round(avg_ms, 5)}
-    if kind == "tri":  # per column launch
-        nbytes = tri_bytes(s) / s
-        avg_ms = avg_ms / s
+    if kind == "tri":  # per launch: one per column, the last 64 columns in one launch
+        launches = max(s - 64, 0) + 1
+        nbytes = tri_bytes(s) / launches
+        avg_ms = avg_ms / launches
     else:
         nbytes = algorithmic_bytes(kind, T, P, Q, M, N1, N2)
     ach = nbytes / (avg_ms * 1e-3) / 1e9
