@@ -93,7 +93,7 @@ enum {
   SLRX_K_UPDATE = 3,  /* CG vector update + residual norm */
   SLRX_K_GRAM = 4,    /* Gram matrix (lagged products, pruned DFT, window) */
   SLRX_K_TRI = 5,     /* Householder tridiagonalisation (one launch per column) */
-  SLRX_K_TDEIG = 6,   /* eigenpairs of the real tridiagonal (rocSOLVER zstedc), or the
+  SLRX_K_TDEIG = 6,   /* eigenpairs of the real tridiagonal (divide and conquer), or the
                          whole library eigen-decomposition with SLRX_FLAG_LIBEIGH */
   SLRX_K_BACKTR = 7,  /* blocked back-transformation U = Q Z */
   SLRX_K_FILTER = 8,  /* weights + filter product H = U diag(alpha) U^H */
