@@ -7,6 +7,14 @@
 // (j / NS) NS R + k.  After the last pass the output is in natural order.
 // Passes run in place: every thread first pulls all of its butterflies into
 // registers, the block synchronises, then the results are written back.
+//
+// LDS layout: element e of transform b sits at b * fft_stride(N) + fft_pidx(e),
+// one unused slot after every 16 elements and one more per transform.  A first
+// pass writes its outputs at stride R (16 elements = 128 bytes), which in an
+// unpadded array puts a wave's stores on two of the 64 banks; padded, the
+// strides become 17 and 34 banks apart.  The twiddles of each pass sit in a
+// table [r][k] of their own, so the lanes of a butterfly row read consecutive
+// entries.
 #pragma once
 #include "common.h"
 
@@ -128,29 +136,63 @@ template <> struct FftPlan<160> { using L = Radices<16, 5, 2>; };
 template <> struct FftPlan<192> { using L = Radices<16, 4, 3>; };
 template <> struct FftPlan<256> { using L = Radices<16, 16>; };
 
-// Layout of a batch of transforms in LDS: element e of transform b sits at
-// b * BS + e * ES.  COLMAJOR chooses which index varies fastest across threads
-// (transform index for column tiles, element index for row tiles).
-// MAXB transforms at most; nb of them are live (runtime).
-template <int N, int R, int NS, int SIGN, int MAXB, int NT, int ES, int BS, bool COLMAJOR>
-SLRX_DEV void fft_pass(float2* lds, const float2* tw, int nb) {
+SLRX_DEV int fft_pidx(int e) { return e + (e >> 4); }
+__host__ __device__ constexpr int fft_stride(int N) { return N + N / 16 + 1; }
+
+// Twiddle table size: NS * R entries for every pass with NS > 1.
+template <int NS, int... Rs> struct TwSize { static constexpr int v = 0; };
+template <int NS, int R, int... Rest> struct TwSize<NS, R, Rest...> {
+  static constexpr int v = (NS > 1 ? NS * R : 0) + TwSize<NS * R, Rest...>::v;
+};
+template <int N, int... Rs> constexpr int tw_size_of(Radices<Rs...>) { return TwSize<1, Rs...>::v; }
+template <int N> constexpr int fft_tw_size() {
+  constexpr int v = tw_size_of<N>(typename FftPlan<N>::L{});
+  return v > 0 ? v : 1;
+}
+
+// Fill the per-pass tables from tw[t] = e^{-2 pi i t / N}: entry OFF + r NS + k
+// of the pass (NS, R) is w^{r k} with w = e^{-2 pi i / (NS R)}.
+template <int N, int NT, int OFF, int NS, int... Rs> struct TwFill {
+  static SLRX_DEV void run(float2*, const float2*) {}
+};
+template <int N, int NT, int OFF, int NS, int R, int... Rest> struct TwFill<N, NT, OFF, NS, R, Rest...> {
+  static SLRX_DEV void run(float2* twt, const float2* tw) {
+    if (NS > 1)
+      for (int i = threadIdx.x; i < NS * R; i += NT) {
+        const int r = i / NS, k = i % NS;
+        twt[OFF + i] = tw[r * k * (N / (NS * R))];
+      }
+    TwFill<N, NT, OFF + (NS > 1 ? NS * R : 0), NS * R, Rest...>::run(twt, tw);
+  }
+};
+template <int N, int NT, int... Rs> SLRX_DEV void tw_fill_of(float2* twt, const float2* tw, Radices<Rs...>) {
+  TwFill<N, NT, 0, 1, Rs...>::run(twt, tw);
+}
+// Called by all NT threads; the tables are valid after the next barrier.
+template <int N, int NT> SLRX_DEV void fft_twiddles(float2* twt, const float2* tw) {
+  tw_fill_of<N, NT>(twt, tw, typename FftPlan<N>::L{});
+}
+
+// One radix-R pass over nb <= MAXB transforms (transform index slowest across
+// threads, butterfly index fastest).
+template <int N, int R, int NS, int OFF, int SIGN, int MAXB, int NT>
+SLRX_DEV void fft_pass(float2* lds, const float2* twt, int nb) {
   constexpr int NBF = N / R;                 // butterflies per transform
   constexpr int MAXTOT = MAXB * NBF;
   constexpr int PER = (MAXTOT + NT - 1) / NT;
+  constexpr int BS = fft_stride(N);
   const int tot = nb * NBF;
   float2 v[PER][R];
   int base[PER], jj[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int b = threadIdx.x + i * NT;
-    int bt, j;
-    if (COLMAJOR) { bt = b % nb; j = b / nb; }
-    else { bt = b / NBF; j = b % NBF; }
+    const int bt = b / NBF, j = b % NBF;
     base[i] = bt * BS;
     jj[i] = j;
     if (b < tot) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = lds[base[i] + (j + r * NBF) * ES];
+      for (int r = 0; r < R; ++r) v[i][r] = lds[base[i] + fft_pidx(j + r * NBF)];
     }
   }
   __syncthreads();
@@ -163,7 +205,7 @@ SLRX_DEV void fft_pass(float2* lds, const float2* tw, int nb) {
       if (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * k * (N / (NS * R))];
+          float2 w = twt[OFF + r * NS + k];
           if (SIGN > 0) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
         }
@@ -171,27 +213,28 @@ SLRX_DEV void fft_pass(float2* lds, const float2* tw, int nb) {
       Dft<R, SIGN>::run(v[i]);
       const int o = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[base[i] + (o + r * NS) * ES] = v[i][r];
+      for (int r = 0; r < R; ++r) lds[base[i] + fft_pidx(o + r * NS)] = v[i][r];
     }
   }
   __syncthreads();
 }
 
-template <int N, int SIGN, int MAXB, int NT, int ES, int BS, bool COLMAJOR, int NS, int R, int... Rest>
-SLRX_DEV void fft_passes(float2* lds, const float2* tw, int nb) {
-  fft_pass<N, R, NS, SIGN, MAXB, NT, ES, BS, COLMAJOR>(lds, tw, nb);
+template <int N, int SIGN, int MAXB, int NT, int NS, int OFF, int R, int... Rest>
+SLRX_DEV void fft_passes(float2* lds, const float2* twt, int nb) {
+  fft_pass<N, R, NS, OFF, SIGN, MAXB, NT>(lds, twt, nb);
   if constexpr (sizeof...(Rest) > 0)
-    fft_passes<N, SIGN, MAXB, NT, ES, BS, COLMAJOR, NS * R, Rest...>(lds, tw, nb);
+    fft_passes<N, SIGN, MAXB, NT, NS * R, OFF + (NS > 1 ? NS * R : 0), Rest...>(lds, twt, nb);
 }
 
-template <int N, int SIGN, int MAXB, int NT, int ES, int BS, bool COLMAJOR, int... Rs>
-SLRX_DEV void fft_run(float2* lds, const float2* tw, int nb, Radices<Rs...>) {
-  fft_passes<N, SIGN, MAXB, NT, ES, BS, COLMAJOR, 1, Rs...>(lds, tw, nb);
+template <int N, int SIGN, int MAXB, int NT, int... Rs>
+SLRX_DEV void fft_run(float2* lds, const float2* twt, int nb, Radices<Rs...>) {
+  fft_passes<N, SIGN, MAXB, NT, 1, 0, Rs...>(lds, twt, nb);
 }
 
-// Unnormalised length-N DFTs (sign SIGN) of nb <= MAXB transforms held in LDS.
-// tw[t] = e^{-2 pi i t / N} (also in LDS).  Must be called by all NT threads.
-template <int N, int SIGN, int MAXB, int NT, int ES, int BS, bool COLMAJOR>
-SLRX_DEV void fft_lds(float2* lds, const float2* tw, int nb) {
-  fft_run<N, SIGN, MAXB, NT, ES, BS, COLMAJOR>(lds, tw, nb, typename FftPlan<N>::L{});
+// Unnormalised length-N DFTs (sign SIGN) of nb <= MAXB transforms held in LDS
+// in the padded layout; twt holds the tables of fft_twiddles.  Must be called
+// by all NT threads.
+template <int N, int SIGN, int MAXB, int NT>
+SLRX_DEV void fft_lds(float2* lds, const float2* twt, int nb) {
+  fft_run<N, SIGN, MAXB, NT>(lds, twt, nb, typename FftPlan<N>::L{});
 }

@@ -34,8 +34,23 @@ bool fft_len_supported(int n) {
 int max_frames() { return kTMax; }
 int max_taps() { return kMMax; }
 
-// Rows per block of the row passes (a tile of RB rows x N columns).
-__host__ __device__ inline int row_block(int P) { return P < 16 ? P : 16; }
+// Rows per block of the row passes (a tile of RB rows x N columns).  Eight
+// rows keep the transposed stores at 64-byte pieces and give 2.5 blocks per CU
+// at 256 x 256 x 20 rather than 1.25.
+constexpr int kRowB = 8;
+__host__ __device__ inline int row_block(int P) { return P < kRowB ? P : kRowB; }
+
+// Block -> (row band, frame) of the row passes.  Blocks are dealt to the 8
+// XCDs round-robin; consecutive work items are given to one XCD, so the two
+// halves of a 128-byte line of the transposed output (neighbouring bands)
+// meet in the same L2.
+SLRX_DEV void row_tile(int& band, int& frame) {
+  const int gx = gridDim.x, nb = gridDim.x * gridDim.y;
+  int id = blockIdx.y * gx + blockIdx.x;
+  if ((nb & 7) == 0) id = (id & 7) * (nb >> 3) + (id >> 3);
+  band = id % gx;
+  frame = id / gx;
+}
 
 // Columns per block of the column penalty pass: largest power of two with
 // CB * N <= 256 that divides Q.
@@ -51,18 +66,21 @@ __host__ __device__ inline int col_block(int cap, int Q) {
 // Row DFT of RB rows of one frame; output transposed: dst[t][c][r].
 template <int N, int SIGN>
 __global__ __launch_bounds__(kNT) void k_rows_t(RowArgs a) {
-  constexpr int RBMAX = 16;
-  __shared__ float2 lds[RBMAX * N];
-  __shared__ float2 tw[N];
+  constexpr int RBMAX = kRowB;
+  constexpr int BS = fft_stride(N);
+  __shared__ float2 lds[RBMAX * BS];
+  __shared__ float2 twt[fft_tw_size<N>()];
   __shared__ double red[kNT / 64];
   const int P = a.P, Q = a.Q;
   const int RB = row_block(P);
-  const int t = blockIdx.y;
-  const int r0 = blockIdx.x * RB;
+  int band, t;
+  row_tile(band, t);
+  const int r0 = band * RB;
   const long fo = (long)t * P * Q;
   const long g0 = fo + (long)r0 * Q;
   const int nel = RB * N;
-  for (int i = threadIdx.x; i < N; i += kNT) tw[i] = a.tw[i];
+  fft_twiddles<N, kNT>(twt, a.tw);
+  auto at = [&](int e) { return (e / N) * BS + fft_pidx(e % N); };  // tile element (row, column) in LDS
 
   if (a.mode == ROW_PUPDATE) {
     const double rr = reduce_partials<kNT>(a.part, a.npart, red);
@@ -90,124 +108,196 @@ __global__ __launch_bounds__(kNT) void k_rows_t(RowArgs a) {
         if (e < nel) {
           const float2 pv = make_float2(v[u].x + fb * po[u].x, v[u].y + fb * po[u].y);
           a.pvec[g0 + e] = pv;
-          lds[e] = pv;
+          lds[at(e)] = pv;
         }
       }
     }
   } else if (a.mode == ROW_MASKED) {
     for (int e = threadIdx.x; e < nel; e += kNT) {
       const float2 v = a.src[g0 + e];
-      lds[e] = a.S[g0 + e] ? v : make_float2(0.f, 0.f);
+      lds[at(e)] = a.S[g0 + e] ? v : make_float2(0.f, 0.f);
     }
   } else {
-    for (int e = threadIdx.x; e < nel; e += kNT) lds[e] = a.src[g0 + e];
+    for (int e = threadIdx.x; e < nel; e += kNT) lds[at(e)] = a.src[g0 + e];
   }
   __syncthreads();
-  fft_lds<N, SIGN, RBMAX, kNT, 1, N, false>(lds, tw, RB);
+  fft_lds<N, SIGN, RBMAX, kNT>(lds, twt, RB);
   const float sc = a.scale;
   // transposed store: consecutive threads take consecutive rows of one column
   for (int e = threadIdx.x; e < nel; e += kNT) {
     const int i = e % RB, c = e / RB;
-    a.dst[fo + (long)c * P + r0 + i] = cscale(lds[i * N + c], sc);
+    a.dst[fo + (long)c * P + r0 + i] = cscale(lds[i * BS + fft_pidx(c)], sc);
   }
 }
 
 // -------------------------------------------------- pass 2: columns + penalty
 // Block: CB columns of all T frames, each column a contiguous transform of
 // length N = P in the transposed layout.  Inverse column DFT, G, forward DFT.
+// Two threads per pixel (halves h = 0, 1): frame loads and stores are split
+// by frame parity, every transform pass takes one butterfly per thread, and
+// the penalty's outputs are split by frame parity.
+constexpr int kPenNT = 512;
+
 template <int N, int M>
-__global__ __launch_bounds__(kNT) void k_cols_pen(PenArgs a) {
+__global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
   constexpr int CAP = ColCap<N>::v;
   constexpr int MAXB = kTMax * CAP;
   constexpr int W = M * (M + 1) / 2;
-  extern __shared__ float2 lds[];  // [T][CB][N]
-  __shared__ float2 tw[N];
+  constexpr int BS = fft_stride(N);
+  constexpr int ME = M > 1 ? 2 * M - 2 : 1;  // frames at each end with a partial window
+  extern __shared__ float2 lds[];  // [T][CB] transforms of length N, padded
+  __shared__ float2 twt[fft_tw_size<N>()];
   const int T = a.T, P = a.P, Q = a.Q;
   const int CB = col_block(CAP, Q);
   const int c0 = blockIdx.x * CB;
   const long fs = (long)P * Q;
-  for (int i = threadIdx.x; i < N; i += kNT) tw[i] = a.tw[i];
-  const int per_t = CB * N;  // <= kNT: one pixel per thread
-  const int pix = threadIdx.x;
-  const bool has_pix = pix < per_t;
+  fft_twiddles<N, kPenNT>(twt, a.tw);
+  const int per_t = CB * BS;  // LDS stride of a frame
+  const int pix = threadIdx.x & 255, h = threadIdx.x >> 8;  // CB * N <= 256 pixels
+  const bool has_pix = pix < CB * N;
+  const int pl = (pix / N) * BS + fft_pidx(pix % N);  // the pixel's slot in a frame
   const long po = (long)c0 * P + pix;  // pixel (row pix % N, column c0 + pix / N) in a frame
+  // this pixel's frames of parity h and all of its masks (stored [w][c][r]);
+  // the masks are issued with the frames and first used after the transform
+  float2 e[W];
   {
-    float2 v[kTMax];
+    float2 v[kTMax / 2];
 #pragma unroll
-    for (int t = 0; t < kTMax; ++t) v[t] = (has_pix && t < T) ? a.buf[(long)t * fs + po] : make_float2(0.f, 0.f);
+    for (int i = 0; i < kTMax / 2; ++i) {
+      const int t = 2 * i + h;
+      v[i] = (has_pix && t < T) ? a.buf[(long)t * fs + po] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) e[w] = has_pix ? a.Et[(long)w * fs + po] : make_float2(0.f, 0.f);
     if (has_pix)
 #pragma unroll
-      for (int t = 0; t < kTMax; ++t)
-        if (t < T) lds[t * per_t + pix] = v[t];
+      for (int i = 0; i < kTMax / 2; ++i)
+        if (2 * i + h < T) lds[(2 * i + h) * per_t + pl] = v[i];
   }
-  // this pixel's masks, stored [w][c][r]; loaded now so they arrive during the transform
-  float2 e[W];
-#pragma unroll
-  for (int w = 0; w < W; ++w) e[w] = has_pix ? a.Et[(long)w * fs + po] : make_float2(0.f, 0.f);
   __syncthreads();
-  fft_lds<N, +1, MAXB, kNT, 1, N, false>(lds, tw, T * CB);
+  fft_lds<N, +1, MAXB, kPenNT>(lds, twt, T * CB);
 
+  // G on this pixel's frames:
+  //   (G rho)_t = sum_{n = max(t, M-1)}^{min(t+M-1, T-1)} sum_m' E[n-t][m'] rho_{n-m'}.
+  // For M-1 <= t <= T-M every n of the window is present and the sum is
+  // Toeplitz in t: (G rho)_t = u_0 rho_t + sum_{d=1}^{M-1} (u_d rho_{t-d} + conj(u_d) rho_{t+d}),
+  // u_d = sum_m E[m][m+d] the diagonal sums of E.  The first and last M-1
+  // frames keep the windowed sum; when T < 2M-1 there is no Toeplitz part and
+  // one thread per pixel runs the windowed sum over all frames.
   const float sc = a.scale;  // lam / (P Q)
-  if (has_pix) {
+  const bool split = T >= 2 * M - 1;
+  auto mac = [](float2 acc, float2 c, float2 x) {
+    return make_float2(acc.x + c.x * x.x - c.y * x.y, acc.y + c.x * x.y + c.y * x.x);
+  };
+  auto E = [&](int m, int mp) { return (m <= mp) ? e[pair_id(m, mp, M)] : cconj(e[pair_id(mp, m, M)]); };
+  float2 rho[kTMax], rt[ME];  // rt[i] = rho_{T-1-i}
+  if (split && has_pix) {
+#pragma unroll
+    for (int t = 0; t < kTMax; ++t) rho[t] = t < T ? lds[t * per_t + pl] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < ME; ++i) rt[i] = lds[(T - 1 - i) * per_t + pl];
+  }
+  __syncthreads();  // every input read before any output is written in place
+  if (split && has_pix) {
+    float2 u[M];
+#pragma unroll
+    for (int d = 0; d < M; ++d) {
+      float2 s = e[pair_id(0, d, M)];
+#pragma unroll
+      for (int m = 1; m + d < M; ++m) s = cadd(s, e[pair_id(m, m + d, M)]);
+      u[d] = s;
+    }
+    // first frames t < M-1: n = t + m for m >= M-1-t
+#pragma unroll
+    for (int t = 0; t < M - 1; ++t) {
+      if ((t & 1) != h) continue;
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int m = M - 1 - t; m < M; ++m)
+#pragma unroll
+        for (int mp = 0; mp < M; ++mp) acc = mac(acc, E(m, mp), rho[t + m - mp]);
+      lds[t * per_t + pl] = cscale(acc, sc);
+    }
+    // Toeplitz part
+#pragma unroll
+    for (int t = M - 1; t < kTMax; ++t) {
+      if (t > T - M || (t & 1) != h) continue;
+      float2 acc = mac(make_float2(0.f, 0.f), u[0], rho[t]);
+#pragma unroll
+      for (int d = 1; d < M; ++d) {
+        acc = mac(acc, u[d], rho[t - d]);
+        acc = mac(acc, cconj(u[d]), rho[t + d < kTMax ? t + d : kTMax - 1]);
+      }
+      lds[t * per_t + pl] = cscale(acc, sc);
+    }
+    // last frames t = T-1-q, q < M-1: n = t + m for m <= q; rho_{t+m-m'} = rt[q-m+m']
+#pragma unroll
+    for (int q = 0; q < M - 1; ++q) {
+      const int t = T - 1 - q;
+      if ((t & 1) != h) continue;
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int m = 0; m <= q; ++m)
+#pragma unroll
+        for (int mp = 0; mp < M; ++mp) acc = mac(acc, E(m, mp), rt[q - m + mp]);
+      lds[t * per_t + pl] = cscale(acc, sc);
+    }
+  } else if (!split && has_pix && h == 0) {
+    // windowed sum over n with a sliding register window: z[m] = rho_{n-m};
+    // acc[m] collects output frame n - m, written once complete
     float2 z[M], acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      z[m] = lds[(M - 1 - m) * per_t + pix];  // z[m] = rho_{n-m}, n = M-1
+      z[m] = lds[(M - 1 - m) * per_t + pl];
       acc[m] = make_float2(0.f, 0.f);
     }
     for (int n = M - 1; n < T; ++n) {
       if (n > M - 1) {
 #pragma unroll
         for (int m = M - 1; m > 0; --m) z[m] = z[m - 1];
-        z[0] = lds[n * per_t + pix];
+        z[0] = lds[n * per_t + pl];
       }
-      // acc[m] (output frame n - m) += sum_m' E[m][m'] z[m']
 #pragma unroll
       for (int m = 0; m < M; ++m) {
-        float2 s = acc[m];
 #pragma unroll
-        for (int mp = 0; mp < M; ++mp) {
-          const float2 em = (m <= mp) ? e[pair_id(m, mp, M)] : cconj(e[pair_id(mp, m, M)]);
-          s = make_float2(s.x + em.x * z[mp].x - em.y * z[mp].y, s.y + em.x * z[mp].y + em.y * z[mp].x);
-        }
-        acc[m] = s;
+        for (int mp = 0; mp < M; ++mp) acc[m] = mac(acc[m], E(m, mp), z[mp]);
       }
-      // frame n - M + 1 is complete; its input already sits in registers (z)
-      lds[(n - M + 1) * per_t + pix] = cscale(acc[M - 1], sc);
+      lds[(n - M + 1) * per_t + pl] = cscale(acc[M - 1], sc);
 #pragma unroll
       for (int m = M - 1; m > 0; --m) acc[m] = acc[m - 1];
       acc[0] = make_float2(0.f, 0.f);
     }
-    // frames T-1-m, m = 0..M-2
 #pragma unroll
-    for (int m = 0; m < M - 1; ++m) lds[(T - 1 - m) * per_t + pix] = cscale(acc[m + 1], sc);
+    for (int m = 0; m < M - 1; ++m) lds[(T - 1 - m) * per_t + pl] = cscale(acc[m + 1], sc);
   }
   __syncthreads();
-  fft_lds<N, -1, MAXB, kNT, 1, N, false>(lds, tw, T * CB);
+  fft_lds<N, -1, MAXB, kPenNT>(lds, twt, T * CB);
   if (has_pix)
-    for (int t = 0; t < T; ++t) a.buf[(long)t * fs + po] = lds[t * per_t + pix];
+    for (int t = h; t < T; t += 2) a.buf[(long)t * fs + po] = lds[t * per_t + pl];
 }
 
 // Plain column DFT of up to 16 columns of one frame: transposed in, row-major out.
 template <int N, int SIGN>
 __global__ __launch_bounds__(kNT) void k_cols_plain(ColArgs a) {
   constexpr int CB = 16;
-  __shared__ float2 lds[CB * N];
-  __shared__ float2 tw[N];
+  constexpr int BS = fft_stride(N);
+  __shared__ float2 lds[CB * BS];
+  __shared__ float2 twt[fft_tw_size<N>()];
   const int P = a.P, Q = a.Q;
   const int cb = Q < CB ? Q : CB;
   const int t = blockIdx.y;
   const int c0 = blockIdx.x * cb;
   const long fo = (long)t * P * Q;
-  for (int i = threadIdx.x; i < N; i += kNT) tw[i] = a.tw[i];
-  for (int e = threadIdx.x; e < cb * N; e += kNT) lds[e] = a.src[fo + (long)c0 * P + e];  // [cc][r]
+  fft_twiddles<N, kNT>(twt, a.tw);
+  for (int e = threadIdx.x; e < cb * N; e += kNT)  // [cc][r]
+    lds[(e / N) * BS + fft_pidx(e % N)] = a.src[fo + (long)c0 * P + e];
   __syncthreads();
-  fft_lds<N, SIGN, CB, kNT, 1, N, false>(lds, tw, cb);
+  fft_lds<N, SIGN, CB, kNT>(lds, twt, cb);
   const float sc = a.scale;
   // row-major store: consecutive threads take consecutive columns of one row
   for (int e = threadIdx.x; e < cb * N; e += kNT) {
     const int cc = e % cb, r = e / cb;
-    a.dst[fo + (long)r * Q + c0 + cc] = cscale(lds[cc * N + r], sc);
+    a.dst[fo + (long)r * Q + c0 + cc] = cscale(lds[cc * BS + fft_pidx(r)], sc);
   }
 }
 
@@ -216,17 +306,19 @@ __global__ __launch_bounds__(kNT) void k_cols_plain(ColArgs a) {
 //   init: r = b - (S o x + pen), partial <r, r>;   else: q = S o p + pen, partial <p, q>.
 template <int N>
 __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
-  constexpr int RBMAX = 16;
-  __shared__ float2 lds[RBMAX * N];
-  __shared__ float2 tw[N];
+  constexpr int RBMAX = kRowB;
+  constexpr int BS = fft_stride(N);
+  __shared__ float2 lds[RBMAX * BS];
+  __shared__ float2 twt[fft_tw_size<N>()];
   __shared__ double red[kNT / 64];
   const int P = a.P, Q = a.Q;
   const int RB = row_block(P);
-  const int t = blockIdx.y;
-  const int r0 = blockIdx.x * RB;
+  int band, t;
+  row_tile(band, t);
+  const int r0 = band * RB;
   const long fo = (long)t * P * Q;
   const int nel = RB * N;
-  for (int i = threadIdx.x; i < N; i += kNT) tw[i] = a.tw[i];
+  fft_twiddles<N, kNT>(twt, a.tw);
   constexpr int UR = RBMAX * N / kNT < 16 ? RBMAX * N / kNT : 16;
   constexpr int U = UR < 1 ? 1 : UR;  // elements per thread held in registers
   const long g0 = fo + (long)r0 * Q;
@@ -240,9 +332,10 @@ __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = threadIdx.x + u * kNT;
-      if (e < nel) lds[(e % RB) * N + e / RB] = tv[u];
+      if (e < nel) lds[(e % RB) * BS + fft_pidx(e / RB)] = tv[u];
     }
-    for (int e = threadIdx.x + U * kNT; e < nel; e += kNT) lds[(e % RB) * N + e / RB] = a.t[fo + (long)(e / RB) * P + r0 + e % RB];
+    for (int e = threadIdx.x + U * kNT; e < nel; e += kNT)
+      lds[(e % RB) * BS + fft_pidx(e / RB)] = a.t[fo + (long)(e / RB) * P + r0 + e % RB];
   }
   // the operands of the combine step, loaded before the transform
   float2 vv[U], yv[U];
@@ -257,11 +350,11 @@ __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
     }
   }
   __syncthreads();
-  fft_lds<N, -1, RBMAX, kNT, 1, N, false>(lds, tw, RB);
+  fft_lds<N, -1, RBMAX, kNT>(lds, twt, RB);
   double dot = 0.0;
   auto combine = [&](int e, float2 v, uint8_t sm, float2 bv) {
     const long g = g0 + e;
-    const float2 pen = lds[e];
+    const float2 pen = lds[(e / N) * BS + fft_pidx(e % N)];
     const float2 av = sm ? make_float2(v.x + pen.x, v.y + pen.y) : pen;
     if (a.init) {
       const float2 rv = make_float2(bv.x - av.x, bv.y - av.y);
@@ -403,15 +496,15 @@ hipError_t launch_cols(const ColArgs& a, hipStream_t s) { SLRX_DISPATCH_N(a.P, c
 template <int N, int M>
 static hipError_t pen_nm(const PenArgs& a, hipStream_t s) {
   const int cb = col_block(ColCap<N>::v, a.Q);
-  const size_t lds = (size_t)a.T * cb * N * sizeof(float2);
+  const size_t lds = (size_t)a.T * cb * fft_stride(N) * sizeof(float2);
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_cols_pen<N, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)((size_t)kTMax * ColCap<N>::v * N * sizeof(float2)));
+                                       (int)((size_t)kTMax * ColCap<N>::v * fft_stride(N) * sizeof(float2)));
     if (e != hipSuccess) return e;
     attr = true;
   }
-  k_cols_pen<N, M><<<dim3(a.Q / cb), kNT, lds, s>>>(a);
+  k_cols_pen<N, M><<<dim3(a.Q / cb), kPenNT, lds, s>>>(a);
   return hipGetLastError();
 }
 
