@@ -30,6 +30,12 @@ paper where it is silent, listed again in the design notes):
   round-off eigenvalues are clamped to zero before adding epsilon.
 * CG is warm-started from the current iterate, runs exactly ``n_cg``
   iterations and stops early only on an exactly zero residual or curvature.
+* Multichannel data (Sec. II.A, eq. ``measurement_ij``): coil j of frame i
+  measures S_i F C_j F^* xhat_i, with C_j a pointwise image-domain
+  sensitivity shared by all frames and S_i shared by all coils.  The data
+  term is then sum_ij ||S_i F C_j F^* xhat_i - b_ij||^2, its normal operator
+  sum_j F C_j^* F^* S F C_j F^*, and the initial iterate the zero-filled coil
+  combination A^H b (which is S o b for one coil of ones).
 """
 from __future__ import annotations
 
@@ -39,7 +45,8 @@ import scipy.fft
 __all__ = [
     "dft2", "idft2", "filter_offsets", "pair_index", "lift", "gram",
     "eig_weights", "weight_matrix", "filter_spectra", "penalty_masks",
-    "penalty_apply", "penalty_value", "normal_apply", "cg", "irls",
+    "penalty_apply", "penalty_value", "normal_apply", "coil_forward", "coil_adjoint",
+    "coil_normal", "cg", "irls",
 ]
 
 
@@ -204,6 +211,30 @@ def normal_apply(xhat: np.ndarray, S: np.ndarray, E: np.ndarray, lam: float) -> 
     return S * xhat + lam * dft2(penalty_apply(idft2(xhat), E))
 
 
+# ------------------------------------------------------------ multichannel
+def coil_forward(xhat: np.ndarray, S: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """A xhat of eq. ``measurement_ij``: b_ij = S_i F C_j F^* xhat_i, shape [Nc][T][P][Q]."""
+    rho = idft2(xhat)
+    return np.stack([S * dft2(C[j][None] * rho) for j in range(C.shape[0])])
+
+
+def coil_adjoint(b: np.ndarray, S: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """A^H b = sum_j F C_j^* F^* (S o b_j) (the adjoint of ``coil_forward``)."""
+    acc = np.zeros(b.shape[1:], dtype=np.complex128)
+    for j in range(C.shape[0]):
+        acc += np.conj(C[j])[None] * idft2(S * b[j])
+    return dft2(acc)
+
+
+def coil_normal(xhat: np.ndarray, S: np.ndarray, C: np.ndarray, E: np.ndarray, lam: float) -> np.ndarray:
+    """Normal operator with the multichannel data term: A^H A xhat + lam F G F^* xhat."""
+    rho = idft2(xhat)
+    acc = lam * penalty_apply(rho, E)
+    for j in range(C.shape[0]):
+        acc = acc + np.conj(C[j])[None] * idft2(S * dft2(C[j][None] * rho))
+    return dft2(acc)
+
+
 # ----------------------------------------------------------------------- CG
 def cg(apply, rhs: np.ndarray, x0: np.ndarray, n_iter: int, trace: list | None = None) -> np.ndarray:
     """Conjugate gradients (Algorithm 1 step 2), warm start, exactly ``n_iter`` iterations."""
@@ -235,16 +266,27 @@ def cg(apply, rhs: np.ndarray, x0: np.ndarray, n_iter: int, trace: list | None =
 def irls(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
          n_irls: int, n_cg: int, p: float = 0.6, gamma: float = 1.4,
          eps0_frac: float = 0.01, x0: np.ndarray | None = None,
-         trace: dict | None = None, return_kspace: bool = False) -> np.ndarray:
+         trace: dict | None = None, return_kspace: bool = False,
+         coils: np.ndarray | None = None) -> np.ndarray:
     """Algorithm 1: alternate the weight update and the CG least-squares step.
 
     Step 1 (Sec. III.C): Gram matrix by FFT autocorrelation, eigen-decomposition,
     weights alpha_i = (lambda_i + eps)^(p/2-1) and masks E.  Step 2 (Sec. III.A):
     a few CG iterations on (S + lam F G F^*) xhat = S o b.  Then eps <- eps/gamma
     (Sec. III.D).  Returns the images F^-1 xhat (or xhat with ``return_kspace``).
+
+    With ``coils`` (sensitivities C, [Nc][P][Q]) the data b is [Nc][T][P][Q] and
+    the least-squares step uses the multichannel model of Sec. II.A:
+    (A^H A + lam F G F^*) xhat = A^H b, starting from A^H b.
     """
     S = S.astype(np.float64)
-    b = S * b.astype(np.complex128)
+    if coils is None:
+        b = S * b.astype(np.complex128)
+        normal = lambda v, E: normal_apply(v, S, E, lam)
+    else:
+        C = coils.astype(np.complex128)
+        b = coil_adjoint(S[None] * b.astype(np.complex128), S, C)
+        normal = lambda v, E: coil_normal(v, S, C, E, lam)
     T, P, Q = b.shape
     x = b.copy() if x0 is None else x0.astype(np.complex128).copy()
     eps = None
@@ -256,7 +298,7 @@ def irls(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
         alpha = (np.maximum(lamR, 0.0) + eps) ** (p / 2.0 - 1.0)
         E = penalty_masks(U, alpha, N1, N2, M, P, Q)
         cg_trace = [] if trace is not None else None
-        x = cg(lambda v: normal_apply(v, S, E, lam), b, x, n_cg, cg_trace)
+        x = cg(lambda v: normal(v, E), b, x, n_cg, cg_trace)
         if trace is not None:
             trace.setdefault("eps", []).append(eps)
             trace.setdefault("lambda_max", []).append(float(lamR.max()))

@@ -30,12 +30,25 @@ MUTATIONS = {
     "lift_shift": ("vals = xhat[n - m][(w1 - a1[ia]) % P, (w2 - a2[ia]) % Q]",
                    "vals = xhat[n - m][(w1 + a1[ia]) % P, (w2 - a2[ia]) % Q]"),
 }
+# mistakes in the multichannel data term, checked against its own pins
+COIL_MUTATIONS = {
+    "coil_adjoint_conj": ("acc += np.conj(C[j])[None] * idft2(S * b[j])", "acc += C[j][None] * idft2(S * b[j])"),
+    "coil_normal_conj": ("acc = acc + np.conj(C[j])[None] * idft2(S * dft2(C[j][None] * rho))",
+                         "acc = acc + C[j][None] * idft2(S * dft2(C[j][None] * rho))"),
+    "coil_normal_mask": ("acc = acc + np.conj(C[j])[None] * idft2(S * dft2(C[j][None] * rho))",
+                         "acc = acc + np.conj(C[j])[None] * idft2(dft2(C[j][None] * rho))"),
+    "coil_forward_transform": ("return np.stack([S * dft2(C[j][None] * rho) for j in range(C.shape[0])])",
+                               "return np.stack([S * idft2(C[j][None] * rho) for j in range(C.shape[0])])"),
+}
+PIN_FILE = {name: "tests/test_oracle_pins.py" for name in MUTATIONS}
+PIN_FILE.update({name: "tests/test_oracle_coils.py" for name in COIL_MUTATIONS})
+ALL = dict(MUTATIONS, **COIL_MUTATIONS)
 
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
+@pytest.mark.parametrize("name", sorted(ALL))
 def test_planted_mistake_is_caught(name, tmp_path):
     src = open(os.path.join(ROOT, "oracle", "slr.py")).read()
-    orig, planted = MUTATIONS[name]
+    orig, planted = ALL[name]
     assert orig in src, f"mutation site of {name} not found in the oracle"
     for d in ("oracle", "workload", "tests"):
         shutil.copytree(os.path.join(ROOT, d), tmp_path / d, ignore=shutil.ignore_patterns("__pycache__"))
@@ -43,6 +56,6 @@ def test_planted_mistake_is_caught(name, tmp_path):
     (tmp_path / "oracle" / "slr.py").write_text(src.replace(orig, planted))
     env = dict(os.environ, PYTHONDONTWRITEBYTECODE="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py"], cwd=tmp_path, capture_output=True, text=True, env=env,
+                        PIN_FILE[name]], cwd=tmp_path, capture_output=True, text=True, env=env,
                        timeout=600)
     assert r.returncode != 0, f"pins did not catch {name}:\n{r.stdout[-2000:]}"

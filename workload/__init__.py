@@ -30,8 +30,11 @@ __all__ = [
     "bumps",
     "make_images",
     "make_mask",
+    "make_coils",
     "make_problem",
+    "make_mc_problem",
     "CONFIGS",
+    "MC_CONFIGS",
     "config_problem",
     "batch_specs",
 ]
@@ -56,6 +59,7 @@ class Problem:
     name: str = ""
     t2_maps: tuple = ()    # ground-truth T2 maps (ms), one per component
     frac: np.ndarray | None = None
+    coils: np.ndarray | None = None  # complex64 [Nc][P][Q] sensitivities; b is then [Nc][T][P][Q]
 
     @property
     def shape(self):
@@ -164,6 +168,53 @@ def make_problem(seed: int, P: int, Q: int, T: int, K: int, R: float,
                    n_irls=n_irls, n_cg=n_cg, name=name, t2_maps=t2s, frac=frac)
 
 
+def make_coils(rng: np.random.Generator, P: int, Q: int, ncoils: int) -> np.ndarray:
+    """Smooth receive sensitivities, complex64 [Nc][P][Q], normalised to sum_j |C_j|^2 = 1.
+
+    Coil j sits on a circle of radius 0.7 P around the frame centre at angle
+    2 pi j / Nc (plus a uniform jitter of 0.2 rad); its magnitude is a Gaussian
+    of width uniform in [0.35, 0.55] P around that point and its phase a plane
+    wave with a uniform random gradient of at most pi across the frame plus a
+    uniform offset.
+    """
+    r1 = np.arange(P)[:, None].astype(np.float64) - P / 2.0
+    r2 = np.arange(Q)[None, :].astype(np.float64) - Q / 2.0
+    C = np.zeros((ncoils, P, Q), dtype=np.complex128)
+    for j in range(ncoils):
+        ang = 2.0 * math.pi * j / ncoils + rng.uniform(-0.2, 0.2)
+        c1, c2 = 0.7 * P * math.cos(ang), 0.7 * Q * math.sin(ang)
+        sig = rng.uniform(0.35, 0.55) * P
+        mag = np.exp(-((r1 - c1) ** 2 + (r2 - c2) ** 2) / (2.0 * sig * sig))
+        g1, g2 = rng.uniform(-1.0, 1.0, size=2) * math.pi
+        ph = g1 * r1 / P + g2 * r2 / Q + rng.uniform(-math.pi, math.pi)
+        C[j] = mag * np.exp(1j * ph)
+    C /= np.sqrt((np.abs(C) ** 2).sum(axis=0, keepdims=True))
+    return C.astype(np.complex64)
+
+
+def make_mc_problem(seed: int, P: int, Q: int, T: int, K: int, R: float, ncoils: int,
+                    N1: int, N2: int, M: int, lam: float = 1e-3, n_irls: int = 15,
+                    n_cg: int = 10, phase: bool = False, snr_db: float = 40.0,
+                    name: str = "") -> Problem:
+    """Multichannel problem (the measurement model of Sec. II.A): coil j of frame t
+    is sampled as S_t o (F(C_j rho_t) + noise), with one mask per frame shared by
+    the coils and complex Gaussian noise at ``snr_db`` per coil."""
+    rng = np.random.default_rng(seed)
+    img, t2s, frac = make_images(rng, P, Q, T, K, phase)
+    C = make_coils(rng, P, Q, ncoils)
+    S = np.stack([make_mask(rng, P, Q, R) for _ in range(T)])
+    sel = S.astype(bool)
+    nsel = int(sel.sum())
+    b = np.zeros((ncoils, T, P, Q), dtype=np.complex64)
+    for j in range(ncoils):
+        x = _unitary_fft2(C[j].astype(np.complex128)[None] * img)
+        sig = np.linalg.norm(x[sel]) / math.sqrt(max(nsel, 1)) * 10.0 ** (-snr_db / 20.0)
+        noise = (rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)) * (sig / math.sqrt(2.0))
+        b[j] = (S * (x + noise)).astype(np.complex64)
+    return Problem(b=b, S=S, truth=img, N1=N1, N2=N2, M=M, lam=lam, n_irls=n_irls,
+                   n_cg=n_cg, name=name, t2_maps=t2s, frac=frac, coils=C)
+
+
 # Named workloads: sizes, filter supports and iteration counts of the
 # single-problem configurations (64^2 x 8 echoes, 128^2 x 16, 256^2 x 20).
 CONFIGS = {
@@ -176,7 +227,19 @@ CONFIGS = {
 }
 
 
+# Multichannel workload shaped like the paper's multichannel experiment
+# (128 x 128, 12 echoes 10 ms apart, 12 coils; Sec. IV).
+MC_CONFIGS = {
+    "mc": dict(seed=4, P=128, Q=128, T=12, K=2, R=8, ncoils=12, N1=9, N2=9, M=5, lam=1e-3,
+               n_irls=15, n_cg=10, phase=False),
+}
+
+
 def config_problem(name: str, **over) -> Problem:
+    if name in MC_CONFIGS:
+        kw = dict(MC_CONFIGS[name])
+        kw.update(over)
+        return make_mc_problem(name=name, **kw)
     kw = dict(CONFIGS[name])
     kw.update(over)
     return make_problem(name=name, **kw)
