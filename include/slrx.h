@@ -87,9 +87,10 @@ typedef struct {
 
 /* Kernel classes timed under SLRX_FLAG_KTIME. */
 enum {
-  SLRX_K_ROWS = 0,    /* forward row pass of the CG operator (fused p update) */
-  SLRX_K_COLS = 1,    /* column pass: FFT, sampling mask, inverse FFT */
-  SLRX_K_FIN = 2,     /* inverse row pass + penalty G + combine + dot */
+  SLRX_K_ROWS = 0,    /* inverse row pass of the CG operator (fused p update) */
+  SLRX_K_COLS = 1,    /* column pass: inverse column DFT, penalty G (and the coil
+                         combination with coil maps), forward column DFT */
+  SLRX_K_FIN = 2,     /* forward row pass + data term S o v + dot */
   SLRX_K_UPDATE = 3,  /* CG vector update + residual norm */
   SLRX_K_GRAM = 4,    /* Gram matrix (lagged products, pruned DFT, window) */
   SLRX_K_TRI = 5,     /* Householder tridiagonalisation (one launch per column) */
@@ -98,7 +99,9 @@ enum {
   SLRX_K_BACKTR = 7,  /* blocked back-transformation U = Q Z */
   SLRX_K_FILTER = 8,  /* weights + filter product H = U diag(alpha) U^H */
   SLRX_K_MASKS = 9,   /* diagonal sums + mask synthesis */
-  SLRX_K_NCLASS = 10
+  SLRX_K_COIL = 10,   /* multichannel data term: coil images, their forward DFT,
+                         sampling mask and inverse row DFT (with coil maps only) */
+  SLRX_K_NCLASS = 11
 };
 
 /* Per-run statistics, filled by slrx_get_stats after a completed run. */
@@ -140,6 +143,24 @@ slrx_status slrx_set_kspace(slrx_plan* plan, const void* b, slrx_mem mem);
 slrx_status slrx_set_mask(slrx_plan* plan, const uint8_t* S, slrx_mem mem);
 slrx_status slrx_set_init(slrx_plan* plan, const void* x0, slrx_mem mem);
 slrx_status slrx_clear_init(slrx_plan* plan);
+/* Multichannel measurements (the model of Sec. II.A, eq. "measurement_ij"):
+ * frame i of coil j is sampled as b_ij = S_i F C_j F^* rho_hat_i + noise, with
+ * C_j a pointwise image-domain sensitivity shared by all frames and S_i the
+ * frame's mask (slrx_set_mask) shared by all coils.  The reconstruction then
+ * solves (A^H A + lam F G F^*) rho_hat = A^H b in every least-squares step and
+ * starts from A^H b = sum_j F C_j^* F^* (S o b_j) (or x0).
+ *   ncoils: 1..SLRX_MAX_COILS, or 0 to return to the single-channel model
+ *           (b of slrx_set_kspace; C and b are then ignored);
+ *   C: complex64 [ncoils][P][Q] sensitivities, row-major frames;
+ *   b: complex64 [ncoils][T][P][Q] coil k-space, DC at [0][0] (entries off
+ *      the mask are ignored).
+ * Copies both (host or device memory per mem).  Allocates 8 ((2 ncoils + 1) T
+ * P Q + ncoils P Q) bytes of device memory beyond slrx_footprint, released by
+ * slrx_plan_destroy or a later call.  SLRX_EINVAL for ncoils out of range or
+ * NULL pointers; SLRX_ESTATE while the plan runs.  Plans with coils can be
+ * run alone or in slrx_run_batch; servers take single-channel requests. */
+#define SLRX_MAX_COILS 32
+slrx_status slrx_set_coils(slrx_plan* plan, int32_t ncoils, const void* C, const void* b, slrx_mem mem);
 /* Change the filter support; N1 N2 M must not exceed the sizes the plan was
  * created with (buffers are sized at creation).  Algorithm parameters: */
 slrx_status slrx_set_filter(slrx_plan* plan, int32_t N1, int32_t N2, int32_t M);

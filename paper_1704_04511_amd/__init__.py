@@ -36,7 +36,7 @@ SLRX_FLAG_TIMING = 1
 SLRX_FLAG_KTIME = 2
 SLRX_FLAG_LIBEIGH = 4
 MAX_IRLS = 256
-KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "tri", "tdeig", "backtr", "filter", "masks")
+KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "tri", "tdeig", "backtr", "filter", "masks", "coil")
 
 STATUS = {0: "SLRX_OK", -1: "SLRX_EINVAL", -2: "SLRX_ENOMEM", -3: "SLRX_EDEVICE", -4: "SLRX_ESTATE",
           -5: "SLRX_ENUMERIC", -6: "SLRX_EBUSY", -7: "SLRX_ENOTREADY"}
@@ -94,6 +94,7 @@ _SIGS = {
     "slrx_plan_destroy": (None, [_P]),
     "slrx_set_kspace": (_I, [_P, _P, _I]),
     "slrx_set_mask": (_I, [_P, _P, _I]),
+    "slrx_set_coils": (_I, [_P, ctypes.c_int32, _P, _P, _I]),
     "slrx_set_init": (_I, [_P, _P, _I]),
     "slrx_clear_init": (_I, [_P]),
     "slrx_set_filter": (_I, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -254,6 +255,23 @@ class Plan:
         ptr, mem, keep = _ptr(S, np.uint8, self.shape)
         _check(lib().slrx_set_mask(self._h, ptr, mem))
         self._keep_S = keep
+
+    def set_coils(self, C, b):
+        """Multichannel data (``slrx_set_coils``): sensitivities C [Nc][P][Q] and
+        coil k-space b [Nc][T][P][Q], both complex64, both host arrays or both
+        device tensors; ``C=None`` returns to the single-channel model."""
+        if C is None:
+            _check(lib().slrx_set_coils(self._h, 0, None, None, SLRX_MEM_HOST))
+            self._keep_coils = None
+            return
+        d = self.dims
+        nc = int(C.shape[0])
+        cp, cm, ck = _ptr(C, np.complex64, (nc, d.P, d.Q))
+        bp, bm, bk = _ptr(b, np.complex64, (nc, d.T, d.P, d.Q))
+        if cm != bm:
+            raise ValueError("coil maps and coil data must both be host arrays or both device tensors")
+        _check(lib().slrx_set_coils(self._h, nc, cp, bp, cm))
+        self._keep_coils = (ck, bk)
 
     def set_init(self, x0):
         ptr, mem, keep = _ptr(x0, np.complex64, self.shape)

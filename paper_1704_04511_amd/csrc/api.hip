@@ -366,6 +366,7 @@ extern "C" void slrx_plan_destroy(slrx_plan* pl) {
     if (pl->ev_iter[i]) (void)hipEventDestroy(pl->ev_iter[i]);
   if (pl->blas) rocblas_destroy_handle(pl->blas);
   if (pl->blas_ws) (void)hipFree(pl->blas_ws);
+  if (pl->coil_mem) (void)hipFree(pl->coil_mem);
   if (pl->arena) (void)hipFree(pl->arena);
   if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
   delete pl;
@@ -412,6 +413,42 @@ extern "C" slrx_status slrx_set_kspace(slrx_plan* pl, const void* b, slrx_mem me
   STCHK(copy_in(pl, pl->b, b, pl->vol() * sizeof(float2), mem));
   pl->has_b = true;
   pl->prepared = false;
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_set_coils(slrx_plan* pl, int32_t ncoils, const void* C, const void* b, slrx_mem mem) {
+  STCHK(check_idle(pl));
+  if (ncoils < 0 || ncoils > SLRX_MAX_COILS)
+    return fail(SLRX_EINVAL, "ncoils=%d out of range [0,%d]", (int)ncoils, SLRX_MAX_COILS);
+  if (mem != SLRX_MEM_HOST && mem != SLRX_MEM_DEVICE) return fail(SLRX_EINVAL, "bad memory kind %d", (int)mem);
+  if (ncoils > 0 && (!C || !b)) return fail(SLRX_EINVAL, "coil maps or coil data pointer is NULL");
+  const slrx_dims& d = pl->d;
+  const size_t V = pl->vol(), pq = (size_t)d.P * d.Q;
+  if (ncoils != pl->ncoils_cap) {
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    if (pl->coil_mem) HIPCHK(hipFree(pl->coil_mem));
+    pl->coil_mem = nullptr;
+    pl->ncoils_cap = 0;
+    pl->Ct = pl->Bc = pl->Yc = pl->rho = nullptr;
+    if (ncoils > 0) {
+      const size_t elems = (size_t)ncoils * pq + 2 * (size_t)ncoils * V + V;
+      HIPCHK(hipMalloc(&pl->coil_mem, elems * sizeof(float2)));
+      pl->ncoils_cap = ncoils;
+      pl->Ct = (float2*)pl->coil_mem;
+      pl->Bc = pl->Ct + (size_t)ncoils * pq;
+      pl->Yc = pl->Bc + (size_t)ncoils * V;
+      pl->rho = pl->Yc + (size_t)ncoils * V;
+    }
+  }
+  pl->ncoils = 0;
+  pl->prepared = false;
+  if (ncoils == 0) return SLRX_OK;
+  // maps [j][P][Q] staged in the per-coil volumes, stored transposed [j][Q][P]
+  STCHK(copy_in(pl, pl->Yc, C, (size_t)ncoils * pq * sizeof(float2), mem));
+  HIPCHK(launch_transpose_planes(ncoils, d.P, d.Q, pl->Yc, pl->Ct, pl->stream));
+  STCHK(copy_in(pl, pl->Bc, b, (size_t)ncoils * V * sizeof(float2), mem));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  pl->ncoils = ncoils;
   return SLRX_OK;
 }
 

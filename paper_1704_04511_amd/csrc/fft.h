@@ -238,3 +238,18 @@ template <int N, int SIGN, int MAXB, int NT>
 SLRX_DEV void fft_lds(float2* lds, const float2* twt, int nb) {
   fft_run<N, SIGN, MAXB, NT>(lds, twt, nb, typename FftPlan<N>::L{});
 }
+
+// Host dispatch of a launch template over the supported transform lengths.
+#define SLRX_DISPATCH_N(n, F, ...)            \
+  switch (n) {                                \
+    case 8: return F<8>(__VA_ARGS__);         \
+    case 16: return F<16>(__VA_ARGS__);       \
+    case 32: return F<32>(__VA_ARGS__);       \
+    case 64: return F<64>(__VA_ARGS__);       \
+    case 96: return F<96>(__VA_ARGS__);       \
+    case 128: return F<128>(__VA_ARGS__);     \
+    case 160: return F<160>(__VA_ARGS__);     \
+    case 192: return F<192>(__VA_ARGS__);     \
+    case 256: return F<256>(__VA_ARGS__);     \
+  }                                           \
+  return hipErrorInvalidValue;

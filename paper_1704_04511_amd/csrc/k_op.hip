@@ -158,14 +158,17 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
   const int pl = (pix / N) * BS + fft_pidx(pix % N);  // the pixel's slot in a frame
   const long po = (long)c0 * P + pix;  // pixel (row pix % N, column c0 + pix / N) in a frame
   // this pixel's frames of parity h and all of its masks (stored [w][c][r]);
-  // the masks are issued with the frames and first used after the transform
+  // the masks are issued with the frames and first used after the transform.
+  // With coils the input is the image rho_u itself (no inverse transform).
+  const bool coil = a.nc > 0;
+  const float2* src = coil ? a.rho : a.buf;
   float2 e[W];
   {
     float2 v[kTMax / 2];
 #pragma unroll
     for (int i = 0; i < kTMax / 2; ++i) {
       const int t = 2 * i + h;
-      v[i] = (has_pix && t < T) ? a.buf[(long)t * fs + po] : make_float2(0.f, 0.f);
+      v[i] = (has_pix && t < T) ? src[(long)t * fs + po] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int w = 0; w < W; ++w) e[w] = has_pix ? a.Et[(long)w * fs + po] : make_float2(0.f, 0.f);
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
         if (2 * i + h < T) lds[(2 * i + h) * per_t + pl] = v[i];
   }
   __syncthreads();
-  fft_lds<N, +1, MAXB, kPenNT>(lds, twt, T * CB);
+  if (!coil) fft_lds<N, +1, MAXB, kPenNT>(lds, twt, T * CB);
 
   // G on this pixel's frames:
   //   (G rho)_t = sum_{n = max(t, M-1)}^{min(t+M-1, T-1)} sum_m' E[n-t][m'] rho_{n-m'}.
@@ -271,6 +274,23 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
     for (int m = 0; m < M - 1; ++m) lds[(T - 1 - m) * per_t + pl] = cscale(acc[m + 1], sc);
   }
   __syncthreads();
+  if (coil) {
+    // multichannel data term: sum_j conj(C_j) IDFT_col(Y_j), scaled by (PQ)^-2,
+    // one coil at a time through a second frame buffer
+    float2* lds2 = lds + T * per_t;
+    for (int j = 0; j < a.nc; ++j) {
+      const float2* Y = a.Y + (long)j * a.vstride;
+      if (has_pix)
+        for (int t = h; t < T; t += 2) lds2[t * per_t + pl] = Y[(long)t * fs + po];
+      __syncthreads();
+      fft_lds<N, +1, MAXB, kPenNT>(lds2, twt, T * CB);
+      if (has_pix) {
+        const float2 cj = cscale(cconj(a.Ct[(long)j * fs + po]), a.cscale);
+        for (int t = h; t < T; t += 2) lds[t * per_t + pl] = cadd(lds[t * per_t + pl], cmul(cj, lds2[t * per_t + pl]));
+      }
+    }
+    __syncthreads();
+  }
   fft_lds<N, -1, MAXB, kPenNT>(lds, twt, T * CB);
   if (has_pix)
     for (int t = h; t < T; t += 2) a.buf[(long)t * fs + po] = lds[t * per_t + pl];
@@ -355,7 +375,7 @@ __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
   auto combine = [&](int e, float2 v, uint8_t sm, float2 bv) {
     const long g = g0 + e;
     const float2 pen = lds[(e / N) * BS + fft_pidx(e % N)];
-    const float2 av = sm ? make_float2(v.x + pen.x, v.y + pen.y) : pen;
+    const float2 av = (sm && !a.coil) ? make_float2(v.x + pen.x, v.y + pen.y) : pen;
     if (a.init) {
       const float2 rv = make_float2(bv.x - av.x, bv.y - av.y);
       a.out[g] = rv;
@@ -460,19 +480,6 @@ __global__ void k_transpose_planes(int W, int A, int B, const float2* in, float2
 }
 
 // --------------------------------------------------------------- launches
-#define SLRX_DISPATCH_N(n, F, ...)            \
-  switch (n) {                                \
-    case 8: return F<8>(__VA_ARGS__);         \
-    case 16: return F<16>(__VA_ARGS__);       \
-    case 32: return F<32>(__VA_ARGS__);       \
-    case 64: return F<64>(__VA_ARGS__);       \
-    case 96: return F<96>(__VA_ARGS__);       \
-    case 128: return F<128>(__VA_ARGS__);     \
-    case 160: return F<160>(__VA_ARGS__);     \
-    case 192: return F<192>(__VA_ARGS__);     \
-    case 256: return F<256>(__VA_ARGS__);     \
-  }                                           \
-  return hipErrorInvalidValue;
 
 template <int N>
 static hipError_t rows_t_n(const RowArgs& a, hipStream_t s) {
@@ -496,11 +503,11 @@ hipError_t launch_cols(const ColArgs& a, hipStream_t s) { SLRX_DISPATCH_N(a.P, c
 template <int N, int M>
 static hipError_t pen_nm(const PenArgs& a, hipStream_t s) {
   const int cb = col_block(ColCap<N>::v, a.Q);
-  const size_t lds = (size_t)a.T * cb * fft_stride(N) * sizeof(float2);
+  const size_t lds = (size_t)(a.nc > 0 ? 2 : 1) * a.T * cb * fft_stride(N) * sizeof(float2);
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_cols_pen<N, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)((size_t)kTMax * ColCap<N>::v * fft_stride(N) * sizeof(float2)));
+                                       (int)((size_t)2 * kTMax * ColCap<N>::v * fft_stride(N) * sizeof(float2)));
     if (e != hipSuccess) return e;
     attr = true;
   }

@@ -53,6 +53,14 @@ struct PenArgs {
   const float2* Et;      // masks, transposed planes [w][c][r]
   float scale;           // lam / (P Q)
   const float2* tw;      // e^{-2 pi i t / P}
+  // multichannel data term (nc > 0): input rho instead of buf, and
+  // cscale sum_j conj(C_j) IDFT_col(Y_j) added before the forward transform
+  int nc;
+  const float2* rho;     // image rho_u, transposed
+  const float2* Y;       // per-coil volumes after the coil row pass, coil j at j * vstride
+  const float2* Ct;      // coil maps, transposed per coil [j][c][r]
+  long vstride;
+  float cscale;          // (P Q)^-2
 };
 hipError_t launch_pen(const PenArgs& a, hipStream_t s);
 
@@ -69,6 +77,7 @@ struct FinArgs {
   double* part;          // per-block partials
   int* flag;             // CG stop flag (cleared by block 0 when init)
   const float2* tw;      // e^{-2 pi i t / Q}
+  int coil;              // 1: the data term is already in t (multichannel); no S o v
 };
 hipError_t launch_fin(const FinArgs& a, hipStream_t s);
 int fin_blocks(int P, int T);
@@ -85,6 +94,23 @@ struct UpdArgs {
 };
 hipError_t launch_update(const UpdArgs& a, hipStream_t s);
 int update_blocks(long n);
+
+// Multichannel data term (k_coil.hip): coil column pass and coil row pass.
+struct CoilArgs {
+  int P, Q, T, nc;
+  const float2* t;       // row pass output (transposed)
+  float2* rho;           // out: image rho_u (transposed)
+  const float2* Ct;      // coil maps, transposed per coil [j][c][r]
+  float2* Y;             // per-coil volumes (transposed), coil j at j * vstride
+  long vstride;
+  const uint8_t* S;      // sampling mask, row-major [t][kr][kc]
+  const float2* tw;      // twiddles of the pass's transform length (P: columns, Q: rows)
+};
+hipError_t launch_coil_cols(const CoilArgs& a, hipStream_t s);
+hipError_t launch_coil_rows(const CoilArgs& a, hipStream_t s);
+// acc (+)= conj(C) o w, row-major volume, C transposed [c][r] (assign: first coil)
+hipError_t launch_coil_acc(long n, int P, int Q, const float2* Ct, const float2* w, float2* acc, bool assign,
+                           hipStream_t s);
 
 hipError_t launch_mask_data(long n, const uint8_t* S, const float2* b, float2* out, hipStream_t s);
 hipError_t launch_store_sum(const double* part, int n, double* dst, hipStream_t s);

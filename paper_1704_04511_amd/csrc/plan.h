@@ -57,6 +57,13 @@ struct slrx_plan {
   rocblas_int* info = nullptr;
   int* flag = nullptr;
 
+  // multichannel data (slrx_set_coils): one allocation holding the coil maps
+  // (transposed per coil), the coil k-space, the per-coil volumes of the
+  // operator and the image rho_u
+  int ncoils = 0, ncoils_cap = 0;
+  void* coil_mem = nullptr;
+  float2 *Ct = nullptr, *Bc = nullptr, *Yc = nullptr, *rho = nullptr;
+
   rocblas_handle blas = nullptr;
   void* blas_ws = nullptr;
   size_t blas_ws_size = 0;
@@ -121,6 +128,7 @@ slrx_status dc_prepare(slrx_plan* pl);
 slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma, const double2* U = nullptr,
                          const double* lamv = nullptr);
 slrx_status apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part);
+slrx_status coil_pass(slrx_plan* pl);
 slrx_status run_cg(slrx_plan* pl, int n_cg, int it);
 slrx_status enqueue_run(slrx_plan* pl);
 slrx_status finish(slrx_plan* pl);

@@ -52,12 +52,25 @@ slrx_status slrx::fft2(slrx_plan* pl, const float2* src, float2* dst, int sign, 
   return SLRX_OK;
 }
 
-// Masked data bm = S o b (the right-hand side) and the initial iterate
-// x = S o b (zero-filled k-space, Algorithm 1 initialisation) or the user's x0.
+// Right-hand side bm = S o b and the initial iterate x = S o b (zero-filled
+// k-space, Algorithm 1 initialisation) or the user's x0.  With coils the
+// right-hand side is A^H b = F sum_j C_j^* F^-1 (S o b_j) (Sec. II.A), formed
+// one coil at a time (images in img, their combination in q).
 slrx_status slrx::prepare(slrx_plan* pl) {
-  if (!pl->has_b || !pl->has_S) return fail(SLRX_ESTATE, "k-space and mask must be set before running");
+  if (!(pl->has_b || pl->ncoils > 0) || !pl->has_S)
+    return fail(SLRX_ESTATE, "k-space (or coil data) and mask must be set before running");
   const long V = (long)pl->vol();
-  HIPCHK(launch_mask_data(V, pl->S, pl->b, pl->bm, pl->stream));
+  if (pl->ncoils > 0) {
+    const slrx_dims& d = pl->d;
+    const long pq = (long)d.P * d.Q;
+    for (int j = 0; j < pl->ncoils; ++j) {
+      STCHK(fft2(pl, pl->Bc + (long)j * V, pl->img, +1, pl->S));
+      HIPCHK(launch_coil_acc(V, d.P, d.Q, pl->Ct + (long)j * pq, pl->img, pl->q, j == 0, pl->stream));
+    }
+    STCHK(fft2(pl, pl->q, pl->bm, -1, nullptr));
+  } else {
+    HIPCHK(launch_mask_data(V, pl->S, pl->b, pl->bm, pl->stream));
+  }
   const float2* x0 = pl->has_init ? pl->x0 : pl->bm;
   HIPCHK(hipMemcpyAsync(pl->x, x0, V * sizeof(float2), hipMemcpyDeviceToDevice, pl->stream));
   pl->prepared = true;
@@ -248,7 +261,28 @@ slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma, 
   return SLRX_OK;
 }
 
-// A v = S o v + lam F G F^-1 v in k-space (init: out = bm - A v).
+// The coil passes of the multichannel operator on the row pass output t:
+// rho_u and, per coil, the masked round trip through k-space (up to the
+// inverse column DFT, which the column pass applies).
+slrx_status slrx::coil_pass(slrx_plan* pl) {
+  const slrx_dims& d = pl->d;
+  CoilArgs ca{};
+  ca.P = d.P; ca.Q = d.Q; ca.T = d.T; ca.nc = pl->ncoils;
+  ca.t = pl->t;
+  ca.rho = pl->rho;
+  ca.Ct = pl->Ct;
+  ca.Y = pl->Yc;
+  ca.vstride = (long)pl->vol();
+  ca.S = pl->S;
+  ca.tw = pl->twPf;
+  HIPCHK(launch_coil_cols(ca, pl->stream));
+  ca.tw = pl->twQf;
+  HIPCHK(launch_coil_rows(ca, pl->stream));
+  return SLRX_OK;
+}
+
+// A v = S o v + lam F G F^-1 v in k-space (init: out = bm - A v); with coils
+// the data term is F sum_j C_j^* F^-1 S F C_j F^-1 v.
 slrx_status slrx::apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part) {
   const slrx_dims& d = pl->d;
   RowArgs ra{};
@@ -260,6 +294,7 @@ slrx_status slrx::apply_op(slrx_plan* pl, const float2* v, float2* out, bool ini
   ra.scale = 1.0f;
   ra.tw = pl->twQf;
   HIPCHK(launch_rows(ra, pl->stream));
+  if (pl->ncoils > 0) STCHK(coil_pass(pl));
   STCHK(penalty_pass(pl));
   FinArgs fa{};
   fa.P = d.P; fa.Q = d.Q; fa.T = d.T;
@@ -272,6 +307,7 @@ slrx_status slrx::apply_op(slrx_plan* pl, const float2* v, float2* out, bool ini
   fa.part = part;
   fa.flag = pl->flag;
   fa.tw = pl->twQf;
+  fa.coil = pl->ncoils > 0 ? 1 : 0;
   HIPCHK(launch_fin(fa, pl->stream));
   return SLRX_OK;
 }
@@ -284,11 +320,21 @@ slrx_status slrx::penalty_pass(slrx_plan* pl) {
   pa.Et = pl->Et;
   pa.scale = (float)(pl->prm.lambda / ((double)d.P * d.Q));
   pa.tw = pl->twPf;
+  if (pl->ncoils > 0) {
+    const double pq = (double)d.P * d.Q;
+    pa.nc = pl->ncoils;
+    pa.rho = pl->rho;
+    pa.Y = pl->Yc;
+    pa.Ct = pl->Ct;
+    pa.vstride = (long)pl->vol();
+    pa.cscale = (float)(1.0 / (pq * pq));
+  }
   HIPCHK(launch_pen(pa, pl->stream));
   return SLRX_OK;
 }
 
-// n_cg iterations of CG on (S + lam F G F^-1) x = S o b, warm-started at x.
+// n_cg iterations of CG on (S + lam F G F^-1) x = S o b (with coils:
+// (A^H A + lam F G F^-1) x = A^H b), warm-started at x.
 slrx_status slrx::run_cg(slrx_plan* pl, int n_cg, int it) {
   const slrx_dims& d = pl->d;
   const long V = (long)pl->vol();
@@ -313,6 +359,10 @@ slrx_status slrx::run_cg(slrx_plan* pl, int n_cg, int it) {
       KTimer kt(pl, SLRX_K_ROWS);
       HIPCHK(launch_rows(ra, pl->stream));
     }
+    if (pl->ncoils > 0) {
+      KTimer kt(pl, SLRX_K_COIL);
+      STCHK(coil_pass(pl));
+    }
     {
       KTimer kt(pl, SLRX_K_COLS);
       STCHK(penalty_pass(pl));
@@ -328,6 +378,7 @@ slrx_status slrx::run_cg(slrx_plan* pl, int n_cg, int it) {
     fa.part = pl->partA;
     fa.flag = pl->flag;
     fa.tw = pl->twQf;
+    fa.coil = pl->ncoils > 0 ? 1 : 0;
     {
       KTimer kt(pl, SLRX_K_FIN);
       HIPCHK(launch_fin(fa, pl->stream));
