@@ -24,11 +24,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def algorithmic_bytes(kind: str, T: int, P: int, Q: int, M: int, N1: int, N2: int) -> float:
+def algorithmic_bytes(kind: str, T: int, P: int, Q: int, M: int, N1: int, N2: int, nc: int = 0) -> float:
     """Bytes one launch of a kernel class must move (complex64 = 8 B per element).
 
     Units: V = T P Q volume elements; mask S 1 B per element; masks E
-    W = M(M+1)/2 complex64 planes of P x Q.
+    W = M(M+1)/2 complex64 planes of P x Q; nc coils (0: single channel).
     """
     V = T * P * Q
     W = M * (M + 1) // 2
@@ -36,10 +36,16 @@ def algorithmic_bytes(kind: str, T: int, P: int, Q: int, M: int, N1: int, N2: in
     c = 8
     if kind == "rows":     # read r, p_old; write p and the row-transformed volume t
         return 4 * V * c
-    if kind == "cols":     # read t and the masks E; write t
+    if kind == "cols":     # read t and the masks E; write t (coils: read rho and the coil
+        if nc:             # combination d instead of t)
+            return 3 * V * c + W * P * Q * c
         return 2 * V * c + W * P * Q * c
-    if kind == "fin":      # read t, p, S (1 B); write q
-        return 3 * V * c + V
+    if kind == "fin":      # read t, p, S (1 B); write q (coils: no S)
+        return 3 * V * c + (0 if nc else V)
+    if kind == "coil":     # coil columns: read t and the maps, write rho and nc volumes; coil
+        return ((2 + nc) * V * c + nc * P * Q * c    # rows: nc volumes both ways + S; combine: read
+                + 2 * nc * V * c + V                 # nc volumes and the maps, write d
+                + (nc + 1) * V * c + nc * P * Q * c)
     if kind == "update":   # read x, p, r, q; write x, r
         return 6 * V * c
     if kind == "gram":     # images (read x, write/read t, write img), read img, write R
@@ -73,7 +79,7 @@ def backtr_flop(n: int, nb: int = 64) -> float:
     return tot
 
 
-def roofline(kind, avg_ms, T, P, Q, M, N1, N2):
+def roofline(kind, avg_ms, T, P, Q, M, N1, N2, nc=0):
     """Roofline entry of one kernel class.  The filter product and the
     back-transformation are FP64 MFMA contractions; the tridiagonalisation is
     reported per launch (one launch per column) against HBM; every other class is
@@ -90,7 +96,7 @@ def roofline(kind, avg_ms, T, P, Q, M, N1, N2):
         nbytes = tri_bytes(s) / launches
         avg_ms = avg_ms / launches
     else:
-        nbytes = algorithmic_bytes(kind, T, P, Q, M, N1, N2)
+        nbytes = algorithmic_bytes(kind, T, P, Q, M, N1, N2, nc)
     ach = nbytes / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": kind, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes,
@@ -341,6 +347,75 @@ def bench_c2(args) -> int:
     return 0
 
 
+def bench_mc(args) -> int:
+    """Multichannel workload (128x128 x 12 echoes, 12 coils, R=8, filter 9x9x5, 15 x 10):
+    IRLS iterations/s, the per-class breakdown and rooflines, NRMSE against the FP64
+    oracle and the oracle's own time for the whole reconstruction."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1704_04511_amd as slrx
+    import workload
+
+    torch.cuda.set_device(0)
+    pb = workload.config_problem("mc")
+    nc, T, P, Q = pb.b.shape
+    mk = lambda kt, classes=None: slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg, p=pb.p,
+                                                    gamma=pb.gamma, eps0_frac=pb.eps0_frac, ktime=kt,
+                                                    ktime_classes=classes)
+    plan = slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, mk(False))
+    plan.set_mask(pb.S)
+    plan.set_coils(pb.coils, pb.b)
+    for _ in range(args.warmup):
+        plan.run()
+        plan.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run()
+        plan.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    img = plan.images()
+    plan.set_params(mk(True))  # one more reconstruction with every class timed
+    plan.run()
+    plan.sync()
+    st = plan.stats()
+    plan.close()
+    kms, kcnt = st["kernel_ms"], st["kernel_count"]
+    own = [k for k in ("rows", "coil", "cols", "fin", "update", "gram", "tri", "backtr", "filter", "masks")
+           if kcnt[k] > 0]
+    roofs = {k: roofline(k, kms[k] / kcnt[k], T, P, Q, pb.M, pb.N1, pb.N2, nc) for k in own}
+    dom = max(own, key=lambda k: kms[k])
+    out = {
+        "metric": "IRLS iters/s (128x128x12, 12 coils, filter 9x9x5)",
+        "value": round(pb.n_irls * args.steps / dt, 3), "unit": "IRLS iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {"workload": "128x128 x 12 echoes, 12 coils (Sec. II.A multichannel model), K=2, R=8, "
+                               "filter 9x9x5 (s=405), 15 IRLS x 10 CG", "ncoils": nc,
+                   "n_irls": pb.n_irls, "n_cg": pb.n_cg},
+        "roofline": roofs[dom],
+        "roofline_by_kernel": {k: {kk: v for kk, v in r.items() if kk in ("bound", "achieved", "unit", "frac")}
+                               for k, r in roofs.items()},
+        "phases_ms_per_step": {k: round(kms[k], 3) for k in kms if kcnt[k] > 0},
+        "recon_nrmse_vs_truth": round(float(np.linalg.norm(img - pb.truth) / np.linalg.norm(pb.truth)), 5),
+    }
+    if not args.no_cpu_baseline:
+        cores = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        ora = oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, pb.n_irls, pb.n_cg, p=pb.p, gamma=pb.gamma,
+                          eps0_frac=pb.eps0_frac, coils=pb.coils)
+        dto = time.perf_counter() - t0
+        out["nrmse_vs_oracle"] = float(f"{np.linalg.norm(img - ora) / np.linalg.norm(ora):.3e}")
+        out["cpu_baseline"] = {"value": pb.n_irls / dto, "unit": "IRLS iter/s", "cores": cores, "kind": "oracle",
+                               "sample": f"the whole reconstruction ({pb.n_irls} outer iterations), {dto:.1f} s wall"}
+    print(json.dumps(out))
+    return 0
+
+
 def copy_bandwidth_gbs() -> float:
     """Device-to-device copy of 1 GiB (read + write counted), best of 5, torch's copy kernel."""
     import torch
@@ -369,7 +444,7 @@ def main() -> int:
     ap.add_argument("--cpu-outer", type=int, default=3, help="outer iterations in the CPU oracle sample")
     ap.add_argument("--n-irls", type=int, default=None,
                     help="override the outer iteration count (profiling runs only; changes the workload)")
-    ap.add_argument("--workload", choices=("c3", "c2", "batch", "serve"), default="c3",
+    ap.add_argument("--workload", choices=("c3", "c2", "mc", "batch", "serve"), default="c3",
                     help="c3: the 256x256x20 headline line (default); c2: 128x128x16 with T2 maps; "
                          "batch: 32 uneven slices; serve: Poisson request stream")
     ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
@@ -380,6 +455,8 @@ def main() -> int:
         return 2
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "mc":
+        return bench_mc(args)
     if args.workload == "c2":
         return bench_c2(args)
     if args.workload == "serve":

@@ -88,7 +88,7 @@ typedef struct {
 /* Kernel classes timed under SLRX_FLAG_KTIME. */
 enum {
   SLRX_K_ROWS = 0,    /* inverse row pass of the CG operator (fused p update) */
-  SLRX_K_COLS = 1,    /* column pass: inverse column DFT, penalty G (and the coil
+  SLRX_K_COLS = 1,    /* column pass: inverse column DFT, penalty G (plus the coil
                          combination with coil maps), forward column DFT */
   SLRX_K_FIN = 2,     /* forward row pass + data term S o v + dot */
   SLRX_K_UPDATE = 3,  /* CG vector update + residual norm */
@@ -99,8 +99,9 @@ enum {
   SLRX_K_BACKTR = 7,  /* blocked back-transformation U = Q Z */
   SLRX_K_FILTER = 8,  /* weights + filter product H = U diag(alpha) U^H */
   SLRX_K_MASKS = 9,   /* diagonal sums + mask synthesis */
-  SLRX_K_COIL = 10,   /* multichannel data term: coil images, their forward DFT,
-                         sampling mask and inverse row DFT (with coil maps only) */
+  SLRX_K_COIL = 10,   /* multichannel data term (with coil maps only): coil images
+                         and their forward DFT, sampling mask, inverse DFT and
+                         coil combination */
   SLRX_K_NCLASS = 11
 };
 
@@ -154,7 +155,7 @@ slrx_status slrx_clear_init(slrx_plan* plan);
  *   C: complex64 [ncoils][P][Q] sensitivities, row-major frames;
  *   b: complex64 [ncoils][T][P][Q] coil k-space, DC at [0][0] (entries off
  *      the mask are ignored).
- * Copies both (host or device memory per mem).  Allocates 8 ((2 ncoils + 1) T
+ * Copies both (host or device memory per mem).  Allocates 8 ((2 ncoils + 2) T
  * P Q + ncoils P Q) bytes of device memory beyond slrx_footprint, released by
  * slrx_plan_destroy or a later call.  SLRX_EINVAL for ncoils out of range or
  * NULL pointers; SLRX_ESTATE while the plan runs.  Plans with coils can be

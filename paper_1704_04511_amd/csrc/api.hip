@@ -429,15 +429,16 @@ extern "C" slrx_status slrx_set_coils(slrx_plan* pl, int32_t ncoils, const void*
     if (pl->coil_mem) HIPCHK(hipFree(pl->coil_mem));
     pl->coil_mem = nullptr;
     pl->ncoils_cap = 0;
-    pl->Ct = pl->Bc = pl->Yc = pl->rho = nullptr;
+    pl->Ct = pl->Bc = pl->Yc = pl->rho = pl->dco = nullptr;
     if (ncoils > 0) {
-      const size_t elems = (size_t)ncoils * pq + 2 * (size_t)ncoils * V + V;
+      const size_t elems = (size_t)ncoils * pq + 2 * (size_t)ncoils * V + 2 * V;
       HIPCHK(hipMalloc(&pl->coil_mem, elems * sizeof(float2)));
       pl->ncoils_cap = ncoils;
       pl->Ct = (float2*)pl->coil_mem;
       pl->Bc = pl->Ct + (size_t)ncoils * pq;
       pl->Yc = pl->Bc + (size_t)ncoils * V;
       pl->rho = pl->Yc + (size_t)ncoils * V;
+      pl->dco = pl->rho + V;
     }
   }
   pl->ncoils = 0;

@@ -273,24 +273,12 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
 #pragma unroll
     for (int m = 0; m < M - 1; ++m) lds[(T - 1 - m) * per_t + pl] = cscale(acc[m + 1], sc);
   }
-  __syncthreads();
-  if (coil) {
-    // multichannel data term: sum_j conj(C_j) IDFT_col(Y_j), scaled by (PQ)^-2,
-    // one coil at a time through a second frame buffer
-    float2* lds2 = lds + T * per_t;
-    for (int j = 0; j < a.nc; ++j) {
-      const float2* Y = a.Y + (long)j * a.vstride;
-      if (has_pix)
-        for (int t = h; t < T; t += 2) lds2[t * per_t + pl] = Y[(long)t * fs + po];
-      __syncthreads();
-      fft_lds<N, +1, MAXB, kPenNT>(lds2, twt, T * CB);
-      if (has_pix) {
-        const float2 cj = cscale(cconj(a.Ct[(long)j * fs + po]), a.cscale);
-        for (int t = h; t < T; t += 2) lds[t * per_t + pl] = cadd(lds[t * per_t + pl], cmul(cj, lds2[t * per_t + pl]));
-      }
-    }
-    __syncthreads();
+  if (coil) {  // multichannel data term: the coil combination of k_coil_combine
+    __syncthreads();  // the windowed sum writes every frame of a pixel from one thread
+    if (has_pix)
+      for (int t = h; t < T; t += 2) lds[t * per_t + pl] = cadd(lds[t * per_t + pl], a.d[(long)t * fs + po]);
   }
+  __syncthreads();
   fft_lds<N, -1, MAXB, kPenNT>(lds, twt, T * CB);
   if (has_pix)
     for (int t = h; t < T; t += 2) a.buf[(long)t * fs + po] = lds[t * per_t + pl];
@@ -503,11 +491,11 @@ hipError_t launch_cols(const ColArgs& a, hipStream_t s) { SLRX_DISPATCH_N(a.P, c
 template <int N, int M>
 static hipError_t pen_nm(const PenArgs& a, hipStream_t s) {
   const int cb = col_block(ColCap<N>::v, a.Q);
-  const size_t lds = (size_t)(a.nc > 0 ? 2 : 1) * a.T * cb * fft_stride(N) * sizeof(float2);
+  const size_t lds = (size_t)a.T * cb * fft_stride(N) * sizeof(float2);
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_cols_pen<N, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)((size_t)2 * kTMax * ColCap<N>::v * fft_stride(N) * sizeof(float2)));
+                                       (int)((size_t)kTMax * ColCap<N>::v * fft_stride(N) * sizeof(float2)));
     if (e != hipSuccess) return e;
     attr = true;
   }

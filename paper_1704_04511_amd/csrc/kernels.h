@@ -53,14 +53,11 @@ struct PenArgs {
   const float2* Et;      // masks, transposed planes [w][c][r]
   float scale;           // lam / (P Q)
   const float2* tw;      // e^{-2 pi i t / P}
-  // multichannel data term (nc > 0): input rho instead of buf, and
-  // cscale sum_j conj(C_j) IDFT_col(Y_j) added before the forward transform
+  // multichannel data term (nc > 0): input rho instead of buf, and the coil
+  // combination d (k_coil_combine) added before the forward transform
   int nc;
   const float2* rho;     // image rho_u, transposed
-  const float2* Y;       // per-coil volumes after the coil row pass, coil j at j * vstride
-  const float2* Ct;      // coil maps, transposed per coil [j][c][r]
-  long vstride;
-  float cscale;          // (P Q)^-2
+  const float2* d;       // coil combination, transposed
 };
 hipError_t launch_pen(const PenArgs& a, hipStream_t s);
 
@@ -105,9 +102,12 @@ struct CoilArgs {
   long vstride;
   const uint8_t* S;      // sampling mask, row-major [t][kr][kc]
   const float2* tw;      // twiddles of the pass's transform length (P: columns, Q: rows)
+  float2* d;             // out of the combine pass: coil combination (transposed)
+  float cscale;          // (P Q)^-2
 };
 hipError_t launch_coil_cols(const CoilArgs& a, hipStream_t s);
 hipError_t launch_coil_rows(const CoilArgs& a, hipStream_t s);
+hipError_t launch_coil_combine(const CoilArgs& a, hipStream_t s);
 // acc (+)= conj(C) o w, row-major volume, C transposed [c][r] (assign: first coil)
 hipError_t launch_coil_acc(long n, int P, int Q, const float2* Ct, const float2* w, float2* acc, bool assign,
                            hipStream_t s);

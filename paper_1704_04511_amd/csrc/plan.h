@@ -59,10 +59,10 @@ struct slrx_plan {
 
   // multichannel data (slrx_set_coils): one allocation holding the coil maps
   // (transposed per coil), the coil k-space, the per-coil volumes of the
-  // operator and the image rho_u
+  // operator, the image rho_u and the coil combination d
   int ncoils = 0, ncoils_cap = 0;
   void* coil_mem = nullptr;
-  float2 *Ct = nullptr, *Bc = nullptr, *Yc = nullptr, *rho = nullptr;
+  float2 *Ct = nullptr, *Bc = nullptr, *Yc = nullptr, *rho = nullptr, *dco = nullptr;
 
   rocblas_handle blas = nullptr;
   void* blas_ws = nullptr;

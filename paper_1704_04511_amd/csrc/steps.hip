@@ -262,8 +262,8 @@ slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma, 
 }
 
 // The coil passes of the multichannel operator on the row pass output t:
-// rho_u and, per coil, the masked round trip through k-space (up to the
-// inverse column DFT, which the column pass applies).
+// rho_u, per coil the masked round trip through k-space, and their
+// combination d (added to the penalty by the column pass).
 slrx_status slrx::coil_pass(slrx_plan* pl) {
   const slrx_dims& d = pl->d;
   CoilArgs ca{};
@@ -278,6 +278,11 @@ slrx_status slrx::coil_pass(slrx_plan* pl) {
   HIPCHK(launch_coil_cols(ca, pl->stream));
   ca.tw = pl->twQf;
   HIPCHK(launch_coil_rows(ca, pl->stream));
+  const double pq = (double)d.P * d.Q;
+  ca.tw = pl->twPf;
+  ca.d = pl->dco;
+  ca.cscale = (float)(1.0 / (pq * pq));
+  HIPCHK(launch_coil_combine(ca, pl->stream));
   return SLRX_OK;
 }
 
@@ -321,13 +326,9 @@ slrx_status slrx::penalty_pass(slrx_plan* pl) {
   pa.scale = (float)(pl->prm.lambda / ((double)d.P * d.Q));
   pa.tw = pl->twPf;
   if (pl->ncoils > 0) {
-    const double pq = (double)d.P * d.Q;
     pa.nc = pl->ncoils;
     pa.rho = pl->rho;
-    pa.Y = pl->Yc;
-    pa.Ct = pl->Ct;
-    pa.vstride = (long)pl->vol();
-    pa.cscale = (float)(1.0 / (pq * pq));
+    pa.d = pl->dco;
   }
   HIPCHK(launch_pen(pa, pl->stream));
   return SLRX_OK;
