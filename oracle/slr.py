@@ -46,7 +46,7 @@ __all__ = [
     "dft2", "idft2", "filter_offsets", "pair_index", "lift", "gram",
     "eig_weights", "weight_matrix", "filter_spectra", "penalty_masks",
     "penalty_apply", "penalty_value", "normal_apply", "coil_forward", "coil_adjoint",
-    "coil_normal", "cg", "irls",
+    "coil_normal", "cg", "irls", "t2_fit",
 ]
 
 
@@ -305,3 +305,23 @@ def irls(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
             trace.setdefault("cg_rr", []).append(cg_trace)
         eps = eps / gamma
     return x if return_kspace else idft2(x)
+
+
+# ---------------------------------------------------------------- T2 maps
+def t2_fit(img: np.ndarray, te_ms: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Mono-exponential fit per pixel (Sec. IV: T2 maps from the reconstructed series).
+
+    Reading: least-squares line through y_t = log|rho_t| (|rho| floored at 1e-30)
+    against TE_t; T2 = -1/slope where the slope is negative, +inf otherwise, and
+    the amplitude exp(intercept at TE = 0).  Returns (T2 [ms], amplitude), each
+    shaped like one frame.
+    """
+    te = np.asarray(te_ms, dtype=np.float64)
+    y = np.log(np.maximum(np.abs(img.astype(np.complex128)), 1e-30))
+    tc = te - te.mean()
+    ybar = y.mean(axis=0)
+    slope = np.tensordot(tc, y - ybar[None], axes=(0, 0)) / (tc * tc).sum()
+    amp = np.exp(ybar - slope * te.mean())
+    with np.errstate(divide="ignore"):
+        t2 = np.where(slope < 0.0, -1.0 / np.where(slope < 0.0, slope, -1.0), np.inf)
+    return t2, amp

@@ -100,3 +100,4 @@ def test_irls_multichannel_recovers_a_noiseless_fully_sampled_series():
     b = np.stack([oracle.dft2(C[j][None] * img) for j in range(4)])
     out = oracle.irls(b, S, 3, 3, 2, 1e-4, 2, 5, coils=C)
     assert np.linalg.norm(out - img) <= 1e-2 * np.linalg.norm(img)
+

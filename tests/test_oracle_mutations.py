@@ -40,9 +40,17 @@ COIL_MUTATIONS = {
     "coil_forward_transform": ("return np.stack([S * dft2(C[j][None] * rho) for j in range(C.shape[0])])",
                                "return np.stack([S * idft2(C[j][None] * rho) for j in range(C.shape[0])])"),
 }
+# mistakes in the mono-exponential fit, checked against its own pins
+T2_MUTATIONS = {
+    "t2_sign": ("t2 = np.where(slope < 0.0, -1.0 / np.where(slope < 0.0, slope, -1.0), np.inf)",
+                "t2 = np.where(slope < 0.0, 1.0 / np.where(slope < 0.0, slope, -1.0), np.inf)"),
+    "t2_uncentred": ("tc = te - te.mean()", "tc = te"),
+    "t2_amplitude": ("amp = np.exp(ybar - slope * te.mean())", "amp = np.exp(ybar)"),
+}
 PIN_FILE = {name: "tests/test_oracle_pins.py" for name in MUTATIONS}
 PIN_FILE.update({name: "tests/test_oracle_coils.py" for name in COIL_MUTATIONS})
-ALL = dict(MUTATIONS, **COIL_MUTATIONS)
+PIN_FILE.update({name: "tests/test_oracle_t2.py" for name in T2_MUTATIONS})
+ALL = dict(MUTATIONS, **COIL_MUTATIONS, **T2_MUTATIONS)
 
 
 @pytest.mark.parametrize("name", sorted(ALL))
