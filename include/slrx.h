@@ -178,6 +178,22 @@ slrx_status slrx_get_images(slrx_plan* plan, void* out, slrx_mem mem);
 slrx_status slrx_get_kspace(slrx_plan* plan, void* out, slrx_mem mem);
 slrx_status slrx_get_stats(slrx_plan* plan, slrx_stats* out);
 
+/* Mono-exponential fit per pixel (Sec. IV: T2 maps are obtained by fitting a
+ * mono-exponential model to every pixel of the reconstructed series): the
+ * least-squares line through log|rho_t| (|rho| floored at 1e-30) against the
+ * echo times, in FP64.
+ *   img: complex64 [T][P][Q] series, or NULL for the plan's reconstruction
+ *        (after slrx_sync of a completed run);
+ *   te_ms: T echo times, host memory (T2 comes out in the same unit);
+ *   t2_out: float64 [P][Q]: -1/slope where the slope is negative, +inf otherwise;
+ *   amp_out: float64 [P][Q] amplitude exp(intercept at TE = 0), or NULL.
+ * img and the outputs are host or device memory per mem.  Overwrites the
+ * plan's image and CG scratch buffers (the reconstruction itself, x, is kept).
+ * SLRX_EINVAL for T < 2, equal or non-finite echo times or NULL pointers;
+ * SLRX_ESTATE without img before a completed run; SLRX_EBUSY while running. */
+slrx_status slrx_fit_t2(slrx_plan* plan, const void* img, const double* te_ms, double* t2_out, double* amp_out,
+                        slrx_mem mem);
+
 /* Run several independent plans.  hip_stream NULL: in lock step, one outer
  * iteration of every plan per step; plans with equal Gram size s share one
  * launch sequence of the eigen-decomposition (every kernel covers all of them,

@@ -95,6 +95,7 @@ _SIGS = {
     "slrx_set_kspace": (_I, [_P, _P, _I]),
     "slrx_set_mask": (_I, [_P, _P, _I]),
     "slrx_set_coils": (_I, [_P, ctypes.c_int32, _P, _P, _I]),
+    "slrx_fit_t2": (_I, [_P, _P, _P, _P, _P, _I]),
     "slrx_set_init": (_I, [_P, _P, _I]),
     "slrx_clear_init": (_I, [_P]),
     "slrx_set_filter": (_I, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -272,6 +273,24 @@ class Plan:
             raise ValueError("coil maps and coil data must both be host arrays or both device tensors")
         _check(lib().slrx_set_coils(self._h, nc, cp, bp, cm))
         self._keep_coils = (ck, bk)
+
+    def fit_t2(self, te_ms, img=None):
+        """Mono-exponential fit per pixel (``slrx_fit_t2``) of ``img`` (complex64
+        [T][P][Q], host array) or, with ``img=None``, of the plan's reconstruction.
+        Returns (T2, amplitude), float64 [P][Q] each."""
+        d = self.dims
+        te = np.ascontiguousarray(te_ms, dtype=np.float64)
+        if te.shape != (d.T,):
+            raise ValueError(f"expected {d.T} echo times, got {te.shape}")
+        t2 = np.empty((d.P, d.Q), np.float64)
+        amp = np.empty((d.P, d.Q), np.float64)
+        ip, keep = (None, None)
+        if img is not None:
+            ip, _, keep = _ptr(np.ascontiguousarray(img, dtype=np.complex64), np.complex64, self.shape)
+        _check(lib().slrx_fit_t2(self._h, ip, te.ctypes.data_as(ctypes.c_void_p),
+                                 t2.ctypes.data_as(ctypes.c_void_p), amp.ctypes.data_as(ctypes.c_void_p),
+                                 SLRX_MEM_HOST))
+        return t2, amp
 
     def set_init(self, x0):
         ptr, mem, keep = _ptr(x0, np.complex64, self.shape)

@@ -584,6 +584,47 @@ extern "C" slrx_status slrx_get_images(slrx_plan* pl, void* out, slrx_mem mem) {
   return copy_out(pl, out, pl->img, pl->vol() * sizeof(float2), mem);
 }
 
+extern "C" slrx_status slrx_fit_t2(slrx_plan* pl, const void* img, const double* te_ms, double* t2_out,
+                                   double* amp_out, slrx_mem mem) {
+  STCHK(check_idle(pl));
+  if (!te_ms || !t2_out) return fail(SLRX_EINVAL, "echo times or output pointer is NULL");
+  if (mem != SLRX_MEM_HOST && mem != SLRX_MEM_DEVICE) return fail(SLRX_EINVAL, "bad memory kind %d", (int)mem);
+  const slrx_dims& d = pl->d;
+  if (d.T < 2) return fail(SLRX_EINVAL, "a line fit needs at least two frames (T=%d)", d.T);
+  FitArgs fa{};
+  fa.npix = (long)d.P * d.Q;
+  fa.T = d.T;
+  double tbar = 0.0;
+  for (int t = 0; t < d.T; ++t) {
+    if (!std::isfinite(te_ms[t])) return fail(SLRX_EINVAL, "echo time %d is not finite", t);
+    fa.te[t] = te_ms[t];
+    tbar += te_ms[t];
+  }
+  tbar /= d.T;
+  double stt = 0.0;
+  for (int t = 0; t < d.T; ++t) stt += (te_ms[t] - tbar) * (te_ms[t] - tbar);
+  if (!(stt > 0.0)) return fail(SLRX_EINVAL, "echo times must not all be equal");
+  fa.tbar = tbar;
+  fa.stt = stt;
+  if (img) {
+    STCHK(copy_in(pl, pl->img, img, pl->vol() * sizeof(float2), mem));
+  } else {
+    STCHK(require_done(pl));
+    STCHK(images(pl));
+  }
+  // outputs staged in the CG scratch q (T >= 2 frames of complex64 hold two FP64 maps)
+  double* t2d = (double*)pl->q;
+  double* ampd = t2d + fa.npix;
+  fa.img = pl->img;
+  fa.t2 = t2d;
+  fa.amp = amp_out ? ampd : nullptr;
+  HIPCHK(launch_fit_t2(fa, pl->stream));
+  STCHK(copy_out(pl, t2_out, t2d, (size_t)fa.npix * sizeof(double), mem));
+  if (amp_out) STCHK(copy_out(pl, amp_out, ampd, (size_t)fa.npix * sizeof(double), mem));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  return SLRX_OK;
+}
+
 extern "C" slrx_status slrx_get_kspace(slrx_plan* pl, void* out, slrx_mem mem) {
   STCHK(require_done(pl));
   return copy_out(pl, out, pl->x, pl->vol() * sizeof(float2), mem);

@@ -112,6 +112,18 @@ hipError_t launch_coil_combine(const CoilArgs& a, hipStream_t s);
 hipError_t launch_coil_acc(long n, int P, int Q, const float2* Ct, const float2* w, float2* acc, bool assign,
                            hipStream_t s);
 
+// Mono-exponential fit per pixel (k_fit.hip); te holds the T echo times.
+struct FitArgs {
+  long npix;
+  int T;
+  const float2* img;     // [T][npix]
+  double te[32];
+  double tbar, stt;      // mean echo time, sum of squared centred times
+  double* t2;            // [npix]
+  double* amp;           // [npix] or null
+};
+hipError_t launch_fit_t2(const FitArgs& a, hipStream_t s);
+
 hipError_t launch_mask_data(long n, const uint8_t* S, const float2* b, float2* out, hipStream_t s);
 hipError_t launch_store_sum(const double* part, int n, double* dst, hipStream_t s);
 hipError_t launch_interleave(long n, const double* re, const double* im, double2* out, hipStream_t s);
