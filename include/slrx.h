@@ -157,9 +157,9 @@ slrx_status slrx_clear_init(slrx_plan* plan);
  *      the mask are ignored).
  * Copies both (host or device memory per mem).  Allocates 8 ((2 ncoils + 2) T
  * P Q + ncoils P Q) bytes of device memory beyond slrx_footprint, released by
- * slrx_plan_destroy or a later call.  SLRX_EINVAL for ncoils out of range or
- * NULL pointers; SLRX_ESTATE while the plan runs.  Plans with coils can be
- * run alone or in slrx_run_batch; servers take single-channel requests. */
+ * slrx_plan_destroy or a later call.  SLRX_EINVAL for ncoils out of range,
+ * NULL pointers or a bad mem; SLRX_EBUSY while the plan runs.  Plans with coils
+ * can be run alone or in slrx_run_batch; servers take single-channel requests. */
 #define SLRX_MAX_COILS 32
 slrx_status slrx_set_coils(slrx_plan* plan, int32_t ncoils, const void* C, const void* b, slrx_mem mem);
 /* Change the filter support; N1 N2 M must not exceed the sizes the plan was
