@@ -190,7 +190,7 @@ slrx_status slrx_get_stats(slrx_plan* plan, slrx_stats* out);
  * img and the outputs are host or device memory per mem.  Overwrites the
  * plan's image and CG scratch buffers (the reconstruction itself, x, is kept).
  * SLRX_EINVAL for T < 2, equal or non-finite echo times or NULL pointers;
- * SLRX_ESTATE without img before a completed run; SLRX_EBUSY while running. */
+ * SLRX_ENOTREADY without img before a completed run; SLRX_EBUSY while running. */
 slrx_status slrx_fit_t2(slrx_plan* plan, const void* img, const double* te_ms, double* t2_out, double* amp_out,
                         slrx_mem mem);
 
