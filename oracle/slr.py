@@ -76,30 +76,33 @@ def pair_index(M: int) -> list[tuple[int, int]]:
 
 
 # ------------------------------------------------------------------ lifting
-def lift(xhat: np.ndarray, N1: int, N2: int, M: int) -> np.ndarray:
+def lift(xhat: np.ndarray, N1: int, N2: int, M: int, circ_t: bool = False) -> np.ndarray:
     """Explicit lifted matrix T(xhat) in C^{(k P Q) x s} (Sec. II.B, eq. ``annihil-compact``).
 
     Rows (n, w) for n = M-1..T-1 (k = T-M+1 valid shifts along the parameter
     axis) and w in Z_P x Z_Q; columns (m, a).  Circular in space per the
-    hybrid approximation of Sec. III.A.  Tiny inputs only.
+    hybrid approximation of Sec. III.A.  With ``circ_t`` (the GIRAF
+    approximation, circular along the parameter axis too): all k = T rows
+    n = 0..T-1, frame index (n - m) mod T.  Tiny inputs only.
     """
     T, P, Q = xhat.shape
     a1, a2 = filter_offsets(N1, N2)
     NN = N1 * N2
-    k = T - M + 1
+    n0 = 0 if circ_t else M - 1
+    k = T - n0
     w1, w2 = np.meshgrid(np.arange(P), np.arange(Q), indexing="ij")
     out = np.zeros((k * P * Q, M * NN), dtype=np.complex128)
-    for n in range(M - 1, T):
-        rows = slice((n - (M - 1)) * P * Q, (n - M + 2) * P * Q)
+    for n in range(n0, T):
+        rows = slice((n - n0) * P * Q, (n - n0 + 1) * P * Q)
         for m in range(M):
             for ia in range(NN):
-                vals = xhat[n - m][(w1 - a1[ia]) % P, (w2 - a2[ia]) % Q]
+                vals = xhat[(n - m) % T][(w1 - a1[ia]) % P, (w2 - a2[ia]) % Q]
                 out[rows, m * NN + ia] = vals.ravel()
     return out
 
 
 # -------------------------------------------------------------- Gram matrix
-def gram(xhat: np.ndarray, N1: int, N2: int, M: int) -> np.ndarray:
+def gram(xhat: np.ndarray, N1: int, N2: int, M: int, circ_t: bool = False) -> np.ndarray:
     """Gram matrix R = T(xhat)^H T(xhat) by FFT autocorrelation (Sec. III.C).
 
     Block (m, m') of R (eq. ``eq:block-expression for R``) sums, over the
@@ -108,6 +111,7 @@ def gram(xhat: np.ndarray, N1: int, N2: int, M: int) -> np.ndarray:
     (2N1-1) x (2N2-1) lag neighbourhood (eq. ``eq:P_ij modified``).  Here
     R[(m,a),(m',a')] = sum_{n=M-1}^{T-1} F_u(conj(rho_{n-m}) rho_{n-m'})[a - a'],
     F_u the unnormalised forward DFT.  All M^2 blocks are formed directly.
+    ``circ_t``: the sum runs over n = 0..T-1 with frame indices mod T.
     """
     T, P, Q = xhat.shape
     rho = idft2(xhat)
@@ -119,8 +123,8 @@ def gram(xhat: np.ndarray, N1: int, N2: int, M: int) -> np.ndarray:
     for m in range(M):
         for mp in range(M):
             c = np.zeros((P, Q), dtype=np.complex128)
-            for n in range(M - 1, T):
-                c += np.conj(rho[n - m]) * rho[n - mp]
+            for n in range(0 if circ_t else M - 1, T):
+                c += np.conj(rho[(n - m) % T]) * rho[(n - mp) % T]
             g = np.fft.fft2(c)
             R[m * NN:(m + 1) * NN, mp * NN:(mp + 1) * NN] = g[d1, d2]
     return R
@@ -185,30 +189,31 @@ def penalty_masks(U: np.ndarray, alpha: np.ndarray, N1: int, N2: int, M: int,
     return E.reshape(M, M, P, Q)
 
 
-def penalty_apply(rho: np.ndarray, E: np.ndarray) -> np.ndarray:
+def penalty_apply(rho: np.ndarray, E: np.ndarray, circ_t: bool = False) -> np.ndarray:
     """Image-domain penalty operator G (Sec. III.A, eq. ``eq:grad_ls``).
 
     J = sum_{n=M-1}^{T-1} sum_r z^H E_r z with z_m = rho_{n-m}(r); returns
-    dJ/d conj(rho): (G rho)_{n-m} += sum_m' E[m, m'] rho_{n-m'}.
+    dJ/d conj(rho): (G rho)_{n-m} += sum_m' E[m, m'] rho_{n-m'}.  ``circ_t``:
+    n = 0..T-1 and frame indices mod T.
     """
     M = E.shape[0]
     T = rho.shape[0]
     out = np.zeros_like(rho, dtype=np.complex128)
-    for n in range(M - 1, T):
+    for n in range(0 if circ_t else M - 1, T):
         for m in range(M):
             for mp in range(M):
-                out[n - m] += E[m, mp] * rho[n - mp]
+                out[(n - m) % T] += E[m, mp] * rho[(n - mp) % T]
     return out
 
 
-def penalty_value(rho: np.ndarray, E: np.ndarray) -> float:
+def penalty_value(rho: np.ndarray, E: np.ndarray, circ_t: bool = False) -> float:
     """J(rho) = <rho, G rho> (real by construction)."""
-    return float(np.vdot(rho, penalty_apply(rho, E)).real)
+    return float(np.vdot(rho, penalty_apply(rho, E, circ_t)).real)
 
 
-def normal_apply(xhat: np.ndarray, S: np.ndarray, E: np.ndarray, lam: float) -> np.ndarray:
+def normal_apply(xhat: np.ndarray, S: np.ndarray, E: np.ndarray, lam: float, circ_t: bool = False) -> np.ndarray:
     """Normal operator of eq. ``eq:grad_ls``: S o xhat + lam F G F^* xhat (A = S, single coil)."""
-    return S * xhat + lam * dft2(penalty_apply(idft2(xhat), E))
+    return S * xhat + lam * dft2(penalty_apply(idft2(xhat), E, circ_t))
 
 
 # ------------------------------------------------------------ multichannel
@@ -226,10 +231,11 @@ def coil_adjoint(b: np.ndarray, S: np.ndarray, C: np.ndarray) -> np.ndarray:
     return dft2(acc)
 
 
-def coil_normal(xhat: np.ndarray, S: np.ndarray, C: np.ndarray, E: np.ndarray, lam: float) -> np.ndarray:
+def coil_normal(xhat: np.ndarray, S: np.ndarray, C: np.ndarray, E: np.ndarray, lam: float,
+                circ_t: bool = False) -> np.ndarray:
     """Normal operator with the multichannel data term: A^H A xhat + lam F G F^* xhat."""
     rho = idft2(xhat)
-    acc = lam * penalty_apply(rho, E)
+    acc = lam * penalty_apply(rho, E, circ_t)
     for j in range(C.shape[0]):
         acc = acc + np.conj(C[j])[None] * idft2(S * dft2(C[j][None] * rho))
     return dft2(acc)
@@ -267,7 +273,7 @@ def irls(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
          n_irls: int, n_cg: int, p: float = 0.6, gamma: float = 1.4,
          eps0_frac: float = 0.01, x0: np.ndarray | None = None,
          trace: dict | None = None, return_kspace: bool = False,
-         coils: np.ndarray | None = None) -> np.ndarray:
+         coils: np.ndarray | None = None, circ_t: bool = False) -> np.ndarray:
     """Algorithm 1: alternate the weight update and the CG least-squares step.
 
     Step 1 (Sec. III.C): Gram matrix by FFT autocorrelation, eigen-decomposition,
@@ -278,20 +284,23 @@ def irls(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
     With ``coils`` (sensitivities C, [Nc][P][Q]) the data b is [Nc][T][P][Q] and
     the least-squares step uses the multichannel model of Sec. II.A:
     (A^H A + lam F G F^*) xhat = A^H b, starting from A^H b.
+
+    ``circ_t``: the GIRAF approximation the paper compares against (Sec. IV,
+    Fig. 3), circular along the parameter axis as well as in space.
     """
     S = S.astype(np.float64)
     if coils is None:
         b = S * b.astype(np.complex128)
-        normal = lambda v, E: normal_apply(v, S, E, lam)
+        normal = lambda v, E: normal_apply(v, S, E, lam, circ_t)
     else:
         C = coils.astype(np.complex128)
         b = coil_adjoint(S[None] * b.astype(np.complex128), S, C)
-        normal = lambda v, E: coil_normal(v, S, C, E, lam)
+        normal = lambda v, E: coil_normal(v, S, C, E, lam, circ_t)
     T, P, Q = b.shape
     x = b.copy() if x0 is None else x0.astype(np.complex128).copy()
     eps = None
     for _ in range(n_irls):
-        R = gram(x, N1, N2, M)
+        R = gram(x, N1, N2, M, circ_t)
         lamR, U = np.linalg.eigh(R)
         if eps is None:
             eps = eps0_frac * float(lamR.max())

@@ -13,22 +13,25 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # (original text, planted mistake) in oracle/slr.py
 MUTATIONS = {
-    "gram_conj_swap": ("c += np.conj(rho[n - m]) * rho[n - mp]", "c += rho[n - m] * np.conj(rho[n - mp])"),
+    "gram_conj_swap": ("c += np.conj(rho[(n - m) % T]) * rho[(n - mp) % T]",
+                       "c += rho[(n - m) % T] * np.conj(rho[(n - mp) % T])"),
     "gram_lag_sign": ("d1 = (a1[:, None] - a1[None, :]) % P", "d1 = (a1[None, :] - a1[:, None]) % P"),
-    "gram_range": ("for n in range(M - 1, T):\n                c +=", "for n in range(M, T):\n                c +="),
+    "gram_range": ("for n in range(0 if circ_t else M - 1, T):\n                c +=",
+                   "for n in range(0 if circ_t else M, T):\n                c +="),
     "spectra_sign": ("return scipy.fft.ifft2(frames, workers=-1) * (P * Q)", "return scipy.fft.fft2(frames, workers=-1)"),
     "alpha_exponent": ("alpha = (np.maximum(lam, 0.0) + eps) ** (p / 2.0 - 1.0)",
                        "alpha = (np.maximum(lam, 0.0) + eps) ** (p / 2.0 - 0.5)"),
     "mask_conj": ('E[m, mp] += np.einsum("ir,ir->r", cmu[:, m], mu[:, mp])',
                   'E[m, mp] += np.einsum("ir,ir->r", mu[:, m], cmu[:, mp])'),
-    "penalty_swap": ("out[n - m] += E[m, mp] * rho[n - mp]", "out[n - mp] += E[m, mp] * rho[n - m]"),
-    "normal_transform_order": ("return S * xhat + lam * dft2(penalty_apply(idft2(xhat), E))",
-                               "return S * xhat + lam * idft2(penalty_apply(dft2(xhat), E))"),
+    "penalty_swap": ("out[(n - m) % T] += E[m, mp] * rho[(n - mp) % T]",
+                     "out[(n - mp) % T] += E[m, mp] * rho[(n - m) % T]"),
+    "normal_transform_order": ("return S * xhat + lam * dft2(penalty_apply(idft2(xhat), E, circ_t))",
+                               "return S * xhat + lam * idft2(penalty_apply(dft2(xhat), E, circ_t))"),
     "cg_beta": ("p = r + (rr_new / rr) * p", "p = r + (rr / rr_new) * p"),
     "eps_schedule": ("eps = eps / gamma", "eps = eps * gamma"),
     "eps_start": ("eps = eps0_frac * float(lamR.max())", "eps = eps0_frac * float(lamR.min() + lamR.max()/2)"),
-    "lift_shift": ("vals = xhat[n - m][(w1 - a1[ia]) % P, (w2 - a2[ia]) % Q]",
-                   "vals = xhat[n - m][(w1 + a1[ia]) % P, (w2 - a2[ia]) % Q]"),
+    "lift_shift": ("vals = xhat[(n - m) % T][(w1 - a1[ia]) % P, (w2 - a2[ia]) % Q]",
+                   "vals = xhat[(n - m) % T][(w1 + a1[ia]) % P, (w2 - a2[ia]) % Q]"),
 }
 # mistakes in the multichannel data term, checked against its own pins
 COIL_MUTATIONS = {
@@ -47,10 +50,18 @@ T2_MUTATIONS = {
     "t2_uncentred": ("tc = te - te.mean()", "tc = te"),
     "t2_amplitude": ("amp = np.exp(ybar - slope * te.mean())", "amp = np.exp(ybar)"),
 }
+# mistakes in the circular (GIRAF) variant, checked against its own pins
+GIRAF_MUTATIONS = {
+    "giraf_gram_range": ("for n in range(0 if circ_t else M - 1, T):\n                c +=",
+                         "for n in range(1 if circ_t else M - 1, T):\n                c +="),
+    "giraf_penalty_wrap": ("out[(n - m) % T] += E[m, mp] * rho[(n - mp) % T]",
+                           "out[(n - m) % T] += E[m, mp] * rho[max(n - mp, 0)]"),
+}
 PIN_FILE = {name: "tests/test_oracle_pins.py" for name in MUTATIONS}
+PIN_FILE.update({name: "tests/test_oracle_giraf.py" for name in GIRAF_MUTATIONS})
 PIN_FILE.update({name: "tests/test_oracle_coils.py" for name in COIL_MUTATIONS})
 PIN_FILE.update({name: "tests/test_oracle_t2.py" for name in T2_MUTATIONS})
-ALL = dict(MUTATIONS, **COIL_MUTATIONS, **T2_MUTATIONS)
+ALL = dict(MUTATIONS, **COIL_MUTATIONS, **T2_MUTATIONS, **GIRAF_MUTATIONS)
 
 
 @pytest.mark.parametrize("name", sorted(ALL))
