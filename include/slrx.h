@@ -81,6 +81,11 @@ typedef struct {
 #define SLRX_FLAG_LIBEIGH 4u /* eigen-decomposition entirely by rocSOLVER zheevd (reference
                                 path); default: own Householder tridiagonalisation, divide
                                 and conquer and back-transformation on the GPU */
+#define SLRX_FLAG_GIRAF 8u  /* the GIRAF approximation the paper compares with (Sec. IV,
+                               Fig. 3): the lifting circular along the parameter axis
+                               as well as in space (all T shifts, frame indices mod T)
+                               in the Gram matrix and the penalty; default: the hybrid
+                               lifting, linear along the parameter axis (Sec. III.A) */
 /* With SLRX_FLAG_KTIME: time only the classes whose bits are set here (none set:
  * every class).  Each timed region adds two events to the stream. */
 #define SLRX_FLAG_KTIME_CLASS(c) (1u << (16 + (c)))

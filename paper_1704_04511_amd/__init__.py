@@ -35,6 +35,7 @@ SLRX_MEM_DEVICE = 1
 SLRX_FLAG_TIMING = 1
 SLRX_FLAG_KTIME = 2
 SLRX_FLAG_LIBEIGH = 4
+SLRX_FLAG_GIRAF = 8
 MAX_IRLS = 256
 KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "tri", "tdeig", "backtr", "filter", "masks", "coil")
 
@@ -163,10 +164,11 @@ def default_params() -> Params:
 
 
 def make_params(lam=1e-3, n_irls=15, n_cg=10, p=0.6, gamma=1.4, eps0_frac=0.01, timing=False,
-                ktime=False, lib_eigh=False, ktime_classes=None) -> Params:
-    """ktime_classes: names from KERNEL_CLASSES to time (default: all, when ktime is set)."""
+                ktime=False, lib_eigh=False, ktime_classes=None, giraf=False) -> Params:
+    """ktime_classes: names from KERNEL_CLASSES to time (default: all, when ktime is set);
+    giraf: the lifting circular along the parameter axis too (SLRX_FLAG_GIRAF)."""
     flags = ((SLRX_FLAG_TIMING if timing else 0) | (SLRX_FLAG_KTIME if ktime else 0)
-             | (SLRX_FLAG_LIBEIGH if lib_eigh else 0))
+             | (SLRX_FLAG_LIBEIGH if lib_eigh else 0) | (SLRX_FLAG_GIRAF if giraf else 0))
     for c in ktime_classes or ():
         flags |= 1 << (16 + KERNEL_CLASSES.index(c))
     return Params(float(lam), float(p), float(gamma), float(eps0_frac), int(n_irls), int(n_cg), flags)

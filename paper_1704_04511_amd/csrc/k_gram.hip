@@ -3,7 +3,8 @@
 // penalty masks E (summed power spectra of the weighted filters).
 //
 // Gram (Sec. III.C, eq. "eq:block-expression for R" and eq. "eq:P_ij modified"):
-//   c_{m,m'}(r) = sum_{n=M-1}^{T-1} conj(rho_{n-m}(r)) rho_{n-m'}(r),
+//   c_{m,m'}(r) = sum_{n=M-1}^{T-1} conj(rho_{n-m}(r)) rho_{n-m'}(r)
+// (the GIRAF variant: n = 0..T-1, frame indices mod T),
 //   R[(m,a),(m',a')] = F_u(c_{m,m'})[a - a'],
 // where only the (2N1-1) x (2N2-1) lags of the sliding window are ever read,
 // so F_u is evaluated at those lags only (a pruned DFT, two small passes).
@@ -38,11 +39,13 @@ __global__ __launch_bounds__(256) void k_gram_rows(GramArgs a) {
     double2 acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = make_double2(0.0, 0.0);
+    // z[m] = rho_{n-m}; with circ the sum starts at n = 0 and frame indices wrap
+    const int n0 = a.circ ? 0 : M - 1;
     double2 z[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) z[m] = f2d(a.rho[(long)(M - 1 - m) * fs + off]);
-    for (int n = M - 1; n < T; ++n) {
-      if (n > M - 1) {
+    for (int m = 0; m < M; ++m) z[m] = f2d(a.rho[(long)((n0 - m + T) % T) * fs + off]);
+    for (int n = n0; n < T; ++n) {
+      if (n > n0) {
 #pragma unroll
         for (int m = M - 1; m > 0; --m) z[m] = z[m - 1];
         z[0] = f2d(a.rho[(long)n * fs + off]);

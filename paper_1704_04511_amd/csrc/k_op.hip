@@ -188,12 +188,42 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
   // frames keep the windowed sum; when T < 2M-1 there is no Toeplitz part and
   // one thread per pixel runs the windowed sum over all frames.
   const float sc = a.scale;  // lam / (P Q)
-  const bool split = T >= 2 * M - 1;
+  const bool circ = a.circ != 0;
+  const bool split = !circ && T >= 2 * M - 1;
   auto mac = [](float2 acc, float2 c, float2 x) {
     return make_float2(acc.x + c.x * x.x - c.y * x.y, acc.y + c.x * x.y + c.y * x.x);
   };
   auto E = [&](int m, int mp) { return (m <= mp) ? e[pair_id(m, mp, M)] : cconj(e[pair_id(mp, m, M)]); };
   float2 rho[kTMax], rt[ME];  // rt[i] = rho_{T-1-i}
+  // GIRAF: every window is complete and G is circulant along the frames,
+  // (G rho)_t = sum_{d=-(M-1)}^{M-1} g_d rho_{(t+d) mod T}, g_{-d} = u_d, g_d = conj(u_d);
+  // outputs of parity h kept in registers until every input is read
+  float2 gout[kTMax / 2];
+  if (circ && has_pix) {
+    float2 u[M];
+#pragma unroll
+    for (int d = 0; d < M; ++d) {
+      float2 s = e[pair_id(0, d, M)];
+#pragma unroll
+      for (int m = 1; m + d < M; ++m) s = cadd(s, e[pair_id(m, m + d, M)]);
+      u[d] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < kTMax / 2; ++i) {
+      const int t = 2 * i + h;
+      float2 acc = make_float2(0.f, 0.f);
+      if (t < T) {
+        acc = mac(acc, u[0], lds[t * per_t + pl]);
+#pragma unroll
+        for (int d = 1; d < M; ++d) {
+          const int lo = ((t - d) % T + T) % T, hi = (t + d) % T;
+          acc = mac(acc, u[d], lds[lo * per_t + pl]);
+          acc = mac(acc, cconj(u[d]), lds[hi * per_t + pl]);
+        }
+      }
+      gout[i] = cscale(acc, sc);
+    }
+  }
   if (split && has_pix) {
 #pragma unroll
     for (int t = 0; t < kTMax; ++t) rho[t] = t < T ? lds[t * per_t + pl] : make_float2(0.f, 0.f);
@@ -201,6 +231,11 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
     for (int i = 0; i < ME; ++i) rt[i] = lds[(T - 1 - i) * per_t + pl];
   }
   __syncthreads();  // every input read before any output is written in place
+  if (circ && has_pix) {
+#pragma unroll
+    for (int i = 0; i < kTMax / 2; ++i)
+      if (2 * i + h < T) lds[(2 * i + h) * per_t + pl] = gout[i];
+  }
   if (split && has_pix) {
     float2 u[M];
 #pragma unroll
@@ -245,7 +280,7 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
         for (int mp = 0; mp < M; ++mp) acc = mac(acc, E(m, mp), rt[q - m + mp]);
       lds[t * per_t + pl] = cscale(acc, sc);
     }
-  } else if (!split && has_pix && h == 0) {
+  } else if (!circ && !split && has_pix && h == 0) {
     // windowed sum over n with a sliding register window: z[m] = rho_{n-m};
     // acc[m] collects output frame n - m, written once complete
     float2 z[M], acc[M];

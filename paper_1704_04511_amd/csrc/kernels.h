@@ -58,6 +58,7 @@ struct PenArgs {
   int nc;
   const float2* rho;     // image rho_u, transposed
   const float2* d;       // coil combination, transposed
+  int circ;              // G circulant along the frames (GIRAF)
 };
 hipError_t launch_pen(const PenArgs& a, hipStream_t s);
 
@@ -140,6 +141,7 @@ struct GramArgs {
   int rowmajor;
   const double2* twP;       // e^{-2 pi i t/P}, t < P
   const double2* twQ;
+  int circ;                 // lagged sums over all n with frame indices mod T (GIRAF)
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t s);
 

@@ -96,6 +96,7 @@ slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor, double2* R_out) {
   ga.rowmajor = lib ? 0 : 1;
   ga.twP = pl->twPd;
   ga.twQ = pl->twQd;
+  ga.circ = (pl->prm.flags & SLRX_FLAG_GIRAF) ? 1 : 0;
   HIPCHK(launch_gram(ga, pl->stream));
   return SLRX_OK;
 }
@@ -325,6 +326,7 @@ slrx_status slrx::penalty_pass(slrx_plan* pl) {
   pa.Et = pl->Et;
   pa.scale = (float)(pl->prm.lambda / ((double)d.P * d.Q));
   pa.tw = pl->twPf;
+  pa.circ = (pl->prm.flags & SLRX_FLAG_GIRAF) ? 1 : 0;
   if (pl->ncoils > 0) {
     pa.nc = pl->ncoils;
     pa.rho = pl->rho;
