@@ -324,13 +324,23 @@ def bench_c2(args) -> int:
     t2_dev, _ = plan.fit_t2(te)  # per-pixel fit on the GPU (host copy of the maps included)
     fit_ms = (time.perf_counter() - tf) * 1e3
     plan.close()
+    # the GIRAF approximation on the same data (circular along the echoes too; Sec. IV, Fig. 3)
+    gprm = slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg, p=pb.p, gamma=pb.gamma,
+                            eps0_frac=pb.eps0_frac, giraf=True)
+    with slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, gprm) as gp:
+        gp.set_kspace(pb.b)
+        gp.set_mask(pb.S)
+        gp.run()
+        gp.sync()
+        img_giraf = gp.images()
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
     ora = oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, pb.n_irls, pb.n_cg, p=pb.p, gamma=pb.gamma,
                       eps0_frac=pb.eps0_frac)
     dto = time.perf_counter() - t0
     mask = np.abs(pb.truth[0]) > 0.1 * np.abs(pb.truth[0]).max()
-    t2g, t2o, t2t = (t2_map(v, te, mask) for v in (img, ora, pb.truth))
+    t2g, t2o, t2t, t2f = (t2_map(v, te, mask) for v in (img, ora, pb.truth, img_giraf))
+    nrm = lambda a: float(np.linalg.norm(a - pb.truth) / np.linalg.norm(pb.truth))
     rel = lambda a, b: float(np.median(np.abs(a - b) / np.abs(b)))
     out = {
         "metric": "IRLS iters/s (128x128x16, filter 9x9x5)", "value": round(pb.n_irls * args.steps / dt, 3),
@@ -346,6 +356,10 @@ def bench_c2(args) -> int:
         "t2_median_rel_diff_gpu_vs_oracle": float(f"{rel(t2g, t2o):.3e}"),
         "t2_gpu_fit_max_rel_diff_vs_host_fit": float(f"{np.max(np.abs(t2_dev[mask] - t2g) / np.abs(t2g)):.3e}"),
         "t2_gpu_fit_ms": round(fit_ms, 3),
+        "approximation_study": {"recon_nrmse_vs_truth_hybrid": round(nrm(img), 5),
+                                "recon_nrmse_vs_truth_giraf": round(nrm(img_giraf), 5),
+                                "t2_median_rel_err_vs_truth_hybrid": round(rel(t2g, t2t), 5),
+                                "t2_median_rel_err_vs_truth_giraf": round(rel(t2f, t2t), 5)},
         "cpu_baseline": {"value": pb.n_irls / dto, "unit": "IRLS iter/s", "cores": cores, "kind": "oracle",
                          "sample": f"the whole reconstruction ({pb.n_irls} outer iterations), {dto:.1f} s wall"},
     }

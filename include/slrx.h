@@ -160,8 +160,9 @@ slrx_status slrx_clear_init(slrx_plan* plan);
  *   C: complex64 [ncoils][P][Q] sensitivities, row-major frames;
  *   b: complex64 [ncoils][T][P][Q] coil k-space, DC at [0][0] (entries off
  *      the mask are ignored).
- * Copies both (host or device memory per mem).  Allocates 8 ((2 ncoils + 2) T
- * P Q + ncoils P Q) bytes of device memory beyond slrx_footprint, released by
+ * Copies both (host or device memory per mem).  Allocates 8 ((2 ncoils + 1 +
+ * min(ncoils, 4)) T P Q + ncoils P Q) bytes of device memory beyond
+ * slrx_footprint, released by
  * slrx_plan_destroy or a later call.  SLRX_EINVAL for ncoils out of range,
  * NULL pointers or a bad mem; SLRX_EBUSY while the plan runs.  Plans with coils
  * can be run alone or in slrx_run_batch; servers take single-channel requests. */

@@ -178,7 +178,7 @@ static Layout plan_layout(const slrx_dims& d) {
   sz[B_RRH] = (kMaxCg + 2) * 8;
   sz[B_SCAL] = 64 * 8;
   sz[B_STATS] = 3 * SLRX_MAX_IRLS * 8;
-  sz[B_INFO] = (SLRX_MAX_IRLS + 1) * 4;
+  sz[B_INFO] = (kInfoEntries) * 4;
   sz[B_FLAG] = 64;
   sz[B_AW] = s * s * 16;
   sz[B_UZ] = s * s * 16;
@@ -431,7 +431,7 @@ extern "C" slrx_status slrx_set_coils(slrx_plan* pl, int32_t ncoils, const void*
     pl->ncoils_cap = 0;
     pl->Ct = pl->Bc = pl->Yc = pl->rho = pl->dco = nullptr;
     if (ncoils > 0) {
-      const size_t elems = (size_t)ncoils * pq + 2 * (size_t)ncoils * V + 2 * V;
+      const size_t elems = (size_t)ncoils * pq + 2 * (size_t)ncoils * V + (1 + (size_t)coil_groups(ncoils)) * V;
       HIPCHK(hipMalloc(&pl->coil_mem, elems * sizeof(float2)));
       pl->ncoils_cap = ncoils;
       pl->Ct = (float2*)pl->coil_mem;
@@ -512,7 +512,7 @@ slrx_status slrx::enqueue_run(slrx_plan* pl) {
       pl->ev_phase.push_back(e);
     }
   }
-  HIPCHK(hipMemsetAsync(pl->info, 0, (SLRX_MAX_IRLS + 1) * sizeof(rocblas_int), pl->stream));
+  HIPCHK(hipMemsetAsync(pl->info, 0, kInfoEntries * sizeof(rocblas_int), pl->stream));
   HIPCHK(hipEventRecord(pl->ev_run[0], pl->stream));
   for (int it = 0; it < nirls; ++it) {
     if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it], pl->stream));
@@ -543,8 +543,12 @@ slrx_status slrx::finish(slrx_plan* pl) {
   HIPCHK(hipEventSynchronize(pl->ev_run[1]));
   pl->running = false;
   pl->ran = true;
-  std::vector<rocblas_int> info(pl->run_irls);
-  HIPCHK(hipMemcpy(info.data(), pl->info, pl->run_irls * sizeof(rocblas_int), hipMemcpyDeviceToHost));
+  std::vector<rocblas_int> info(kInfoEntries);
+  HIPCHK(hipMemcpy(info.data(), pl->info, kInfoEntries * sizeof(rocblas_int), hipMemcpyDeviceToHost));
+  if (info[kInfoNonfinite] != 0) {
+    pl->ran = false;
+    return fail(SLRX_ENUMERIC, "non-finite Gram matrix (non-finite data, initial guess or iterate)");
+  }
   std::vector<double> st(3 * SLRX_MAX_IRLS);
   HIPCHK(hipMemcpy(st.data(), pl->stats, st.size() * sizeof(double), hipMemcpyDeviceToHost));
   for (int it = 0; it < pl->run_irls; ++it) {

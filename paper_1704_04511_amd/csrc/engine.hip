@@ -127,7 +127,7 @@ slrx_status slrx::engine_begin(slrx_plan* pl) {
   STCHK(prepare(pl));
   pl->ktime = false;
   for (int c = 0; c < SLRX_K_NCLASS; ++c) pl->kused[c] = 0;
-  HIPCHK(hipMemsetAsync(pl->info, 0, (SLRX_MAX_IRLS + 1) * sizeof(rocblas_int), pl->stream));
+  HIPCHK(hipMemsetAsync(pl->info, 0, kInfoEntries * sizeof(rocblas_int), pl->stream));
   HIPCHK(hipEventRecord(pl->ev_run[0], pl->stream));
   pl->it_next = 0;
   pl->running = true;

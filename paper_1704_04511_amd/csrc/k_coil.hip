@@ -9,14 +9,15 @@
 //      the forward column DFT of C_j rho_u;
 //   2. k_coil_rows (per k-space row tile, frame and coil): forward row DFT, the
 //      frame's sampling mask, inverse row DFT;
-//   3. k_coil_combine (per column tile and frame): the coil combination
-//      d = (PQ)^-2 sum_j conj(C_j) IDFT_col(Y_j), one coil after another with
-//      the next coil's loads in flight during the current transform;
-// and the column pass (k_cols_pen, coil mode) adds d to the penalty before its
-// forward column DFT.  All transforms here are unnormalised; the (PQ)^-2 makes
-// the composition the unitary operator.  Volumes use the transposed layout of
-// the column pass ([t][c][r]); the coil maps are stored transposed per coil
-// ([j][c][r]).
+//   3. k_coil_combine (per column tile, frame and group of coils): the coil
+//      combination d_g = (PQ)^-2 sum_{j in group g} conj(C_j) IDFT_col(Y_j),
+//      one coil after another with the next coil's loads in flight during the
+//      current transform;
+// and the column pass (k_cols_pen, coil mode) adds d_0 + d_1 + ... (in that
+// order) to the penalty before its forward column DFT.  All transforms here
+// are unnormalised; the (PQ)^-2 makes the composition the unitary operator.
+// Volumes use the transposed layout of the column pass ([t][c][r]); the coil
+// maps are stored transposed per coil ([j][c][r]).
 #include "common.h"
 #include "fft.h"
 #include "kernels.h"
@@ -101,9 +102,11 @@ __global__ __launch_bounds__(kCoilNT) void k_coil_rows(CoilArgs a) {
 }
 
 // ---------------------------------------------------- pass 3: coil combine
-// Block: CB columns of one frame.  d = cscale sum_j conj(C_j) IDFT_col(Y_j),
-// coils in order (a fixed summation order); each thread keeps the sums of its
-// elements in registers and loads coil j+1 while coil j is transformed.
+// Block: CB columns of one frame and one group g of coils (a balanced split of
+// the coils into the groups of the grid's z dimension).
+// d_g = cscale sum_{j in g} conj(C_j) IDFT_col(Y_j), coils in order (a fixed
+// summation order); each thread keeps the sums of its elements in registers
+// and loads coil j+1 while coil j is transformed.
 template <int N>
 __global__ __launch_bounds__(kCoilNT) void k_coil_combine(CoilArgs a) {
   constexpr int CAP = CoilCap<N>::v;
@@ -113,7 +116,8 @@ __global__ __launch_bounds__(kCoilNT) void k_coil_combine(CoilArgs a) {
   __shared__ float2 twt[fft_tw_size<N>()];
   const int P = a.P, Q = a.Q;
   const int CB = coil_col_block(CAP, Q);
-  const int c0 = blockIdx.x * CB, f = blockIdx.y;
+  const int c0 = blockIdx.x * CB, f = blockIdx.y, g = blockIdx.z;
+  const int j0 = g * a.nc / a.groups, j1 = (g + 1) * a.nc / a.groups;  // coils of group g
   const long fs = (long)P * Q;
   const long base = (long)f * fs + (long)c0 * P;
   const int nel = CB * N;
@@ -125,11 +129,11 @@ __global__ __launch_bounds__(kCoilNT) void k_coil_combine(CoilArgs a) {
     const int e = threadIdx.x + u * kCoilNT;
     acc[u] = make_float2(0.f, 0.f);
     if (e < nel) {
-      y[u] = a.Y[base + e];
-      cj[u] = a.Ct[(long)c0 * P + e];
+      y[u] = a.Y[(long)j0 * a.vstride + base + e];
+      cj[u] = a.Ct[(long)j0 * fs + (long)c0 * P + e];
     }
   }
-  for (int j = 0; j < a.nc; ++j) {
+  for (int j = j0; j < j1; ++j) {
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int e = threadIdx.x + u * kCoilNT;
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(kCoilNT) void k_coil_combine(CoilArgs a) {
     float2 cur[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) cur[u] = cj[u];
-    if (j + 1 < a.nc) {  // next coil in flight during this transform
+    if (j + 1 < j1) {  // next coil in flight during this transform
       const float2* Yn = a.Y + (long)(j + 1) * a.vstride + base;
       const float2* Cn = a.Ct + (long)(j + 1) * fs + (long)c0 * P;
 #pragma unroll
@@ -158,10 +162,11 @@ __global__ __launch_bounds__(kCoilNT) void k_coil_combine(CoilArgs a) {
       if (e < nel) acc[u] = cadd(acc[u], cmul(cconj(cur[u]), lds[at(e)]));
     }
   }
+  float2* dg = a.d + (long)g * a.vstride;
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
     const int e = threadIdx.x + u * kCoilNT;
-    if (e < nel) a.d[base + e] = cscale(acc[u], a.cscale);
+    if (e < nel) dg[base + e] = cscale(acc[u], a.cscale);
   }
 }
 
@@ -188,7 +193,7 @@ hipError_t launch_coil_cols(const CoilArgs& a, hipStream_t s) { SLRX_DISPATCH_N(
 template <int N>
 static hipError_t coil_combine_n(const CoilArgs& a, hipStream_t s) {
   const int cb = coil_col_block(CoilCap<N>::v, a.Q);
-  k_coil_combine<N><<<dim3(a.Q / cb, a.T), kCoilNT, 0, s>>>(a);
+  k_coil_combine<N><<<dim3(a.Q / cb, a.T, a.groups), kCoilNT, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_coil_combine(const CoilArgs& a, hipStream_t s) { SLRX_DISPATCH_N(a.P, coil_combine_n, a, s) }

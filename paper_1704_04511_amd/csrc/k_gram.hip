@@ -133,6 +133,12 @@ __global__ __launch_bounds__(256) void k_gram_assemble(GramArgs a) {
     const int w = pair_id(mp, m, M);
     v = dconj(a.g[((size_t)w * L1 + (b1 - a1 + N1 - 1)) * L2 + (b2 - a2 + N2 - 1)]);
   }
+  // a non-finite entry (non-finite data or iterate) is reported and replaced by
+  // zero, so the eigen-decomposition only ever sees finite input
+  if (!isfinite(v.x) || !isfinite(v.y)) {
+    v = make_double2(0.0, 0.0);
+    if (a.bad) *a.bad = 1;
+  }
   a.R[idx] = v;
 }
 

@@ -311,7 +311,11 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
   if (coil) {  // multichannel data term: the coil combination of k_coil_combine
     __syncthreads();  // the windowed sum writes every frame of a pixel from one thread
     if (has_pix)
-      for (int t = h; t < T; t += 2) lds[t * per_t + pl] = cadd(lds[t * per_t + pl], a.d[(long)t * fs + po]);
+      for (int t = h; t < T; t += 2) {
+        float2 s = lds[t * per_t + pl];
+        for (int g = 0; g < a.dparts; ++g) s = cadd(s, a.d[(long)g * a.dstride + (long)t * fs + po]);
+        lds[t * per_t + pl] = s;
+      }
   }
   __syncthreads();
   fft_lds<N, -1, MAXB, kPenNT>(lds, twt, T * CB);

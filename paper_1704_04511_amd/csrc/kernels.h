@@ -57,7 +57,9 @@ struct PenArgs {
   // combination d (k_coil_combine) added before the forward transform
   int nc;
   const float2* rho;     // image rho_u, transposed
-  const float2* d;       // coil combination, transposed
+  const float2* d;       // per-group coil sums, transposed, group g at g * dstride
+  int dparts;            // number of groups
+  long dstride;
   int circ;              // G circulant along the frames (GIRAF)
 };
 hipError_t launch_pen(const PenArgs& a, hipStream_t s);
@@ -103,9 +105,14 @@ struct CoilArgs {
   long vstride;
   const uint8_t* S;      // sampling mask, row-major [t][kr][kc]
   const float2* tw;      // twiddles of the pass's transform length (P: columns, Q: rows)
-  float2* d;             // out of the combine pass: coil combination (transposed)
+  float2* d;             // out of the combine pass: per-group coil sums (transposed), group g at g * vstride
   float cscale;          // (P Q)^-2
+  int groups;            // coil groups of the combine pass (coil_groups(nc))
 };
+// Coils are combined in up to kCoilGroups groups in parallel, their sums added
+// in group order by the column pass.
+constexpr int kCoilGroups = 4;
+inline int coil_groups(int nc) { return nc < kCoilGroups ? nc : kCoilGroups; }
 hipError_t launch_coil_cols(const CoilArgs& a, hipStream_t s);
 hipError_t launch_coil_rows(const CoilArgs& a, hipStream_t s);
 hipError_t launch_coil_combine(const CoilArgs& a, hipStream_t s);
@@ -142,6 +149,7 @@ struct GramArgs {
   const double2* twP;       // e^{-2 pi i t/P}, t < P
   const double2* twQ;
   int circ;                 // lagged sums over all n with frame indices mod T (GIRAF)
+  int* bad;                 // set to 1 if any entry is non-finite (then written as 0), or null
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t s);
 

@@ -11,6 +11,10 @@ namespace slrx {
 
 constexpr int kMaxS = 4096;    // largest filter size s = N1 N2 M
 constexpr int kMaxCg = 10000;  // largest CG iteration count
+// info: eigensolver status per outer iteration, the single-step slot
+// (SLRX_MAX_IRLS), and a flag raised by the Gram pass on a non-finite entry
+constexpr int kInfoNonfinite = SLRX_MAX_IRLS + 1;
+constexpr int kInfoEntries = SLRX_MAX_IRLS + 2;
 
 enum Buf {
   B_B, B_BM, B_X0, B_IMG, B_X, B_R, B_P, B_Q, B_T, B_S, B_ET, B_ESTAGE,

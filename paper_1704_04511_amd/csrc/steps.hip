@@ -97,6 +97,7 @@ slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor, double2* R_out) {
   ga.twP = pl->twPd;
   ga.twQ = pl->twQd;
   ga.circ = (pl->prm.flags & SLRX_FLAG_GIRAF) ? 1 : 0;
+  ga.bad = (int*)(pl->info + kInfoNonfinite);
   HIPCHK(launch_gram(ga, pl->stream));
   return SLRX_OK;
 }
@@ -283,6 +284,7 @@ slrx_status slrx::coil_pass(slrx_plan* pl) {
   ca.tw = pl->twPf;
   ca.d = pl->dco;
   ca.cscale = (float)(1.0 / (pq * pq));
+  ca.groups = coil_groups(pl->ncoils);
   HIPCHK(launch_coil_combine(ca, pl->stream));
   return SLRX_OK;
 }
@@ -331,6 +333,8 @@ slrx_status slrx::penalty_pass(slrx_plan* pl) {
     pa.nc = pl->ncoils;
     pa.rho = pl->rho;
     pa.d = pl->dco;
+    pa.dparts = coil_groups(pl->ncoils);
+    pa.dstride = (long)pl->vol();
   }
   HIPCHK(launch_pen(pa, pl->stream));
   return SLRX_OK;

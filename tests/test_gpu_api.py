@@ -1,7 +1,7 @@
 """C-ABI behaviour on the GPU beyond the numerics of one run: changing the
 filter support of a plan (smaller, then back to its capacity), batches that mix
-the library eigensolver with the own chain, batches on a caller's stream, and
-state errors."""
+the library eigensolver with the own chain, batches on a caller's stream,
+state errors and non-finite input."""
 import numpy as np
 import pytest
 import torch
@@ -108,3 +108,48 @@ def test_state_errors():
         pl.run()
         pl.sync()
         assert pl.stats()["n_irls"] == 1
+
+
+def test_non_finite_input_is_reported_and_the_plan_recovers():
+    """A NaN in the sampled k-space makes every Gram entry non-finite; the Gram
+    pass writes zeros in their place (the eigen-decomposition only sees finite
+    input) and the run reports SLRX_ENUMERIC.  With good data the same plan runs
+    again; in a batch the other plans are unaffected."""
+    say("non-finite input")
+    pb = problem(seed=311)
+    bad = pb.b.copy()
+    t, r, c = np.argwhere(pb.S)[0]
+    bad[t, r, c] = np.nan
+    with new_plan(pb) as ref_plan:
+        ref = run_images(ref_plan)
+    with new_plan(pb) as pl:
+        pl.set_kspace(bad)
+        pl.run()
+        with pytest.raises(slrx.SlrxError) as ei:
+            pl.sync()
+        assert ei.value.name == "SLRX_ENUMERIC"
+        pl.set_kspace(pb.b)
+        assert np.array_equal(run_images(pl), ref)
+    good, poisoned = new_plan(pb), new_plan(pb)
+    poisoned.set_kspace(bad)
+    try:
+        slrx.run_batch([good, poisoned], sync=False)
+        good.sync()
+        with pytest.raises(slrx.SlrxError) as ei:
+            poisoned.sync()
+        assert ei.value.name == "SLRX_ENUMERIC"
+        assert np.array_equal(good.images(), ref)
+    finally:
+        good.close()
+        poisoned.close()
+
+
+def test_zero_data_reconstructs_zero():
+    """All-zero data: R = 0 and eps = 0 make the weights infinite, and the CG stop
+    rule (NaN or non-positive <r,r>) keeps the iterate at zero."""
+    say("zero data")
+    pb = problem(seed=312)
+    with new_plan(pb) as pl:
+        pl.set_kspace(np.zeros_like(pb.b))
+        img = run_images(pl)
+    assert np.array_equal(img, np.zeros_like(img))
