@@ -103,21 +103,32 @@ def roofline(kind, avg_ms, T, P, Q, M, N1, N2, nc=0):
             "avg_launch_ms": round(avg_ms, 6)}
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 of the kernel sources with comments and blank lines removed, so that
+    a counter summary stays attached to the code it measured across comment edits."""
+    import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_1704_04511_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name)) as f:
+            text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        for line in text.splitlines():
+            code = re.sub(r"//.*", "", line).strip()
+            if code:
+                h.update(code.encode() + b"\n")
+    return h.hexdigest()
+
+
 def measured_traffic(kind: str):
     """HBM bytes per launch of a kernel class from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, or None when the kernel sources changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "c3_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    csrc = os.path.join(ROOT, "paper_1704_04511_amd", "csrc")
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != rec.get("source_sha256"):
+    if kernel_source_hash() != rec.get("source_sha256"):
         return None
     return rec.get("bytes_per_launch", {}).get(kind)
 

@@ -13,8 +13,11 @@
 //               frame of its columns in LDS;
 //   3. rows:    forward row DFT back to row-major, plus S o v and the partial
 //               dot product <v, A v> (or r = b - A x for the initial residual).
-// Plain unitary 2-D transforms (images for the Gram matrix, outputs) reuse
-// pass 1 and a column pass that writes row-major.
+// With coil maps (k_coil.hip) the column pass takes the image and the coil
+// combination from the coil passes instead of inverting the columns itself,
+// and pass 3 omits S o v.  With the GIRAF option G is circulant along the
+// frames.  Plain unitary 2-D transforms (images for the Gram matrix, outputs)
+// reuse pass 1 and a column pass that writes row-major.
 #include "common.h"
 #include "fft.h"
 #include "kernels.h"
