@@ -133,17 +133,18 @@ def measured_traffic(kind: str):
     return rec.get("bytes_per_launch", {}).get(kind)
 
 
-def cpu_baseline(pb, n_outer: int = 1) -> dict:
-    """FP64 oracle on a bounded sample: the first outer iteration(s) of the workload."""
+def cpu_baseline(pb, n_outer: int = 1):
+    """FP64 oracle on a bounded sample: the first outer iteration(s) of the workload.
+    Returns the baseline record and the oracle's images after those iterations."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, n_outer, pb.n_cg, p=pb.p, gamma=pb.gamma,
-                eps0_frac=pb.eps0_frac)
+    img = oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, n_outer, pb.n_cg, p=pb.p, gamma=pb.gamma,
+                      eps0_frac=pb.eps0_frac)
     dt = time.perf_counter() - t0
     return {"value": n_outer / dt, "unit": "IRLS iter/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_outer} of {pb.n_irls} outer iterations ({pb.n_cg} CG each) of the same "
-                      f"256x256x20 workload, NumPy/SciPy FP64, {dt:.1f} s wall"}
+                      f"256x256x20 workload, NumPy/SciPy FP64, {dt:.1f} s wall"}, img
 
 
 def bench_batch(args) -> int:
@@ -573,7 +574,14 @@ def main() -> int:
         "recon_nrmse_vs_truth": round(float(np.linalg.norm(img - pb.truth) / np.linalg.norm(pb.truth)), 5),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pb, args.cpu_outer)
+        out["cpu_baseline"], ora = cpu_baseline(pb, args.cpu_outer)
+        # the same number of outer iterations on the GPU, compared with the oracle's images
+        plan.set_params(slrx.make_params(lam=pb.lam, n_irls=args.cpu_outer, n_cg=pb.n_cg, p=pb.p,
+                                         gamma=pb.gamma, eps0_frac=pb.eps0_frac))
+        plan.run()
+        plan.sync()
+        out["nrmse_vs_oracle"] = {"value": float(f"{np.linalg.norm(plan.images() - ora) / np.linalg.norm(ora):.3e}"),
+                                  "outer_iterations": args.cpu_outer, "bar": 1e-4}
     plan.close()
     print(json.dumps(out))
     return 0
