@@ -379,13 +379,15 @@ __global__ __launch_bounds__(256) void k_mask_rows(MaskArgs a, int W) {
   const int r2 = (int)(o % Q);
   const long wj = o / Q;  // w * L1 + j1
   double sx = 0.0, sy = 0.0;
+  // twiddle index (Delta2 r2) mod Q, stepped by r2 as Delta2 grows by one
+  int t = (int)(((long)((Q - (a.N2 - 1) % Q) % Q) * r2) % Q);
   for (int j2 = 0; j2 < L2; ++j2) {
-    const int d2 = j2 - (a.N2 - 1);
-    const int t = (int)((((long)d2 % Q + Q) % Q) * r2 % Q);
     const double2 c = a.wsum[wj * L2 + j2];
     const double2 tw = a.twQ[t];  // conj gives the + sign
     sx += c.x * tw.x + c.y * tw.y;
     sy += c.y * tw.x - c.x * tw.y;
+    t += r2;
+    if (t >= Q) t -= Q;
   }
   a.s1[o] = make_double2(sx, sy);
 }
@@ -400,13 +402,15 @@ __global__ __launch_bounds__(256) void k_mask_cols(MaskArgs a, int W) {
   const int r2 = (int)((o / P) % Q);
   const int w = (int)(o / ((long)P * Q));
   double sx = 0.0, sy = 0.0;
+  // twiddle index (Delta1 r1) mod P, stepped by r1 as Delta1 grows by one
+  int t = (int)(((long)((P - (a.N1 - 1) % P) % P) * r1) % P);
   for (int j1 = 0; j1 < L1; ++j1) {
-    const int d1 = j1 - (a.N1 - 1);
-    const int t = (int)((((long)d1 % P + P) % P) * r1 % P);
     const double2 c = a.s1[((long)w * L1 + j1) * Q + r2];
     const double2 tw = a.twP[t];
     sx += c.x * tw.x + c.y * tw.y;
     sy += c.y * tw.x - c.x * tw.y;
+    t += r1;
+    if (t >= P) t -= P;
   }
   a.Et[o] = make_float2((float)sx, (float)sy);
 }
