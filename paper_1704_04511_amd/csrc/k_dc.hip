@@ -99,154 +99,289 @@ __global__ void k_dc_init(DcArgs a0) {
   a.Q[(long)i * a.n + i] = 1.0;
 }
 
-// Sort, z, deflation of one merge (one workgroup per node).
+// Sort, z, deflation of one merge (one workgroup per node, its size a multiple
+// of 64 that covers the largest node of the level, at most kDefNT).
 constexpr int kDefNT = 1024;
+constexpr int kDefRank = 256;  // largest node sorted by rank counting
+inline size_t dc_deflate_lds(int m) { return (size_t)m * (4 * sizeof(double) + 4 * sizeof(int)); }
+
+// Inclusive block scan of chunk[0, nt) (sum, or max when MAX).
+template <bool MAX>
+SLRX_DEV void block_scan(int* chunk, int tid, int nt) {
+  for (int off = 1; off < nt; off <<= 1) {
+    const int v = tid >= off ? chunk[tid - off] : (MAX ? -1 : 0);
+    __syncthreads();
+    chunk[tid] = MAX ? max(chunk[tid], v) : chunk[tid] + v;
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kDefNT) void k_dc_deflate(DcArgs a0) {
   const DcArgs a = dc_at(a0, blockIdx.y);
   extern __shared__ double lds[];
   const int4 nd = a.nodes[a.node0 + blockIdx.x];
   const int s = nd.x, m = nd.y, n1 = nd.z, n = a.n;
   const int node = a.node0 + blockIdx.x;
-  double* dv = lds;
-  double* zv = dv + m;
-  double* ds = zv + m;
-  double* zs = ds + m;
+  const int nt = blockDim.x;
+  double* dv = lds;     // node entries; after the sort, the kept entries' poles
+  double* zv = dv + m;  // node couplings; after the sort, the kept entries' couplings
+  double* ds = zv + m;  // sorted poles
+  double* zs = ds + m;  // sorted couplings
   int* perm = (int*)(zs + m);  // sorted position -> node column
   int* order = perm + m;       // final column order -> sorted position
-  int* keep = order + m;       // 1 if not deflated by a negligible z entry
+  int* flag = order + m;       // per sorted entry, see below
+  int* ki = flag + m;          // kept entry i -> sorted position
   __shared__ int chunk[kDefNT];
   __shared__ double red[2][kDefNT / 64];
-  __shared__ int kout;
-  const int tid = threadIdx.x;
+  __shared__ int kout, nkept, nrout;
+  __shared__ unsigned long long cbits[(kDcMaxN + 63) / 64];  // candidate pairs, by kept index
+  const int tid = threadIdx.x, lane = tid & 63;
   const double beta = a.E[s + n1 - 1];
   const double rho = 2.0 * fabs(beta);
   const double sgn = beta >= 0.0 ? 1.0 : -1.0;
   const double r2 = 0.70710678118654752440;
-  for (int i = tid; i < m; i += kDefNT) {
+  for (int i = tid; i < m; i += nt) {
     dv[i] = a.D[s + i];
     zv[i] = i < n1 ? a.Q[(long)(s + n1 - 1) * n + s + i] * r2 : sgn * a.Q[(long)(s + n1) * n + s + i] * r2;
   }
   __syncthreads();
-  // rank sort (stable): position of entry i among all entries
+  // Sort by (pole, node column), the stable order. Up to kDefRank entries by
+  // rank (each thread counts the entries before its own); above, a bitonic
+  // network over the next power of two, keys staged in ds/zs and columns in
+  // order/flag/ki (free until the sort is done; P2 doubles < 2m, P2 ints < 3m).
   double dmax = 0.0, zmax = 0.0;
-  for (int i = tid; i < m; i += kDefNT) {
-    const double di = dv[i];
-    int r = 0;
-    int j = 0;
-    for (; j + 8 <= m; j += 8) {  // eight independent LDS reads in flight
-      double dj[8];
+  if (m <= kDefRank) {
+    for (int i = tid; i < m; i += nt) {
+      const double di = dv[i];
+      int r = 0;
+      int j = 0;
+      for (; j + 8 <= m; j += 8) {  // eight independent LDS reads in flight
+        double dj[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) dj[u] = dv[j + u];
+        for (int u = 0; u < 8; ++u) dj[u] = dv[j + u];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) r += (dj[u] < di) || (dj[u] == di && j + u < i);
+        for (int u = 0; u < 8; ++u) r += (dj[u] < di) || (dj[u] == di && j + u < i);
+      }
+      for (; j < m; ++j) r += (dv[j] < di) || (dv[j] == di && j < i);
+      perm[r] = i;
+      dmax = fmax(dmax, fabs(di));
+      zmax = fmax(zmax, fabs(zv[i]));
     }
-    for (; j < m; ++j) r += (dv[j] < di) || (dv[j] == di && j < i);
-    perm[r] = i;
-    dmax = fmax(dmax, fabs(di));
-    zmax = fmax(zmax, fabs(zv[i]));
+  } else {
+    int P2 = 1;
+    while (P2 < m) P2 <<= 1;
+    double* sk = ds;
+    int* si = order;
+    for (int i = tid; i < P2; i += nt) {
+      sk[i] = i < m ? dv[i] : __builtin_huge_val();
+      si[i] = i;
+      if (i < m) {
+        dmax = fmax(dmax, fabs(dv[i]));
+        zmax = fmax(zmax, fabs(zv[i]));
+      }
+    }
+    __syncthreads();
+    for (int kb = 2; kb <= P2; kb <<= 1) {
+      for (int j = kb >> 1; j > 0; j >>= 1) {
+        for (int q = tid; q < P2 / 2; q += nt) {
+          const int lo = 2 * j * (q / j) + (q % j), hi = lo + j;
+          const double a = sk[lo], b = sk[hi];
+          const int ia = si[lo], ib = si[hi];
+          const bool gt = a > b || (a == b && ia > ib);
+          if (gt == ((lo & kb) == 0)) {
+            sk[lo] = b;
+            sk[hi] = a;
+            si[lo] = ib;
+            si[hi] = ia;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int r = tid; r < m; r += nt) perm[r] = si[r];
   }
   dmax = wave_max(dmax);
   zmax = wave_max(zmax);
-  if ((tid & 63) == 0) {
+  if (lane == 0) {
     red[0][tid >> 6] = dmax;
     red[1][tid >> 6] = zmax;
   }
   __syncthreads();
-  for (int t = tid; t < m; t += kDefNT) {
+  for (int t = tid; t < m; t += nt) {
     ds[t] = dv[perm[t]];
     zs[t] = zv[perm[t]];
   }
   double mx = 0.0;
-  for (int w = 0; w < kDefNT / 64; ++w) mx = fmax(mx, fmax(red[0][w], red[1][w]));
+  for (int w = 0; w < nt / 64; ++w) mx = fmax(mx, fmax(red[0][w], red[1][w]));
   const double tol = 8.0 * __DBL_EPSILON__ * mx;
   __syncthreads();
+  // Deflation with LAPACK's criteria, in sorted order. An entry whose coupling
+  // is negligible (rho |z| <= tol) is an eigenpair as it stands. Of two
+  // consecutive kept entries p < t, with c = z_t / r, s = -z_p / r, r^2 = z_p^2
+  // + z_t^2, the rotation that moves z_p into z_t deflates p when
+  // |(d_t - d_p) c s| <= tol; t then carries the coupling r and the pole
+  // d_p s^2 + d_t c^2, and the test of the next pair uses them. Along a chain of
+  // rotations these are running sums: r^2 = Z2 = sum z^2 and the pole is
+  // N / Z2 with N = sum d z^2, and the test reads
+  //   (d_t Z2 - N)^2 z_t^2 <= tol^2 Z2 (Z2 + z_t^2)^2,
+  // products only. One thread walks the kept entries with that test (poles
+  // scaled by 1/mx, so that tol becomes 8 eps); c, s and the deflated poles of
+  // the rotations it records follow in parallel.
+  //   flag bit 0: kept; bit 1: rotated into (bits 3.. hold the entry rotated
+  //   away into it); bit 2: rotated away.
+  const int per = (m + nt - 1) / nt;
+  const int u0 = tid * per, u1 = min(m, u0 + per);
+  int cnt = 0;
+  for (int u = u0; u < u1; ++u) {
+    const int f = rho * fabs(zs[u]) > tol;
+    flag[u] = f;
+    cnt += f;
+  }
+  chunk[tid] = cnt;
+  __syncthreads();
+  block_scan<false>(chunk, tid, nt);
+  {
+    int i = chunk[tid] - cnt;
+    for (int u = u0; u < u1; ++u) {
+      if (!flag[u]) continue;
+      dv[i] = ds[u];
+      zv[i] = zs[u];
+      ki[i] = u;
+      ++i;
+    }
+  }
+  if (tid == 0) nkept = chunk[nt - 1];
+  __syncthreads();
+  const int nk = nkept;
+  double* rc = a.ws_d + 2 * n + s;   // rotation c; Z2 before it while walking
+  double* rsn = a.ws_d + 3 * n + s;  // rotation s; N / mx before it while walking
+  double* rec = a.ws_d + 6 * n + s;  // kept index of the entry rotated away, ~index at a chain start
   int* rp = a.ws_i + 2 * n + s;
   int* rq = a.ws_i + 3 * n + s;
-  double* rc = a.ws_d + 2 * n + s;
-  double* rsn = a.ws_d + 3 * n + s;
-  // Fast path: when no two consecutive kept entries are close enough to be
-  // rotated (the usual case), deflation is a parallel compaction.
-  for (int t = tid; t < m; t += kDefNT) keep[t] = rho * fabs(zs[t]) > tol;
-  __syncthreads();
-  int close = 0;
-  for (int t = tid; t < m; t += kDefNT) {
-    if (!keep[t]) continue;
-    int p = t - 1;
-    while (p >= 0 && !keep[p]) --p;
-    if (p < 0) continue;
-    const double tau = hypot(zs[t], zs[p]);
-    if (fabs((ds[t] - ds[p]) * (zs[t] / tau) * (zs[p] / tau)) <= tol) close = 1;
+  const double inv = 1.0 / mx;
+  const double tol2 = 64.0 * __DBL_EPSILON__ * __DBL_EPSILON__;
+  // Pairs (i-1, i) whose entry values pass the test with twice its tolerance:
+  // a pair outside these, reached with the values of i-1 unchanged, does not
+  // rotate, and the walk skips it.
+  for (int i0 = tid & ~63; i0 < nk; i0 += nt) {
+    const int i = i0 + lane;
+    bool cand = false;
+    if (i >= 1 && i < nk) {
+      const double zp = zv[i - 1], zt = zv[i];
+      const double Z2 = zp * zp, zt2 = zt * zt, r2 = Z2 + zt2;
+      const double x = (dv[i] * inv) * Z2 - (dv[i - 1] * inv) * Z2;
+      cand = x * x * zt2 <= 2.0 * tol2 * Z2 * r2 * r2 || !(2.0 * tol2 * Z2 * r2 * r2 >= 1e-290);
+    }
+    const unsigned long long b = __ballot(cand);
+    if (lane == 0) cbits[i0 >> 6] = b;
   }
-  close = __syncthreads_or(close);
-  if (!close) {
-    // positions: kept entries first in sorted order, then the others
-    const int per = (m + kDefNT - 1) / kDefNT;
-    const int t0 = tid * per, t1 = min(m, t0 + per);
-    int cnt = 0;
-    for (int t = t0; t < t1; ++t) cnt += keep[t];
-    chunk[tid] = cnt;
-    __syncthreads();
-    for (int off = 1; off < kDefNT; off <<= 1) {  // inclusive scan of the chunk counts
-      const int v = tid >= off ? chunk[tid - off] : 0;
-      __syncthreads();
-      chunk[tid] += v;
-      __syncthreads();
-    }
-    const int kk = chunk[kDefNT - 1];
-    int before = chunk[tid] - cnt;
-    for (int t = t0; t < t1; ++t) {
-      if (keep[t]) order[before++] = t;
-      else order[kk + (t - before)] = t;  // t - before = deflated entries before t
-    }
-    if (tid == 0) {
-      a.ws_node[4 * node] = kk;
-      a.ws_node[4 * node + 1] = 0;
-      kout = kk;
-    }
-  } else if (tid == 0) {
-    int k = 0, kd = 0, nrot = 0, pj = -1;
-    for (int t = 0; t < m; ++t) {
-      if (rho * fabs(zs[t]) <= tol) {  // negligible coupling: (d_t, column t) is an eigenpair
-        order[m - 1 - kd++] = t;
-        continue;
+  __syncthreads();
+  if (tid == 0) {
+    const int nw = (nk + 63) >> 6;
+    auto next = [&](int f) {  // smallest candidate i >= f, or -1
+      for (int w = f >> 6; w < nw; ++w) {
+        unsigned long long b = cbits[w];
+        if (w == (f >> 6)) b &= ~0ull << (f & 63);
+        if (b) return (w << 6) + __builtin_ctzll(b);
       }
-      if (pj < 0) {
-        pj = t;
-        continue;
-      }
-      double sv = zs[pj], cv = zs[t];
-      const double tau = hypot(cv, sv);
-      const double tt = ds[t] - ds[pj];
-      cv /= tau;
-      sv = -sv / tau;
-      if (fabs(tt * cv * sv) <= tol) {  // close poles: rotate z_pj into z_t, deflate pj
-        zs[t] = tau;
-        zs[pj] = 0.0;
-        rp[nrot] = pj;
-        rq[nrot] = t;
-        rc[nrot] = cv;
-        rsn[nrot] = sv;
+      return -1;
+    };
+    int nrot = 0;
+    int i = nk >= 2 ? next(1) : -1;
+    while (i >= 0) {
+      // a chain from the pair (i-1, i): Z2, N of the entry carrying the coupling
+      const double zp = zv[i - 1];
+      double Z2 = zp * zp, N = (dv[i - 1] * inv) * Z2;
+      bool start = true;
+      double zt = zv[i], dt = dv[i] * inv;
+      for (;;) {
+        const int in = min(i + 1, nk - 1);  // next entry's values in flight
+        const double zn = zv[in], dn = dv[in];
+        const double zt2 = zt * zt;
+        const double r2 = Z2 + zt2;
+        const double x = dt * Z2 - N;
+        const double rhs = tol2 * Z2 * r2 * r2;
+        bool rot;
+        if (rhs >= 1e-290) {
+          rot = x * x * zt2 <= rhs;
+        } else {  // products near underflow: the test in its direct form
+          const double r = sqrt(r2);
+          rot = fabs((dt - N / Z2) * (zt / r) * (sqrt(Z2) / r)) <= 8.0 * __DBL_EPSILON__;
+        }
+        if (!rot) break;
+        rec[nrot] = start ? (double)~(i - 1) : (double)(i - 1);
+        rc[nrot] = Z2;
+        rsn[nrot] = N;
         ++nrot;
-        const double t2 = ds[pj] * cv * cv + ds[t] * sv * sv;
-        ds[t] = ds[pj] * sv * sv + ds[t] * cv * cv;
-        ds[pj] = t2;
-        order[m - 1 - kd++] = pj;
-        pj = t;
-      } else {
-        order[k++] = pj;
-        pj = t;
+        Z2 = r2;
+        N = N + dt * zt2;
+        start = false;
+        if (++i >= nk) break;
+        zt = zn;
+        dt = dn * inv;
       }
+      i = i < nk ? next(i + 1) : -1;
     }
-    if (pj >= 0) order[k++] = pj;
-    a.ws_node[4 * node] = k;
+    nrout = nrot;
+  }
+  __syncthreads();
+  const int nrot = nrout;
+  for (int j = tid; j < nrot; j += nt) {
+    const int e = (int)rec[j];
+    const bool start = e < 0;
+    const int ip = start ? ~e : e, it = ip + 1;
+    const bool end = j == nrot - 1 || (int)rec[j + 1] < 0;  // the next rotation starts a new chain
+    const int p = ki[ip], t = ki[it];
+    const double zt = zv[it], dt = dv[it];
+    const double Z2 = rc[j];
+    const double zp = start ? zv[ip] : sqrt(Z2);
+    const double dp = start ? dv[ip] : (rsn[j] / Z2) * mx;
+    const double r = hypot(zt, zp);
+    const double c = zt / r, sv = -zp / r;
+    rp[j] = p;
+    rq[j] = t;
+    rc[j] = c;
+    rsn[j] = sv;
+    ds[p] = dp * c * c + dt * sv * sv;
+    zs[p] = 0.0;
+    if (end) {
+      ds[t] = dp * sv * sv + dt * c * c;
+      zs[t] = r;
+    }
+    flag[t] = 3 | (end ? 0 : 4) | (p << 3);
+    if (start) flag[p] = 5;
+  }
+  __syncthreads();
+  // Final order: the kept entries that were not rotated away, in sorted order,
+  // then the deflated ones from the back in the order of deflation (an entry
+  // with a negligible coupling at its own position, a rotated-away entry at the
+  // position of the entry it was rotated into). Both counts by one block scan,
+  // packed into one int (m < 65536).
+  cnt = 0;
+  for (int u = u0; u < u1; ++u) {
+    const int f = flag[u];
+    if (!(f & 1) || (f & 2)) cnt += 1;
+    if ((f & 1) && !(f & 4)) cnt += 0x10000;
+  }
+  chunk[tid] = cnt;
+  __syncthreads();
+  block_scan<false>(chunk, tid, nt);
+  int be = (chunk[tid] - cnt) & 0xffff, bk = (chunk[tid] - cnt) >> 16;
+  for (int u = u0; u < u1; ++u) {
+    const int f = flag[u];
+    if (!(f & 1) || (f & 2)) order[m - 1 - be++] = (f & 2) ? (f >> 3) : u;
+    if ((f & 1) && !(f & 4)) order[bk++] = u;
+  }
+  if (tid == 0) {
+    kout = chunk[nt - 1] >> 16;
+    a.ws_node[4 * node] = kout;
     a.ws_node[4 * node + 1] = nrot;
-    kout = k;
   }
   __syncthreads();
   const int k = kout;
   double* dl = a.ws_d + s;
   double* zl = a.ws_d + n + s;
-  for (int c = tid; c < m; c += kDefNT) {
+  for (int c = tid; c < m; c += nt) {
     const int t = order[c];
     a.ws_i[n + s + c] = t;
     a.ws_i[s + t] = perm[t];
@@ -309,11 +444,11 @@ __global__ __launch_bounds__(256) void k_dc_gather(DcArgs a0, int mmax) {
 struct SecTerms {
   double psi, dpsi, phi, dphi, fa;
 };
-SLRX_DEV SecTerms secular(const double* dl, const double* zl, int k, int j, double dor, double rho, double tau) {
+SLRX_DEV SecTerms secular(const double* dl, const double* z2, int k, int j, double dor, double rho, double tau) {
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x & 63; i < k; i += 64) {
     const double r = 1.0 / ((dl[i] - dor) - tau);
-    const double w = zl[i] * zl[i] * r;
+    const double w = z2[i] * r;
     if (i <= j) {
       v[0] += w;
       v[1] += w * r;
@@ -348,21 +483,30 @@ SLRX_DEV double bit_mid(double x0, double x1, double sign) {
 // always ends.  It stops when |f| is within the rounding of its terms.
 __global__ __launch_bounds__(256) void k_dc_secular(DcArgs a0) {
   const DcArgs a = dc_at(a0, blockIdx.z);
+  extern __shared__ double sec_lds[];
   const int node = a.node0 + blockIdx.y;
   const int4 nd = a.nodes[node];
   const int s = nd.x, n = a.n;
   const int k = a.ws_node[4 * node];
+  // the node's poles and squared couplings, read by every step of the four roots
+  double* dl = sec_lds;
+  double* z2 = sec_lds + k;
+  if (blockIdx.x * 4 >= k) return;
+  for (int i = threadIdx.x; i < k; i += 256) {
+    dl[i] = a.ws_d[s + i];
+    const double z = a.ws_d[n + s + i];
+    z2[i] = z * z;
+  }
+  __syncthreads();
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= k) return;
   const double rho = 2.0 * fabs(a.E[s + nd.z - 1]);
-  const double* dl = a.ws_d + s;
-  const double* zl = a.ws_d + n + s;
   const bool last = j == k - 1;
   int o;
   double sign, hiv;
   if (!last) {
     const double gap = dl[j + 1] - dl[j];
-    const SecTerms t = secular(dl, zl, k, j, dl[j], rho, 0.5 * gap);
+    const SecTerms t = secular(dl, z2, k, j, dl[j], rho, 0.5 * gap);
     if (1.0 + t.psi + t.phi >= 0.0) {
       o = j;
       sign = 1.0;
@@ -372,11 +516,11 @@ __global__ __launch_bounds__(256) void k_dc_secular(DcArgs a0) {
     }
     hiv = 0.5 * gap;
   } else {
-    double z2 = 0.0;
-    for (int i = threadIdx.x & 63; i < k; i += 64) z2 += zl[i] * zl[i];
+    double zz = 0.0;
+    for (int i = threadIdx.x & 63; i < k; i += 64) zz += z2[i];
     o = j;
     sign = 1.0;
-    hiv = rho * wave_sum(z2);
+    hiv = rho * wave_sum(zz);
   }
   const double dor = dl[o];
   const double pa = dl[j] - dor;                     // left pole
@@ -385,7 +529,7 @@ __global__ __launch_bounds__(256) void k_dc_secular(DcArgs a0) {
   double x = sign * hiv;  // the midpoint (the far end for the last root)
   double prev_step = 1e300;
   for (int it = 0; it < 200; ++it) {
-    const SecTerms t = secular(dl, zl, k, j, dor, rho, x);
+    const SecTerms t = secular(dl, z2, k, j, dor, rho, x);
     const double f = 1.0 + t.psi + t.phi;
     if (fabs(f) <= 4.0 * __DBL_EPSILON__ * (1.0 + t.fa)) break;
     if (f < 0.0) lo = x;
@@ -674,7 +818,7 @@ hipError_t launch_tdeig(const TdArgs& t, hipStream_t st) {
   if (n < 1 || n > kDcMaxN) return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = set_lds(k_dc_deflate, (size_t)kDcMaxN * (4 * sizeof(double) + 3 * sizeof(int)));
+    hipError_t e = set_lds(k_dc_deflate, dc_deflate_lds(kDcMaxN));
     if (e == hipSuccess) e = set_lds(k_dc_gather, (size_t)4 * kDcMaxN * sizeof(double));
     if (e == hipSuccess) e = set_lds(k_dc_sort, (size_t)4096 * (sizeof(double) + sizeof(int)));
     if (e != hipSuccess) return e;
@@ -707,9 +851,10 @@ hipError_t launch_tdeig(const TdArgs& t, hipStream_t st) {
     for (int q = first; q < first + count; ++q) mmax = std::max(mmax, t.node_sizes[q]);
     a.node0 = first;
     a.count = count;
-    k_dc_deflate<<<dim3(count, nb), kDefNT, (size_t)mmax * (4 * sizeof(double) + 3 * sizeof(int)), st>>>(a);
+    const int dnt = std::min(kDefNT, (mmax + 63) / 64 * 64);
+    k_dc_deflate<<<dim3(count, nb), dnt, dc_deflate_lds(mmax), st>>>(a);
     k_dc_gather<<<dim3((mmax + 3) / 4, count, nb), 256, (size_t)4 * mmax * sizeof(double), st>>>(a, mmax);
-    k_dc_secular<<<dim3((mmax + 3) / 4, count, nb), 256, 0, st>>>(a);
+    k_dc_secular<<<dim3((mmax + 3) / 4, count, nb), 256, (size_t)2 * mmax * sizeof(double), st>>>(a);
     k_dc_zhat<<<dim3((mmax + 3) / 4, count, nb), 256, 0, st>>>(a);
     k_dc_vectors<<<dim3((mmax + 3) / 4, count, nb), 256, 0, st>>>(a);
     k_dc_gemm<<<dim3((mmax + 63) / 64, (mmax + 63) / 64, count * nb), 256, 0, st>>>(a);
