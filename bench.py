@@ -50,14 +50,45 @@ def algorithmic_bytes(kind: str, T: int, P: int, Q: int, M: int, N1: int, N2: in
         return 6 * V * c
     if kind == "gram":     # images (read x, write/read t, write img), read img, write R
         return 5 * V * c + s * s * 16
-    if kind == "masks":    # read H (2 s^2 doubles); write E
-        return 2 * s * s * 8 + W * P * Q * c
+    if kind == "masks":    # spectral path: read the group partial sums of the pair
+        g = spectral_groups(N1, N2, M)  # spectra; else read H (2 s^2 doubles); write E
+        lag = g * W * (2 * N1 - 1) * (2 * N2 - 1) * 16 if g else 2 * s * s * 8
+        return lag + W * P * Q * c
     if kind == "filter":   # read U (s^2 complex128); write H (2 s^2 doubles)
         return s * s * 16 + 2 * s * s * 8
     return 0.0
 
 
+def spectral_groups(N1: int, N2: int, M: int) -> int:
+    """Eigenvector groups of the spectral lag sums (0: the shape takes the H path);
+    the same rule as the library's: M <= 5, 2 N1 - 1 <= 32, s <= 2048, 64 KB of LDS
+    for the accumulation and the inverse transform, partial and slice sums within
+    s^2 complex128."""
+    s, W = N1 * N2 * M, M * (M + 1) // 2
+    L1, L2 = 2 * N1 - 1, 2 * N2 - 1
+    if M > 5 or L1 > 32 or s > 2048:
+        return 0
+    if (s + M * N1 * 8 + L1 + L2) * 16 > 65536 or (2 * L1 * L2 + L1 + L2) * 16 > 65536:
+        return 0
+    gmax = (s * s) // (W * L1 * L2) - 8
+    if gmax < 1:
+        return 0
+    g = min(gmax, 128, s)
+    kper = -(-s // g)
+    return -(-s // kper)
+
+
+def spectral_flop(N1: int, N2: int, M: int) -> float:
+    """Flops of the spectral lag sums (complex MAC = 8 flop): per eigenvector the
+    N2-point DFTs of its M N1 rows at L2 frequencies, the N1-point DFTs of the
+    M L1 L2 outputs, and W pair products at each of the L1 L2 frequencies."""
+    s, W = N1 * N2 * M, M * (M + 1) // 2
+    L1, L2 = 2 * N1 - 1, 2 * N2 - 1
+    return 8.0 * s * (M * N1 * L2 * N2 + M * L1 * L2 * N1 + W * L1 * L2)
+
+
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix
+FP64_VALU_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 
 
 def tri_bytes(n: int) -> float:
@@ -81,10 +112,17 @@ def backtr_flop(n: int, nb: int = 64) -> float:
 
 def roofline(kind, avg_ms, T, P, Q, M, N1, N2, nc=0):
     """Roofline entry of one kernel class.  The filter product and the
-    back-transformation are FP64 MFMA contractions; the tridiagonalisation is
+    back-transformation are FP64 MFMA contractions (the spectral lag sums that
+    replace the filter product where the shape allows are FP64 vector work); the tridiagonalisation is
     reported per launch (one launch per column) against HBM; every other class is
     bound by HBM."""
     s = N1 * N2 * M
+    if kind == "filter" and spectral_groups(N1, N2, M):  # FP64 vector arithmetic
+        flop = spectral_flop(N1, N2, M)
+        ach = flop / (avg_ms * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": kind, "achieved": round(ach, 2), "peak": FP64_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "flop_per_launch": flop, "avg_launch_ms": round(avg_ms, 5)}
     if kind in ("filter", "backtr"):
         flop = 8.0 * s ** 3 if kind == "filter" else backtr_flop(s)
         ach = flop / (avg_ms * 1e-3) / 1e12

@@ -742,7 +742,7 @@ extern "C" slrx_status slrx_step_weights(slrx_plan* pl, double eps, double* lam_
   STCHK(step_eigh(pl, -1));
   HIPCHK(hipMemcpyAsync(pl->scal, &eps, sizeof(double), hipMemcpyHostToDevice, pl->stream));
   HIPCHK(hipStreamSynchronize(pl->stream));
-  STCHK(step_weights(pl, -1, false, 1.0));
+  STCHK(step_weights(pl, -1, false, 1.0, nullptr, nullptr, H_out != nullptr));
   const slrx_dims& d = pl->d;
   const size_t s = (size_t)d.N1 * d.N2 * d.M;
   const size_t W = (size_t)d.M * (d.M + 1) / 2;

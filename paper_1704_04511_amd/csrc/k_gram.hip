@@ -13,6 +13,8 @@
 // "eq:grad_ls"): E_r[m,m'] = sum_i alpha_i conj(mu_m^(i)(r)) mu_m'^(i)(r)
 //   = sum_Delta w_{m',m}[Delta] e^{+2 pi i Delta.r},
 //   w_{m',m}[Delta] = sum_{a'-a = Delta} H[(m',a'),(m,a)].
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -205,10 +207,14 @@ __global__ __launch_bounds__(256) void k_weights(WeightArgs a) {
   a.VT[(long)(s + k) * s + i] = u.y * sa;
 }
 
-hipError_t launch_weights(const WeightArgs& a, hipStream_t s) {
+hipError_t launch_eps(const WeightArgs& a, hipStream_t s) {
   k_eps<<<1, 64, 0, s>>>(a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_weights(const WeightArgs& a, hipStream_t s, bool eps) {
+  hipError_t e;
+  if (eps && (e = launch_eps(a, s)) != hipSuccess) return e;
   const long n = (long)a.s * a.s;
   k_weights<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a);
   return hipGetLastError();
@@ -335,6 +341,262 @@ hipError_t launch_filter_product(int s, const double* VT, double* Hre, double* H
   return hipGetLastError();
 }
 
+// ----------------------------------------------- masks from filter spectra
+// The diagonal sums of H = U diag(alpha) U^H are the weighted correlations of
+// the filters: with u_k(m, a) the tap-m, offset-a entry of eigenvector k,
+//   wsum_{m<=m'}[Delta] = sum_k alpha_k sum_{a' - a = Delta} u_k(m', a') conj(u_k(m, a)).
+// On the L1 x L2 = (2N1 - 1) x (2N2 - 1) grid every lag Delta is distinct, so
+// the correlation is the inverse DFT of C_w(f) = sum_k alpha_k X_{k,m'}(f)
+// conj(X_{k,m}(f)), X_{k,m} the DFT of u_k(m, .) over its N1 x N2 offsets:
+// about s (6 M N^3 + 2 M^2 N^2) flop against the s^3 of forming H.
+// k_spec_accum: workgroup (group g of eigenvectors, block of up to 8 columns
+// f2); per eigenvector the N2-point DFTs of its rows for those columns (stage
+// 1, in LDS), then one thread per frequency (f1, f2) finishes its M spectra
+// and accumulates the W pair products.  Partial sums per group go to
+// part[g][w][f], added in a fixed order by k_spec_reduce; k_spec_inverse
+// transforms back to the lags.
+constexpr int kSpecF2 = 8;     // columns f2 per workgroup
+constexpr int kSpecPf = kSpecMaxS / 256;  // prefetched eigenvector entries per thread
+constexpr int kSpecMaxL1 = 32; // 256 threads = 32 rows f1 x 8 columns f2
+
+template <int M>
+__global__ __launch_bounds__(256) void k_spec_accum(SpecArgs a) {
+  constexpr int W = M * (M + 1) / 2;
+  extern __shared__ double2 spl[];
+  const int N1 = a.N1, N2 = a.N2, s = a.s, NN = N1 * N2;
+  const int L1 = 2 * N1 - 1, L2 = 2 * N2 - 1, F = L1 * L2;
+  const int c0 = blockIdx.y * kSpecF2, nf2 = min(kSpecF2, L2 - c0);
+  double2* v = spl;                    // eigenvector k, s entries
+  double2* Y = v + s;                  // [M N1][nf2]
+  double2* t1 = Y + M * N1 * kSpecF2;  // e^{-2 pi i j / L1}
+  double2* t2 = t1 + L1;               // e^{-2 pi i j / L2}
+  const int tid = threadIdx.x;
+  for (int j = tid; j < L1; j += 256) {
+    double sn, cs;
+    sincospi(-2.0 * j / L1, &sn, &cs);
+    t1[j] = make_double2(cs, sn);
+  }
+  for (int j = tid; j < L2; j += 256) {
+    double sn, cs;
+    sincospi(-2.0 * j / L2, &sn, &cs);
+    t2[j] = make_double2(cs, sn);
+  }
+  const int f1 = tid / kSpecF2, fl = tid % kSpecF2;
+  const bool act = f1 < L1 && fl < nf2;
+  double2 acc[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) acc[w] = make_double2(0.0, 0.0);
+  const int k0 = blockIdx.x * a.kper, k1 = min(s, k0 + a.kper);
+  const double e = *a.eps, ex = a.p * 0.5 - 1.0;
+  // eigenvector k + 1 is loaded into registers while k is transformed
+  double2 nxt[kSpecPf];
+#pragma unroll
+  for (int r = 0; r < kSpecPf; ++r) {
+    const int i = tid + 256 * r;
+    nxt[r] = (k0 < k1 && i < s) ? a.U[(long)k0 * s + i] : make_double2(0.0, 0.0);
+  }
+  for (int k = k0; k < k1; ++k) {
+    __syncthreads();  // the previous eigenvector's v and Y are no longer read
+#pragma unroll
+    for (int r = 0; r < kSpecPf; ++r) {
+      const int i = tid + 256 * r;
+      if (i < s) v[i] = nxt[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSpecPf; ++r) {
+      const int i = tid + 256 * r;
+      if (k + 1 < k1 && i < s) nxt[r] = a.U[(long)(k + 1) * s + i];
+    }
+    // stage 1: Y[m N1 + a1][c] = sum_{a2} v(m, a1, a2) e^{-2 pi i a2 (c0 + c) / L2},
+    // a thread per (a1, c) and all M taps (one twiddle per M products)
+    for (int o = tid; o < N1 * nf2; o += 256) {
+      const int c = o % nf2, a1 = o / nf2;
+      const int g2 = c0 + c;
+      double sx[M], sy[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) sx[m] = sy[m] = 0.0;
+      int t = 0;
+      for (int a2 = 0; a2 < N2; ++a2) {
+        const double2 w = t2[t];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const double2 x = v[(m * N1 + a1) * N2 + a2];
+          sx[m] += x.x * w.x - x.y * w.y;
+          sy[m] += x.x * w.y + x.y * w.x;
+        }
+        t += g2;
+        if (t >= L2) t -= L2;
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) Y[(m * N1 + a1) * kSpecF2 + c] = make_double2(sx[m], sy[m]);
+    }
+    __syncthreads();
+    if (act) {
+      const double lk = a.lamv[k];
+      const double al = pow((lk > 0.0 ? lk : 0.0) + e, ex);
+      double2 X[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) X[m] = make_double2(0.0, 0.0);
+      int t = 0;
+      for (int a1 = 0; a1 < N1; ++a1) {  // stage 2 along a1
+        const double2 w = t1[t];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const double2 y = Y[(m * N1 + a1) * kSpecF2 + fl];
+          X[m].x += y.x * w.x - y.y * w.y;
+          X[m].y += y.x * w.y + y.y * w.x;
+        }
+        t += f1;
+        if (t >= L1) t -= L1;
+      }
+      int w = 0;
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int mp = m; mp < M; ++mp, ++w) {  // alpha X_{m'} conj(X_m)
+          const double re = X[mp].x * X[m].x + X[mp].y * X[m].y;
+          const double im = X[mp].y * X[m].x - X[mp].x * X[m].y;
+          acc[w].x += al * re;
+          acc[w].y += al * im;
+        }
+    }
+  }
+  (void)NN;
+  if (act) {
+    const int f = f1 * L2 + c0 + fl;
+#pragma unroll
+    for (int w = 0; w < W; ++w) a.part[((long)blockIdx.x * W + w) * F + f] = acc[w];
+  }
+}
+
+// Slice q of the groups: C[q][w][f] = sum over groups g = q, q + kSpecSlices, ..
+// of part[g][w][f], in group order (the slices are added in order by the
+// inverse transform).
+__global__ __launch_bounds__(256) void k_spec_reduce(SpecArgs a, int W) {
+  const int F = (2 * a.N1 - 1) * (2 * a.N2 - 1);
+  const long WF = (long)W * F;
+  const long o = (long)blockIdx.x * 256 + threadIdx.x;
+  if (o >= kSpecSlices * WF) return;
+  const int q = (int)(o / WF);
+  const long wf = o % WF;
+  double sx = 0.0, sy = 0.0;
+  for (int g = q; g < a.ngroups; g += kSpecSlices) {
+    const double2 v = a.part[(long)g * WF + wf];
+    sx += v.x;
+    sy += v.y;
+  }
+  a.C[o] = make_double2(sx, sy);
+}
+
+// wsum[w][j1][j2] = (1 / F) sum_f C[w][f] e^{+2 pi i (Delta1 f1 / L1 + Delta2 f2 / L2)},
+// Delta = j - (N - 1): one workgroup per pair, the two 1-D transforms in turn.
+__global__ __launch_bounds__(1024) void k_spec_inverse(SpecArgs a, double2* wsum, int W) {
+  extern __shared__ double2 spl[];
+  const int N1 = a.N1, N2 = a.N2, L1 = 2 * N1 - 1, L2 = 2 * N2 - 1, F = L1 * L2;
+  const int w = blockIdx.x, tid = threadIdx.x;
+  double2* Cs = spl;       // C[w][f1][f2]
+  double2* Ts = Cs + F;    // [f1][j2]
+  double2* t1 = Ts + F;    // e^{+2 pi i j / L1}
+  double2* t2 = t1 + L1;   // e^{+2 pi i j / L2}
+  const long WF = (long)W * F;
+  for (int f = tid; f < F; f += 1024) {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSpecSlices; ++q) {
+      const double2 v = a.C[q * WF + (long)w * F + f];
+      sx += v.x;
+      sy += v.y;
+    }
+    Cs[f] = make_double2(sx, sy);
+  }
+  for (int j = tid; j < L1; j += 1024) {
+    double sn, cs;
+    sincospi(2.0 * j / L1, &sn, &cs);
+    t1[j] = make_double2(cs, sn);
+  }
+  for (int j = tid; j < L2; j += 1024) {
+    double sn, cs;
+    sincospi(2.0 * j / L2, &sn, &cs);
+    t2[j] = make_double2(cs, sn);
+  }
+  __syncthreads();
+  for (int o = tid; o < F; o += 1024) {  // along f2
+    const int f1 = o / L2, j2 = o % L2;
+    const int d2 = (j2 - (N2 - 1) + L2) % L2;
+    const double2* cr = Cs + f1 * L2;
+    double sx = 0.0, sy = 0.0;
+    int u = 0;
+    for (int f2 = 0; f2 < L2; ++f2) {
+      const double2 c = cr[f2], e = t2[u];
+      sx += c.x * e.x - c.y * e.y;
+      sy += c.x * e.y + c.y * e.x;
+      u += d2;
+      if (u >= L2) u -= L2;
+    }
+    Ts[o] = make_double2(sx, sy);
+  }
+  __syncthreads();
+  const double sc = 1.0 / F;
+  for (int o = tid; o < F; o += 1024) {  // along f1
+    const int j1 = o / L2, j2 = o % L2;
+    const int d1 = (j1 - (N1 - 1) + L1) % L1;
+    double sx = 0.0, sy = 0.0;
+    int u = 0;
+    for (int f1 = 0; f1 < L1; ++f1) {
+      const double2 c = Ts[f1 * L2 + j2], e = t1[u];
+      sx += c.x * e.x - c.y * e.y;
+      sy += c.x * e.y + c.y * e.x;
+      u += d1;
+      if (u >= L1) u -= L1;
+    }
+    wsum[(long)w * F + o] = make_double2(sx * sc, sy * sc);
+  }
+}
+
+bool spec_supported(int N1, int N2, int M) {
+  const int s = N1 * N2 * M, L1 = 2 * N1 - 1, L2 = 2 * N2 - 1;
+  if (M > kSpecMaxM || L1 > kSpecMaxL1 || s > kSpecMaxS) return false;
+  // LDS of the accumulation and of the inverse transform within 64 KB
+  const size_t acc = ((size_t)s + (size_t)M * N1 * kSpecF2 + L1 + L2) * sizeof(double2);
+  const size_t inv = (2 * (size_t)L1 * L2 + L1 + L2) * sizeof(double2);
+  return acc <= 65536 && inv <= 65536;
+}
+
+// Groups of eigenvectors that fit the partial sums (and C) into cap double2.
+int spec_groups(int N1, int N2, int M, size_t cap) {
+  const int s = N1 * N2 * M, W = M * (M + 1) / 2;
+  const size_t per = (size_t)W * (2 * N1 - 1) * (2 * N2 - 1);
+  const long gmax = (long)(cap / per) - kSpecSlices;  // room for the slice sums C
+  if (gmax < 1) return 0;
+  const int g = (int)std::min<long>(std::min<long>(gmax, 128), s);
+  const int kper = (s + g - 1) / g;
+  return (s + kper - 1) / kper;
+}
+
+hipError_t launch_spec_masks(const SpecArgs& a0, double2* wsum, hipStream_t st) {
+  SpecArgs a = a0;
+  const int M = a.M, W = M * (M + 1) / 2;
+  const int L1 = 2 * a.N1 - 1, L2 = 2 * a.N2 - 1, F = L1 * L2;
+  a.kper = (a.s + a.ngroups - 1) / a.ngroups;
+  const dim3 grid(a.ngroups, (L2 + kSpecF2 - 1) / kSpecF2);
+  const size_t lds = ((size_t)a.s + (size_t)M * a.N1 * kSpecF2 + L1 + L2) * sizeof(double2);
+  switch (M) {
+    case 1: k_spec_accum<1><<<grid, 256, lds, st>>>(a); break;
+    case 2: k_spec_accum<2><<<grid, 256, lds, st>>>(a); break;
+    case 3: k_spec_accum<3><<<grid, 256, lds, st>>>(a); break;
+    case 4: k_spec_accum<4><<<grid, 256, lds, st>>>(a); break;
+    case 5: k_spec_accum<5><<<grid, 256, lds, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_spec_reduce<<<(unsigned)(((long)kSpecSlices * W * F + 255) / 256), 256, 0, st>>>(a, W);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_spec_inverse<<<W, 1024, (2 * (size_t)F + L1 + L2) * sizeof(double2), st>>>(a, wsum, W);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ masks
 // w_{m',m}[Delta] for pairs (m <= m'), Delta = a' - a.
 __global__ __launch_bounds__(256) void k_diagsum(MaskArgs a, int W, int s) {
@@ -419,10 +681,12 @@ hipError_t launch_masks(const MaskArgs& a, hipStream_t s) {
   const int W = a.M * (a.M + 1) / 2;
   const int sN = a.N1 * a.N2 * a.M;
   const int L1 = 2 * a.N1 - 1, L2 = 2 * a.N2 - 1;
-  const int n1 = W * L1 * L2;
-  k_diagsum<<<(4 * n1 + 255) / 256, 256, 0, s>>>(a, W, sN);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (a.Hre) {  // lag sums from H; otherwise wsum holds them already
+    const int n1 = W * L1 * L2;
+    k_diagsum<<<(4 * n1 + 255) / 256, 256, 0, s>>>(a, W, sN);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const long n2 = (long)W * L1 * a.Q;
   k_mask_rows<<<(unsigned)((n2 + 255) / 256), 256, 0, s>>>(a, W);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -164,7 +164,8 @@ struct WeightArgs {
   int first;                // 1 on the first IRLS iteration
   double eps0_frac, gamma, p;
 };
-hipError_t launch_weights(const WeightArgs& a, hipStream_t s);
+hipError_t launch_eps(const WeightArgs& a, hipStream_t s);  // the eps update alone
+hipError_t launch_weights(const WeightArgs& a, hipStream_t s, bool eps = true);
 
 // Householder tridiagonalisation R = Q T Q^H of nbatch n x n Hermitian matrices
 // (one launch per column).  Aw: row-major full matrices (overwritten); Vst:
@@ -236,5 +237,24 @@ struct MaskArgs {
   const double2* twP; const double2* twQ;
 };
 hipError_t launch_masks(const MaskArgs& a, hipStream_t s);
+
+// Lag sums wsum of H = U diag(alpha) U^H from the filter spectra, without H
+// (M <= kSpecMaxM, 2 N1 - 1 <= 32, s <= kSpecMaxS, LDS bounds: spec_supported).
+constexpr int kSpecMaxM = 5;
+constexpr int kSpecMaxS = 2048;   // largest s = N1 N2 M
+constexpr int kSpecSlices = 8;    // fixed-order slices of the group sums
+struct SpecArgs {
+  int N1, N2, M, s;
+  int ngroups, kper;     // eigenvector groups (spec_groups) and eigenvectors per group
+  const double* lamv;    // eigenvalues
+  const double2* U;      // eigenvectors, column-major s x s
+  const double* eps;     // eps of this iteration (device)
+  double p;
+  double2* part;         // [ngroups][W][L1 L2] partial sums
+  double2* C;            // [kSpecSlices][W][L1 L2] slice sums
+};
+bool spec_supported(int N1, int N2, int M);
+int spec_groups(int N1, int N2, int M, size_t cap);
+hipError_t launch_spec_masks(const SpecArgs& a, double2* wsum, hipStream_t st);
 
 }  // namespace slrx

@@ -130,7 +130,7 @@ hipError_t eigh_tdeig(const EighBufs& e, hipStream_t s);   // D, E -> eigenvalue
 hipError_t eigh_backtr(const EighBufs& e, hipStream_t s);  // Z <- Q Z (A used as workspace)
 slrx_status dc_prepare(slrx_plan* pl);
 slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma, const double2* U = nullptr,
-                         const double* lamv = nullptr);
+                         const double* lamv = nullptr, bool want_H = false);
 slrx_status apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part);
 slrx_status coil_pass(slrx_plan* pl);
 slrx_status run_cg(slrx_plan* pl, int n_cg, int it);

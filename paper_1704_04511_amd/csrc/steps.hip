@@ -227,9 +227,12 @@ slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
   return SLRX_OK;
 }
 
-// Weights, filter product and masks from the eigenpairs in lam / Rm.
+// Weights and masks from the eigenpairs in lam / Rm: the lag sums of
+// H = U diag(alpha) U^H from the filter spectra where the shape allows
+// (spec_supported), else from H itself (filter product on MFMA, then its
+// diagonal sums). want_H also forms H (in Hre / Him) on the spectral path.
 slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma, const double2* U,
-                               const double* lamv) {
+                               const double* lamv, bool want_H) {
   const slrx_dims& d = pl->d;
   const int s = d.N1 * d.N2 * d.M;
   WeightArgs wa{};
@@ -244,14 +247,33 @@ slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma, 
   wa.eps0_frac = pl->prm.eps0_frac;
   wa.gamma = gamma;
   wa.p = pl->prm.p;
+  const int ng = spec_supported(d.N1, d.N2, d.M) ? spec_groups(d.N1, d.N2, d.M, (size_t)s * s) : 0;
   {
     KTimer kt(pl, SLRX_K_FILTER);
-    HIPCHK(launch_weights(wa, pl->stream));
-    HIPCHK(launch_filter_product(s, pl->VT, pl->Hre, pl->Him, pl->stream));
+    if (ng > 0) {
+      HIPCHK(launch_eps(wa, pl->stream));
+      SpecArgs sa{};
+      sa.N1 = d.N1; sa.N2 = d.N2; sa.M = d.M; sa.s = s;
+      sa.ngroups = ng;
+      sa.lamv = wa.lamv;
+      sa.U = wa.U;
+      sa.eps = pl->scal;
+      sa.p = pl->prm.p;
+      sa.part = (double2*)pl->VT;  // s^2 double2, unused by this path until H is formed
+      sa.C = sa.part + (size_t)ng * (d.M * (d.M + 1) / 2) * (2 * d.N1 - 1) * (2 * d.N2 - 1);
+      HIPCHK(launch_spec_masks(sa, pl->wsum, pl->stream));
+      if (want_H) {
+        HIPCHK(launch_weights(wa, pl->stream, false));
+        HIPCHK(launch_filter_product(s, pl->VT, pl->Hre, pl->Him, pl->stream));
+      }
+    } else {
+      HIPCHK(launch_weights(wa, pl->stream));
+      HIPCHK(launch_filter_product(s, pl->VT, pl->Hre, pl->Him, pl->stream));
+    }
   }
   MaskArgs ma{};
   ma.P = d.P; ma.Q = d.Q; ma.N1 = d.N1; ma.N2 = d.N2; ma.M = d.M;
-  ma.Hre = pl->Hre;
+  ma.Hre = ng > 0 ? nullptr : pl->Hre;  // null: wsum is already the lag sums
   ma.Him = pl->Him;
   ma.wsum = pl->wsum;
   ma.s1 = pl->s1;
