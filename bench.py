@@ -50,9 +50,9 @@ def algorithmic_bytes(kind: str, T: int, P: int, Q: int, M: int, N1: int, N2: in
         return 6 * V * c
     if kind == "gram":     # images (read x, write/read t, write img), read img, write R
         return 5 * V * c + s * s * 16
-    if kind == "masks":    # spectral path: read the group partial sums of the pair
-        g = spectral_groups(N1, N2, M)  # spectra; else read H (2 s^2 doubles); write E
-        lag = g * W * (2 * N1 - 1) * (2 * N2 - 1) * 16 if g else 2 * s * s * 8
+    if kind == "masks":    # read the lag sums (spectral path) or H (2 s^2 doubles); write E
+        g = spectral_groups(N1, N2, M)
+        lag = W * (2 * N1 - 1) * (2 * N2 - 1) * 16 if g else 2 * s * s * 8
         return lag + W * P * Q * c
     if kind == "filter":   # read U (s^2 complex128); write H (2 s^2 doubles)
         return s * s * 16 + 2 * s * s * 8
