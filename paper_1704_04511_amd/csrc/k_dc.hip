@@ -51,7 +51,7 @@ struct DcArgs {
   const int4* nodes;  // (start, size, size of the first child, unused) per internal node
   int node0;          // first node of the level being merged
   int* ws_i;          // 4 n ints: perm, order, rot_p, rot_q
-  double* ws_d;       // 7 n doubles: dl, zl, rot_c, rot_s, tau, zhat, (spare)
+  double* ws_d;       // 7 n doubles: dl, zl, rot_c, rot_s, tau, zhat, deflation records
   int* ws_node;       // 4 ints per node: k, nrot, 0, 0
   int* ws_orig;       // n ints: pole each root is measured from
   double2* Z;         // output eigenvectors, complex column-major n x n
