@@ -85,6 +85,40 @@ def test_weights_and_masks_match_oracle(shape):
         assert nrmse(E[w], E_ref[m, mp]) < 2e-5, (m, mp)
 
 
+def masks_from_H(H, N1, N2, M, P, Q):
+    """Masks straight from H: the lag sums w_{m',m}[a' - a] of the (m', m) block, then
+    E(r) = sum_Delta w[Delta] e^{+2 pi i (Delta1 r1 / P + Delta2 r2 / Q)} (FP64)."""
+    NN, L1, L2 = N1 * N2, 2 * N1 - 1, 2 * N2 - 1
+    a1, a2 = np.divmod(np.arange(NN), N2)
+    d1 = (a1[:, None] - a1[None, :] + N1 - 1).ravel()  # row a', column a
+    d2 = (a2[:, None] - a2[None, :] + N2 - 1).ravel()
+    F1 = np.exp(2j * np.pi * np.outer(np.arange(P), np.arange(L1) - (N1 - 1)) / P)
+    F2 = np.exp(2j * np.pi * np.outer(np.arange(Q), np.arange(L2) - (N2 - 1)) / Q)
+    out = []
+    for m, mp in pairs(M):
+        w = np.zeros((L1, L2), np.complex128)
+        np.add.at(w, (d1, d2), H[mp * NN:(mp + 1) * NN, m * NN:(m + 1) * NN].ravel())
+        out.append(F1 @ w @ F2.T)
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("shape", STEP_SHAPES[:-1])
+def test_masks_agree_with_the_returned_filter_matrix(shape):
+    """The masks of one weights step (from the filter spectra where the shape allows,
+    else from H's diagonal sums) against masks synthesised on the host from the H the
+    same call returns: two routes to the same quantity, FP64 up to the FP32 store."""
+    T, P, Q, N1, N2, M = shape
+    say(f"masks vs H {shape}")
+    rng, x, _ = problem(6, T, P, Q)
+    lam_max = np.linalg.eigvalsh(oracle.gram(x.astype(np.complex128), N1, N2, M)).max()
+    with make_plan(*shape) as pl:
+        pl.set_kspace(x)
+        pl.set_mask(np.ones((T, P, Q), np.uint8))
+        lam, H, E = pl.step_weights(0.01 * lam_max)
+    ref = masks_from_H(H, N1, N2, M, P, Q)
+    assert nrmse(E, ref) < 2e-6
+
+
 @pytest.mark.parametrize("shape", STEP_SHAPES)
 def test_normal_operator_matches_oracle(shape):
     T, P, Q, N1, N2, M = shape

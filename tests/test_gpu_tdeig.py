@@ -3,8 +3,9 @@ stage of the Gram eigen-decomposition) against its definition: T Z = Z diag(lam)
 with Z orthogonal, and the eigenvalues of LAPACK's tridiagonal solver.  The
 matrices exercise the solver's branches: random, zero couplings (merges
 without a rank-one term), nearly equal diagonals (deflation by rotation),
-repeated blocks, Wilkinson's matrix, a clustered Gram-like spectrum and a
-graded diagonal."""
+repeated blocks, Wilkinson's matrix, a clustered Gram-like spectrum, a
+rank-deficient Gram-like spectrum at the full 1125 size and a graded
+diagonal."""
 import numpy as np
 import pytest
 import scipy.linalg
@@ -39,6 +40,12 @@ def matrices(n, rng):
         X = rng.standard_normal((n, 8 * n))
         Tm = scipy.linalg.hessenberg(X @ X.T)
         out["clustered gram"] = (np.diag(Tm).copy(), np.diag(Tm, 1).copy())
+    if n == 1125:
+        # rank n/3 plus a 1e-12 floor: two thirds of the spectrum in a tight cluster, as in
+        # the Gram matrices of late IRLS iterations (long deflation chains, bitonic sort)
+        X = rng.standard_normal((n, n // 3))
+        Tm = scipy.linalg.hessenberg(X @ X.T + 1e-12 * np.eye(n))
+        out["low-rank gram"] = (np.diag(Tm).copy(), np.diag(Tm, 1).copy())
     return out
 
 
