@@ -20,7 +20,8 @@ slrx = pytest.importorskip("paper_1704_04511_amd")
 
 # (T, P, Q, N1, N2, M): several tiles, odd radices (96 = 16*3*2, 160 = 16*5*2,
 # 192 = 16*4*3), even/odd filters, M = 1 and M = T, the largest frame count
-# (T = 32) with the largest tap count (M = 8).
+# (T = 32) with the largest tap count (M = 8), one-wide filters (N1 = 1 or N2 = 1)
+# on the spectral lag-sum route.
 STEP_SHAPES = [
     (5, 16, 16, 3, 3, 2),
     (32, 16, 16, 2, 2, 8),
@@ -32,6 +33,8 @@ STEP_SHAPES = [
     (16, 128, 128, 9, 9, 5),
     (6, 16, 16, 2, 1, 1),
     (6, 16, 16, 1, 1, 3),
+    (4, 32, 32, 1, 18, 1),
+    (4, 32, 32, 16, 1, 2),
     (20, 256, 256, 15, 15, 5),
 ]
 
