@@ -527,7 +527,7 @@ __global__ __launch_bounds__(256) void k_dc_secular(DcArgs a0) {
   const double pb = last ? 0.0 : dl[j + 1] - dor;    // right pole (unused for the last root)
   double lo = sign > 0.0 ? 0.0 : -hiv, hi = sign > 0.0 ? hiv : 0.0;
   double x = sign * hiv;  // the midpoint (the far end for the last root)
-  double prev_step = 1e300;
+  double prev_step = 1e300, fprev = 0.0;
   for (int it = 0; it < 200; ++it) {
     const SecTerms t = secular(dl, z2, k, j, dor, rho, x);
     const double f = 1.0 + t.psi + t.phi;
@@ -547,10 +547,23 @@ __global__ __launch_bounds__(256) void k_dc_secular(DcArgs a0) {
         ok = true;
       }
     } else {
-      const double T = t.dphi * (pb - x) * (pb - x);
-      const double c = f - S / (pa - x) - T / (pb - x);
+      // When the last step cut |f| by less than 10x (a root close to a pole whose
+      // coupling is tiny: the curvature of the other poles is then fitted onto it),
+      // the nearer pole keeps its exact weight and the rest of f' goes to the other.
+      double Sm = S, T = t.dphi * (pb - x) * (pb - x);
+      if (it > 0 && fabs(f) > 0.1 * fabs(fprev)) {
+        const double fp = t.dpsi + t.dphi;
+        if (o == j) {
+          Sm = rho * z2[j];
+          T = (fp - Sm / ((pa - x) * (pa - x))) * (pb - x) * (pb - x);
+        } else {
+          T = rho * z2[j + 1];
+          Sm = (fp - T / ((pb - x) * (pb - x))) * (pa - x) * (pa - x);
+        }
+      }
+      const double c = f - Sm / (pa - x) - T / (pb - x);
       // c (pa - y)(pb - y) + S (pb - y) + T (pa - y) = 0
-      const double qa = c, qb = -(c * (pa + pb) + S + T), qc = c * pa * pb + S * pb + T * pa;
+      const double qa = c, qb = -(c * (pa + pb) + Sm + T), qc = c * pa * pb + Sm * pb + T * pa;
       const double disc = qb * qb - 4.0 * qa * qc;
       if (disc >= 0.0) {
         const double q = -0.5 * (qb + copysign(sqrt(disc), qb));
@@ -577,6 +590,7 @@ __global__ __launch_bounds__(256) void k_dc_secular(DcArgs a0) {
       step = fabs(xn - x);
     }
     prev_step = step;
+    fprev = f;
     x = xn;
   }
   if ((threadIdx.x & 63) == 0) {
