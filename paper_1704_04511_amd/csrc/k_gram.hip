@@ -363,7 +363,7 @@ template <int M>
 __global__ __launch_bounds__(256) void k_spec_accum(SpecArgs a) {
   constexpr int W = M * (M + 1) / 2;
   extern __shared__ double2 spl[];
-  const int N1 = a.N1, N2 = a.N2, s = a.s, NN = N1 * N2;
+  const int N1 = a.N1, N2 = a.N2, s = a.s;
   const int L1 = 2 * N1 - 1, L2 = 2 * N2 - 1, F = L1 * L2;
   const int c0 = blockIdx.y * kSpecF2, nf2 = min(kSpecF2, L2 - c0);
   double2* v = spl;                    // eigenvector k, s entries
@@ -462,7 +462,6 @@ __global__ __launch_bounds__(256) void k_spec_accum(SpecArgs a) {
         }
     }
   }
-  (void)NN;
   if (act) {
     const int f = f1 * L2 + c0 + fl;
 #pragma unroll
