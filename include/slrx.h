@@ -5,14 +5,14 @@
  * Method: Balachandrasekaran, Magnotta, Jacob, "Recovery of damped exponentials
  * using structured low rank matrix completion" (arXiv 1704.04511).  The
  * library runs the IRLS loop of Algorithm 1 on one GPU:
- *   step 1 (Sec. III.C): Gram matrix R of the multi-fold Toeplitz lifting of
+ *   step 1 (Sec. III.B): Gram matrix R of the multi-fold Toeplitz lifting of
  *     the k-space samples, formed by Fourier autocorrelation of the images
  *     (eq. "eq:block-expression for R", eq. "eq:P_ij modified"); its FP64
  *     eigen-decomposition; weights alpha_i = (lambda_i + eps)^(p/2-1); the
  *     summed filter power spectra as per-pixel penalty masks (Sec. III.A);
  *   step 2 (Sec. III.A, eq. "eq:grad_ls"): a fixed number of conjugate-gradient
  *     iterations on (S + lam F G F^H) x = S b;
- *   then eps <- eps / gamma (Sec. III.D).
+ *   then eps <- eps / gamma (Sec. III.C).
  *
  * Conventions
  *   - k-space and images are complex64 (interleaved re, im float) arrays
@@ -23,7 +23,8 @@
  *     min ||S x - b||^2 + lam J(x);  lam = 2/(mu p) for the paper's mu.
  *   - Filter support N1 x N2 x M (spatial x spatial x taps); s = N1 N2 M.
  *   - Supported frame sizes P, Q in {8,16,32,64,96,128,160,192,256};
- *     1 <= M <= min(T, 8); T <= 32; 1 <= N1 <= P; 1 <= N2 <= Q.
+ *     1 <= M <= min(T, 8); T <= 32; 1 <= N1 <= P; 1 <= N2 <= Q;
+ *     s = N1 N2 M <= 3000 (the size the eigensolver chain handles).
  *
  * Ownership and errors
  *   - The library owns every device buffer it allocates.  Host inputs are
@@ -32,8 +33,8 @@
  *     the next slrx_sync on that plan.
  *   - Every call returns an slrx_status; no C++ exception crosses the ABI.
  *     Argument validation happens before any device work and is testable
- *     without a GPU.  slrx_last_error() returns a message for the calling
- *     thread's last failure.
+ *     without a GPU.  slrx_last_error(plan) returns the message of the plan's
+ *     last failed call, slrx_last_error(NULL) that of the calling thread's.
  *   - One plan is used by one thread at a time; different plans may run
  *     concurrently on different streams.
  */
@@ -55,7 +56,9 @@ typedef enum {
   SLRX_ESTATE = -4,      /* call not allowed in the plan's current state */
   SLRX_ENUMERIC = -5,    /* eigen-decomposition failed or non-finite values */
   SLRX_EBUSY = -6,       /* plan is running */
-  SLRX_ENOTREADY = -7    /* no completed run / request not finished */
+  SLRX_ENOTREADY = -7,   /* no completed run / request not finished */
+  SLRX_ECANCELED = -8,   /* server request canceled before admission */
+  SLRX_ETIMEDOUT = -9    /* server request waited longer than the queue timeout */
 } slrx_status;
 
 typedef enum { SLRX_MEM_HOST = 0, SLRX_MEM_DEVICE = 1 } slrx_mem;
@@ -67,7 +70,7 @@ typedef struct {
 } slrx_dims;
 
 /* Algorithm parameters.  lambda >= 0; p in [0, 1] (Schatten exponent,
- * Sec. II.D); gamma > 1 (eps decrease, Sec. III.D); eps0_frac > 0
+ * Sec. II.D); gamma > 1 (eps decrease, Sec. III.C); eps0_frac > 0
  * (eps^(0) = eps0_frac * lambda_max of the first Gram matrix); n_irls >= 1
  * outer iterations; n_cg >= 0 CG iterations per outer iteration. */
 typedef struct {
@@ -78,9 +81,12 @@ typedef struct {
 
 #define SLRX_FLAG_TIMING 1u /* record per-phase device times (hipEvents) */
 #define SLRX_FLAG_KTIME 2u  /* record every launch of each kernel class (hipEvents) */
-#define SLRX_FLAG_LIBEIGH 4u /* eigen-decomposition entirely by rocSOLVER zheevd (reference
-                                path); default: own Householder tridiagonalisation, divide
-                                and conquer and back-transformation on the GPU */
+#define SLRX_FLAG_LIBEIGH 4u /* test reference only: the eigen-decomposition by rocSOLVER
+                                zheevd instead of the library's own chain (Householder
+                                tridiagonalisation, divide and conquer, back-transformation),
+                                to check the latter against an independent solver; its
+                                handle and workspace are allocated at the first such run,
+                                outside slrx_footprint; servers reject it */
 #define SLRX_FLAG_GIRAF 8u  /* the GIRAF approximation the paper compares with (Sec. IV,
                                Fig. 3): the lifting circular along the parameter axis
                                as well as in space (all T shifts, frame indices mod T)
@@ -133,7 +139,8 @@ void slrx_default_params(slrx_params* out);
 /* Validate dims/params without touching the device.  SLRX_OK or SLRX_EINVAL. */
 slrx_status slrx_validate(const slrx_dims* dims, const slrx_params* params);
 
-/* Device bytes a plan of these dims allocates (used for admission). */
+/* Device bytes a plan of these dims allocates (its buffer arena; a server adds
+ * the request's share of the engine's eigen-decomposition buffers). */
 size_t slrx_footprint(const slrx_dims* dims);
 
 /* Create a plan on the current HIP device.  hip_stream: a hipStream_t to run
@@ -241,10 +248,13 @@ slrx_status slrx_step_cg(slrx_plan* plan, const void* E, int32_t n_cg);
  * scheduler thread advances every active request by one outer iteration per
  * step, exactly as slrx_run_batch does; a request arriving while others run
  * joins at the next step.  A request's result is bit-identical to slrx_run on
- * the same data.  The engine's shared eigen-decomposition buffers (about
- * 72 s^2 bytes per active request of Gram size s) are not charged to the
- * budget.  hip_stream is ignored.
- * Thread-safe: any thread may submit, poll, wait or fetch. */
+ * the same data.  A request is charged its plan's footprint plus its share of
+ * the engine's shared eigen-decomposition buffers (about 72 s^2 bytes for Gram
+ * size s); the budget bounds every device byte the server holds: running
+ * requests, idle plans kept for reuse, and engine buffers left from earlier
+ * steps (freed when an admission needs the room).  Every request runs on a
+ * stream of its own and the engine's on another, so hip_stream is ignored.
+ * Thread-safe: any thread may submit, poll, wait, cancel or fetch. */
 typedef struct {
   double t_submit, t_admit, t_done; /* steady-clock seconds */
   int32_t state;                    /* 0 queued, 1 running, 2 done */
@@ -254,10 +264,13 @@ typedef struct {
 
 slrx_status slrx_server_create(size_t budget_bytes, int32_t max_slots,
                                void* hip_stream, slrx_server** out);
-/* Cancels queued requests, waits for running ones, frees server-owned state. */
+/* Cancels queued requests (SLRX_ECANCELED), waits for running ones and for
+ * threads inside slrx_wait to return, frees server-owned state. */
 void slrx_server_destroy(slrx_server* srv);
 /* Submit an existing plan (k-space and mask set); it is run in place and its
- * footprint is charged while it runs.  The plan must not be used until done. */
+ * footprint is charged while it runs.  The plan must not be used until done;
+ * SLRX_EBUSY if it is already queued or running on this server, SLRX_EINVAL
+ * for a plan with SLRX_FLAG_LIBEIGH. */
 slrx_status slrx_submit(slrx_server* srv, slrx_plan* plan, uint64_t* ticket);
 /* Submit host data; at admission the server takes an idle plan of the same
  * shape or creates one (allocating its device state), keeps it resident while
@@ -270,10 +283,21 @@ slrx_status slrx_submit_data(slrx_server* srv, const slrx_dims* dims, const slrx
 slrx_status slrx_poll(slrx_server* srv, uint64_t ticket, int32_t* done);
 /* Block until the request is done; returns its status. */
 slrx_status slrx_wait(slrx_server* srv, uint64_t ticket);
+/* As slrx_wait, but returns SLRX_ENOTREADY if the request is not done within
+ * timeout_s seconds (>= 0; 0 polls). */
+slrx_status slrx_wait_for(slrx_server* srv, uint64_t ticket, double timeout_s);
+/* Cancel a queued request: it completes with SLRX_ECANCELED.  SLRX_EBUSY if it
+ * is already running (it then runs to completion), SLRX_ESTATE if done. */
+slrx_status slrx_cancel(slrx_server* srv, uint64_t ticket);
+/* Requests not admitted within `seconds` of their submission complete with
+ * SLRX_ETIMEDOUT (0, the default: no limit).  Checked by the scheduler at
+ * least every seconds / 4. */
+slrx_status slrx_server_set_queue_timeout(slrx_server* srv, double seconds);
 slrx_status slrx_get_request_info(slrx_server* srv, uint64_t ticket, slrx_request_info* out);
-/* Budget in use (bytes: running requests plus idle plans kept for reuse by
- * later requests of the same shape; idle plans are evicted when a request of
- * another shape needs the room) and number of queued requests. */
+/* Device bytes the server holds (running requests, idle plans kept for reuse
+ * by later requests of the same shape, engine buffers beyond the running
+ * requests' shares; idle plans are evicted and engine buffers trimmed when a
+ * request needs the room) and number of queued requests. */
 slrx_status slrx_server_usage(slrx_server* srv, size_t* used, int32_t* queued);
 /* Copy a done server-owned request's images (complex64 [T][P][Q]) to host memory. */
 slrx_status slrx_fetch_images(slrx_server* srv, uint64_t ticket, void* out_host);
@@ -281,7 +305,9 @@ slrx_status slrx_fetch_images(slrx_server* srv, uint64_t ticket, void* out_host)
 slrx_status slrx_release(slrx_server* srv, uint64_t ticket);
 
 const char* slrx_status_str(slrx_status s);
-const char* slrx_last_error(void);
+/* Message of the last failed call on `plan`, or of the calling thread's last
+ * failed call when plan is NULL ("" if none).  Valid until the next call. */
+const char* slrx_last_error(const slrx_plan* plan);
 
 #ifdef __cplusplus
 }

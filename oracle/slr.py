@@ -21,12 +21,12 @@ paper where it is silent, listed again in the design notes):
   n = M-1..T-1 and all w, i.e. T(xhat) d is a 3-D convolution that is linear
   (valid) along the parameter axis and circular in space.
 * The Gram matrix is R = T^H T (s x s, the filter side); its eigenvectors are
-  the filters (Sec. III.C, eq. ``eq:gram matrix``).
+  the filters (Sec. III.B, eq. ``eq:gram matrix``).
 * Per least-squares step the objective is ||S xhat - b||^2 + lam J(xhat) with
   J = sum_i alpha_i ||T(xhat) u_i||^2; lam = 2/(mu p) relative to eq.
   ``eq:x-update``.
 * epsilon^(0) = eps0_frac * lambda_max of the first Gram matrix, and after each
-  least-squares step epsilon <- epsilon / gamma (Sec. III.D); negative
+  least-squares step epsilon <- epsilon / gamma (Sec. III.C); negative
   round-off eigenvalues are clamped to zero before adding epsilon.
 * CG is warm-started from the current iterate, runs exactly ``n_cg``
   iterations and stops early only on an exactly zero residual or curvature.
@@ -103,7 +103,7 @@ def lift(xhat: np.ndarray, N1: int, N2: int, M: int, circ_t: bool = False) -> np
 
 # -------------------------------------------------------------- Gram matrix
 def gram(xhat: np.ndarray, N1: int, N2: int, M: int, circ_t: bool = False) -> np.ndarray:
-    """Gram matrix R = T(xhat)^H T(xhat) by FFT autocorrelation (Sec. III.C).
+    """Gram matrix R = T(xhat)^H T(xhat) by FFT autocorrelation (Sec. III.B).
 
     Block (m, m') of R (eq. ``eq:block-expression for R``) sums, over the
     k valid parameter shifts, products of Toeplitz blocks; each product is read
@@ -132,7 +132,7 @@ def gram(xhat: np.ndarray, N1: int, N2: int, M: int, circ_t: bool = False) -> np
 
 # ---------------------------------------------------------- weight update
 def eig_weights(R: np.ndarray, eps: float, p: float):
-    """Eigen-decomposition of R and IRLS weights (Sec. III.C, Algorithm 1 step 1).
+    """Eigen-decomposition of R and IRLS weights (Sec. III.B, Algorithm 1 step 1).
 
     alpha_i = (lambda_i + eps)^(p/2 - 1), with lambda_i clamped at 0.
     Returns (lambda ascending, U, alpha).
@@ -143,7 +143,7 @@ def eig_weights(R: np.ndarray, eps: float, p: float):
 
 
 def weight_matrix(U: np.ndarray, alpha: np.ndarray) -> np.ndarray:
-    """H = U (Lambda + eps I)^(p/2-1) U^* (Sec. III.C, weight update eq. ``eq:weight-update``)."""
+    """H = U (Lambda + eps I)^(p/2-1) U^* (Sec. III.B, weight update eq. ``eq:weight-update``)."""
     return (U * alpha[None, :]) @ U.conj().T
 
 
@@ -276,10 +276,10 @@ def irls(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
          coils: np.ndarray | None = None, circ_t: bool = False) -> np.ndarray:
     """Algorithm 1: alternate the weight update and the CG least-squares step.
 
-    Step 1 (Sec. III.C): Gram matrix by FFT autocorrelation, eigen-decomposition,
+    Step 1 (Sec. III.B): Gram matrix by FFT autocorrelation, eigen-decomposition,
     weights alpha_i = (lambda_i + eps)^(p/2-1) and masks E.  Step 2 (Sec. III.A):
     a few CG iterations on (S + lam F G F^*) xhat = S o b.  Then eps <- eps/gamma
-    (Sec. III.D).  Returns the images F^-1 xhat (or xhat with ``return_kspace``).
+    (Sec. III.C).  Returns the images F^-1 xhat (or xhat with ``return_kspace``).
 
     With ``coils`` (sensitivities C, [Nc][P][Q]) the data b is [Nc][T][P][Q] and
     the least-squares step uses the multichannel model of Sec. II.A:

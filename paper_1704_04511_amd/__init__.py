@@ -40,7 +40,8 @@ MAX_IRLS = 256
 KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "tri", "tdeig", "backtr", "filter", "masks", "coil")
 
 STATUS = {0: "SLRX_OK", -1: "SLRX_EINVAL", -2: "SLRX_ENOMEM", -3: "SLRX_EDEVICE", -4: "SLRX_ESTATE",
-          -5: "SLRX_ENUMERIC", -6: "SLRX_EBUSY", -7: "SLRX_ENOTREADY"}
+          -5: "SLRX_ENUMERIC", -6: "SLRX_EBUSY", -7: "SLRX_ENOTREADY", -8: "SLRX_ECANCELED",
+          -9: "SLRX_ETIMEDOUT"}
 
 
 class SlrxError(RuntimeError):
@@ -123,8 +124,11 @@ _SIGS = {
     "slrx_server_usage": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32)]),
     "slrx_fetch_images": (_I, [_P, ctypes.c_uint64, _P]),
     "slrx_release": (_I, [_P, ctypes.c_uint64]),
+    "slrx_wait_for": (_I, [_P, ctypes.c_uint64, ctypes.c_double]),
+    "slrx_cancel": (_I, [_P, ctypes.c_uint64]),
+    "slrx_server_set_queue_timeout": (_I, [_P, ctypes.c_double]),
     "slrx_status_str": (ctypes.c_char_p, [_I]),
-    "slrx_last_error": (ctypes.c_char_p, []),
+    "slrx_last_error": (ctypes.c_char_p, [_P]),
 }
 
 
@@ -152,9 +156,11 @@ def lib():
     return _lib
 
 
-def _check(status: int):
+def _check(status: int, plan=None):
+    """Raise SlrxError for a failed call; the message is the plan's last error
+    (or the calling thread's, for calls without a plan)."""
     if status != 0:
-        raise SlrxError(status, lib().slrx_last_error().decode(errors="replace"))
+        raise SlrxError(status, lib().slrx_last_error(plan).decode(errors="replace"))
 
 
 def default_params() -> Params:
@@ -218,6 +224,9 @@ class Plan:
     def handle(self):
         return self._h
 
+    def _c(self, status: int):
+        _check(status, self._h)
+
     @property
     def shape(self):
         d = self.dims
@@ -251,12 +260,12 @@ class Plan:
 
     def set_kspace(self, b):
         ptr, mem, keep = _ptr(b, np.complex64, self.shape)
-        _check(lib().slrx_set_kspace(self._h, ptr, mem))
+        self._c(lib().slrx_set_kspace(self._h, ptr, mem))
         self._keep_b = keep
 
     def set_mask(self, S):
         ptr, mem, keep = _ptr(S, np.uint8, self.shape)
-        _check(lib().slrx_set_mask(self._h, ptr, mem))
+        self._c(lib().slrx_set_mask(self._h, ptr, mem))
         self._keep_S = keep
 
     def set_coils(self, C, b):
@@ -264,7 +273,7 @@ class Plan:
         coil k-space b [Nc][T][P][Q], both complex64, both host arrays or both
         device tensors; ``C=None`` returns to the single-channel model."""
         if C is None:
-            _check(lib().slrx_set_coils(self._h, 0, None, None, SLRX_MEM_HOST))
+            self._c(lib().slrx_set_coils(self._h, 0, None, None, SLRX_MEM_HOST))
             self._keep_coils = None
             return
         d = self.dims
@@ -273,7 +282,7 @@ class Plan:
         bp, bm, bk = _ptr(b, np.complex64, (nc, d.T, d.P, d.Q))
         if cm != bm:
             raise ValueError("coil maps and coil data must both be host arrays or both device tensors")
-        _check(lib().slrx_set_coils(self._h, nc, cp, bp, cm))
+        self._c(lib().slrx_set_coils(self._h, nc, cp, bp, cm))
         self._keep_coils = (ck, bk)
 
     def fit_t2(self, te_ms, img=None):
@@ -289,57 +298,57 @@ class Plan:
         ip, keep = (None, None)
         if img is not None:
             ip, _, keep = _ptr(np.ascontiguousarray(img, dtype=np.complex64), np.complex64, self.shape)
-        _check(lib().slrx_fit_t2(self._h, ip, te.ctypes.data_as(ctypes.c_void_p),
+        self._c(lib().slrx_fit_t2(self._h, ip, te.ctypes.data_as(ctypes.c_void_p),
                                  t2.ctypes.data_as(ctypes.c_void_p), amp.ctypes.data_as(ctypes.c_void_p),
                                  SLRX_MEM_HOST))
         return t2, amp
 
     def set_init(self, x0):
         ptr, mem, keep = _ptr(x0, np.complex64, self.shape)
-        _check(lib().slrx_set_init(self._h, ptr, mem))
+        self._c(lib().slrx_set_init(self._h, ptr, mem))
         self._keep_x0 = keep
 
     def clear_init(self):
-        _check(lib().slrx_clear_init(self._h))
+        self._c(lib().slrx_clear_init(self._h))
 
     def set_filter(self, N1, N2, M):
-        _check(lib().slrx_set_filter(self._h, N1, N2, M))
+        self._c(lib().slrx_set_filter(self._h, N1, N2, M))
         self.dims.N1, self.dims.N2, self.dims.M = N1, N2, M
 
     def set_params(self, params: Params):
-        _check(lib().slrx_set_params(self._h, ctypes.byref(params)))
+        self._c(lib().slrx_set_params(self._h, ctypes.byref(params)))
         self.params = params
 
     def run(self):
-        _check(lib().slrx_run(self._h))
+        self._c(lib().slrx_run(self._h))
 
     def sync(self):
-        _check(lib().slrx_sync(self._h))
+        self._c(lib().slrx_sync(self._h))
 
     def images(self, out=None):
         if out is None:
             out = np.empty(self.shape, np.complex64)
         ptr, mem, _ = _ptr(out, np.complex64, self.shape)
-        _check(lib().slrx_get_images(self._h, ptr, mem))
+        self._c(lib().slrx_get_images(self._h, ptr, mem))
         return out
 
     def kspace(self, out=None):
         if out is None:
             out = np.empty(self.shape, np.complex64)
         ptr, mem, _ = _ptr(out, np.complex64, self.shape)
-        _check(lib().slrx_get_kspace(self._h, ptr, mem))
+        self._c(lib().slrx_get_kspace(self._h, ptr, mem))
         return out
 
     def stats(self) -> dict:
         s = Stats()
-        _check(lib().slrx_get_stats(self._h, ctypes.byref(s)))
+        self._c(lib().slrx_get_stats(self._h, ctypes.byref(s)))
         return s.as_dict()
 
     # ---- single steps
     def step_gram(self):
         s = self.s
         R = np.empty((s, s), np.complex128, order="F")
-        _check(lib().slrx_step_gram(self._h, R.ctypes.data_as(ctypes.c_void_p), SLRX_MEM_HOST))
+        self._c(lib().slrx_step_gram(self._h, R.ctypes.data_as(ctypes.c_void_p), SLRX_MEM_HOST))
         return R
 
     def step_weights(self, eps: float):
@@ -347,7 +356,7 @@ class Plan:
         lam = np.empty(s, np.float64)
         H = np.empty((s, s), np.complex128)
         E = np.empty((self.W, d.P, d.Q), np.complex64)
-        _check(lib().slrx_step_weights(self._h, float(eps), lam.ctypes.data_as(ctypes.c_void_p),
+        self._c(lib().slrx_step_weights(self._h, float(eps), lam.ctypes.data_as(ctypes.c_void_p),
                                        H.ctypes.data_as(ctypes.c_void_p), E.ctypes.data_as(ctypes.c_void_p),
                                        SLRX_MEM_HOST))
         return lam, H, E
@@ -362,7 +371,7 @@ class Plan:
         lam = np.empty(s, np.float64)
         Z = np.empty((s, s), np.complex128)  # column-major: Z[c] is eigenvector c
         Ep = E.ctypes.data_as(ctypes.c_void_p) if s > 1 else None
-        _check(lib().slrx_step_tdeig(self._h, D.ctypes.data_as(ctypes.c_void_p), Ep,
+        self._c(lib().slrx_step_tdeig(self._h, D.ctypes.data_as(ctypes.c_void_p), Ep,
                                      lam.ctypes.data_as(ctypes.c_void_p), Z.ctypes.data_as(ctypes.c_void_p),
                                      SLRX_MEM_HOST))
         return lam, Z.T
@@ -372,13 +381,13 @@ class Plan:
         Ep, _, Ek = _ptr(E, np.complex64, (self.W, d.P, d.Q))
         vp, _, vk = _ptr(v, np.complex64, self.shape)
         out = np.empty(self.shape, np.complex64)
-        _check(lib().slrx_step_apply(self._h, Ep, vp, out.ctypes.data_as(ctypes.c_void_p), SLRX_MEM_HOST))
+        self._c(lib().slrx_step_apply(self._h, Ep, vp, out.ctypes.data_as(ctypes.c_void_p), SLRX_MEM_HOST))
         return out
 
     def step_cg(self, E, n_cg: int):
         d = self.dims
         Ep, _, Ek = _ptr(E, np.complex64, (self.W, d.P, d.Q))
-        _check(lib().slrx_step_cg(self._h, Ep, int(n_cg)))
+        self._c(lib().slrx_step_cg(self._h, Ep, int(n_cg)))
 
 
 def run_batch(plans, stream=None, sync=True):
@@ -412,6 +421,20 @@ class Server:
             self.close()
         except Exception:
             pass
+
+    def wait_for(self, ticket: int, timeout_s: float) -> bool:
+        """True when the request finished (ok) within timeout_s; False if not yet done."""
+        st = lib().slrx_wait_for(self._h, ticket, float(timeout_s))
+        if st == -7:
+            return False
+        _check(st)
+        return True
+
+    def cancel(self, ticket: int):
+        _check(lib().slrx_cancel(self._h, ticket))
+
+    def set_queue_timeout(self, seconds: float):
+        _check(lib().slrx_server_set_queue_timeout(self._h, float(seconds)))
 
     def submit(self, plan: Plan) -> int:
         t = ctypes.c_uint64()

@@ -26,6 +26,10 @@ using namespace slrx;
 
 // ---------------------------------------------------------------- errors
 static thread_local std::string g_last_error;
+static thread_local slrx_plan* g_cur_plan = nullptr;
+
+slrx::PlanScope::PlanScope(slrx_plan* p) : prev(g_cur_plan) { g_cur_plan = p; }
+slrx::PlanScope::~PlanScope() { g_cur_plan = prev; }
 
 slrx_status slrx::fail(slrx_status st, const char* fmt, ...) {
   char buf[512];
@@ -34,6 +38,7 @@ slrx_status slrx::fail(slrx_status st, const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_last_error = buf;
+  if (g_cur_plan) g_cur_plan->last_error = buf;
   return st;
 }
 
@@ -71,7 +76,7 @@ slrx::KTimer::~KTimer() {
   if (idx >= 0) (void)hipEventRecord(pl->kev[cls][2 * idx + 1], pl->stream);
 }
 
-bool slrx_plan::lib_eigh() const { return (prm.flags & SLRX_FLAG_LIBEIGH) != 0 || s() > tri_max_n(); }
+bool slrx_plan::lib_eigh() const { return (prm.flags & SLRX_FLAG_LIBEIGH) != 0; }
 
 extern "C" const char* slrx_status_str(slrx_status s) {
   switch (s) {
@@ -83,11 +88,15 @@ extern "C" const char* slrx_status_str(slrx_status s) {
     case SLRX_ENUMERIC: return "numerical failure";
     case SLRX_EBUSY: return "busy";
     case SLRX_ENOTREADY: return "not ready";
+    case SLRX_ECANCELED: return "canceled";
+    case SLRX_ETIMEDOUT: return "timed out";
   }
   return "unknown status";
 }
 
-extern "C" const char* slrx_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* slrx_last_error(const slrx_plan* pl) {
+  return pl ? pl->last_error.c_str() : g_last_error.c_str();
+}
 
 extern "C" void slrx_default_params(slrx_params* out) {
   if (!out) return;
@@ -201,9 +210,7 @@ static Layout plan_layout(const slrx_dims& d) {
 
 extern "C" size_t slrx_footprint(const slrx_dims* dims) {
   if (validate_dims(dims) != SLRX_OK) return 0;
-  // plan buffers plus the eigensolver workspace (bounded estimate: 3 s^2 complex + s^2 real)
-  const size_t s = (size_t)dims->N1 * dims->N2 * dims->M;
-  return plan_layout(*dims).total + align_up(s * s * 16 * 3 + s * s * 8 + (1 << 20));
+  return plan_layout(*dims).total;
 }
 
 // ------------------------------------------------------------ plan create
@@ -229,7 +236,8 @@ static slrx_status make_twiddles(slrx_plan* pl) {
   return SLRX_OK;
 }
 
-static slrx_status setup_eigensolver(slrx_plan* pl) {
+slrx_status slrx::setup_libeigh(slrx_plan* pl) {
+  if (pl->blas) return SLRX_OK;
   if (rocblas_create_handle(&pl->blas) != rocblas_status_success)
     return fail(SLRX_EDEVICE, "rocblas_create_handle failed");
   if (rocblas_set_stream(pl->blas, pl->stream) != rocblas_status_success)
@@ -332,8 +340,8 @@ extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params
   }
   pl->arena_bytes = L.total;
   assign_buffers(pl, L);
-  slrx_status st = setup_eigensolver(pl);
-  if (st == SLRX_OK && hipMemset(pl->arena, 0, L.total) != hipSuccess) st = fail(SLRX_EDEVICE, "hipMemset failed");
+  slrx_status st = SLRX_OK;
+  if (hipMemset(pl->arena, 0, L.total) != hipSuccess) st = fail(SLRX_EDEVICE, "hipMemset failed");
   if (st == SLRX_OK) st = make_twiddles(pl);
   if (st == SLRX_OK) st = dc_prepare(pl);
   if (st == SLRX_OK) {
@@ -409,6 +417,7 @@ static slrx_status check_idle(slrx_plan* pl) {
 }
 
 extern "C" slrx_status slrx_set_kspace(slrx_plan* pl, const void* b, slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   STCHK(copy_in(pl, pl->b, b, pl->vol() * sizeof(float2), mem));
   pl->has_b = true;
@@ -417,6 +426,7 @@ extern "C" slrx_status slrx_set_kspace(slrx_plan* pl, const void* b, slrx_mem me
 }
 
 extern "C" slrx_status slrx_set_coils(slrx_plan* pl, int32_t ncoils, const void* C, const void* b, slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   if (ncoils < 0 || ncoils > SLRX_MAX_COILS)
     return fail(SLRX_EINVAL, "ncoils=%d out of range [0,%d]", (int)ncoils, SLRX_MAX_COILS);
@@ -454,6 +464,7 @@ extern "C" slrx_status slrx_set_coils(slrx_plan* pl, int32_t ncoils, const void*
 }
 
 extern "C" slrx_status slrx_set_mask(slrx_plan* pl, const uint8_t* S, slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   STCHK(copy_in(pl, pl->S, S, pl->vol(), mem));
   pl->has_S = true;
@@ -462,6 +473,7 @@ extern "C" slrx_status slrx_set_mask(slrx_plan* pl, const uint8_t* S, slrx_mem m
 }
 
 extern "C" slrx_status slrx_set_init(slrx_plan* pl, const void* x0, slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   STCHK(copy_in(pl, pl->x0, x0, pl->vol() * sizeof(float2), mem));
   pl->has_init = true;
@@ -470,6 +482,7 @@ extern "C" slrx_status slrx_set_init(slrx_plan* pl, const void* x0, slrx_mem mem
 }
 
 extern "C" slrx_status slrx_clear_init(slrx_plan* pl) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   pl->has_init = false;
   pl->prepared = false;
@@ -477,6 +490,7 @@ extern "C" slrx_status slrx_clear_init(slrx_plan* pl) {
 }
 
 extern "C" slrx_status slrx_set_filter(slrx_plan* pl, int32_t N1, int32_t N2, int32_t M) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   slrx_dims d = pl->d;
   d.N1 = N1;
@@ -492,6 +506,7 @@ extern "C" slrx_status slrx_set_filter(slrx_plan* pl, int32_t N1, int32_t N2, in
 }
 
 extern "C" slrx_status slrx_set_params(slrx_plan* pl, const slrx_params* prm) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   STCHK(validate_params(prm));
   pl->prm = *prm;
@@ -534,6 +549,7 @@ slrx_status slrx::enqueue_run(slrx_plan* pl) {
 }
 
 extern "C" slrx_status slrx_run(slrx_plan* pl) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   return enqueue_run(pl);
 }
@@ -566,6 +582,7 @@ slrx_status slrx::finish(slrx_plan* pl) {
 }
 
 extern "C" slrx_status slrx_sync(slrx_plan* pl) {
+  PlanScope scope(pl);
   if (!pl) return fail(SLRX_EINVAL, "plan is NULL");
   STCHK(finish(pl));
   HIPCHK(hipStreamSynchronize(pl->stream));
@@ -583,6 +600,7 @@ static slrx_status require_done(slrx_plan* pl) {
 }
 
 extern "C" slrx_status slrx_get_images(slrx_plan* pl, void* out, slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(require_done(pl));
   STCHK(images(pl));
   return copy_out(pl, out, pl->img, pl->vol() * sizeof(float2), mem);
@@ -590,6 +608,7 @@ extern "C" slrx_status slrx_get_images(slrx_plan* pl, void* out, slrx_mem mem) {
 
 extern "C" slrx_status slrx_fit_t2(slrx_plan* pl, const void* img, const double* te_ms, double* t2_out,
                                    double* amp_out, slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   if (!te_ms || !t2_out) return fail(SLRX_EINVAL, "echo times or output pointer is NULL");
   if (mem != SLRX_MEM_HOST && mem != SLRX_MEM_DEVICE) return fail(SLRX_EINVAL, "bad memory kind %d", (int)mem);
@@ -630,11 +649,13 @@ extern "C" slrx_status slrx_fit_t2(slrx_plan* pl, const void* img, const double*
 }
 
 extern "C" slrx_status slrx_get_kspace(slrx_plan* pl, void* out, slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(require_done(pl));
   return copy_out(pl, out, pl->x, pl->vol() * sizeof(float2), mem);
 }
 
 extern "C" slrx_status slrx_get_stats(slrx_plan* pl, slrx_stats* out) {
+  PlanScope scope(pl);
   if (!out) return fail(SLRX_EINVAL, "out is NULL");
   STCHK(require_done(pl));
   std::memset(out, 0, sizeof *out);
@@ -726,6 +747,7 @@ static slrx_status ensure_prepared(slrx_plan* pl) {
 }
 
 extern "C" slrx_status slrx_step_gram(slrx_plan* pl, void* R_out, slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(ensure_prepared(pl));
   STCHK(step_gram(pl, true));
   const size_t s = (size_t)pl->d.N1 * pl->d.N2 * pl->d.M;
@@ -736,6 +758,7 @@ extern "C" slrx_status slrx_step_gram(slrx_plan* pl, void* R_out, slrx_mem mem) 
 
 extern "C" slrx_status slrx_step_weights(slrx_plan* pl, double eps, double* lam_out, void* H_out, void* E_out,
                                          slrx_mem mem) {
+  PlanScope scope(pl);
   if (!(eps > 0.0) || !std::isfinite(eps)) return fail(SLRX_EINVAL, "eps must be finite and > 0");
   STCHK(ensure_prepared(pl));
   STCHK(step_gram(pl));
@@ -775,6 +798,7 @@ extern "C" slrx_status slrx_step_weights(slrx_plan* pl, double eps, double* lam_
 
 extern "C" slrx_status slrx_step_tdeig(slrx_plan* pl, const double* D, const double* E, double* lam_out, void* Z_out,
                                        slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(check_idle(pl));
   if (!D || (!E && pl->s() > 1) || !lam_out || !Z_out) return fail(SLRX_EINVAL, "NULL argument");
   const int s = pl->s();
@@ -789,6 +813,7 @@ extern "C" slrx_status slrx_step_tdeig(slrx_plan* pl, const double* D, const dou
 }
 
 extern "C" slrx_status slrx_step_apply(slrx_plan* pl, const void* E, const void* v, void* out, slrx_mem mem) {
+  PlanScope scope(pl);
   STCHK(ensure_prepared(pl));
   const slrx_dims& d = pl->d;
   const size_t W = (size_t)d.M * (d.M + 1) / 2;
@@ -802,6 +827,7 @@ extern "C" slrx_status slrx_step_apply(slrx_plan* pl, const void* E, const void*
 }
 
 extern "C" slrx_status slrx_step_cg(slrx_plan* pl, const void* E, int32_t n_cg) {
+  PlanScope scope(pl);
   if (n_cg < 0 || n_cg > kMaxCg) return fail(SLRX_EINVAL, "n_cg out of range");
   STCHK(ensure_prepared(pl));
   pl->ktime = false;

@@ -27,8 +27,16 @@ struct BatchEig {
   hipEvent_t ev_free = nullptr;  // every reader of the group buffers has run
   bool have_free = false;
   std::map<int, EigGroup> groups;
+  size_t allocated() const;  // device bytes held by the groups
   ~BatchEig();
 };
+
+// Device bytes the shared eigen-decomposition buffers hold per problem of Gram
+// size n (an upper bound of what one more problem of that size adds).
+size_t engine_problem_bytes(int n);
+// Shrink the groups to at most keep[n] problems of size n (absent: none), after
+// the work that reads them has finished (synchronises the engine's stream).
+slrx_status engine_trim(BatchEig& be, const std::map<int, int>& keep);
 
 // Start a problem: masked data, initial iterate, start event, iteration 0.
 slrx_status engine_begin(slrx_plan* pl);

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
 #include <map>
 #include <vector>
 
@@ -53,7 +54,63 @@ slrx::BatchEig::~BatchEig() {
 
 static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Buffers for nb problems of size n (grown, never shrunk).
+// Layout of the buffers for nb problems of size n: every matrix-sized buffer
+// per problem, the vectors for all of them.
+struct GroupLayout {
+  size_t sA, sQ, sWi, sWd, sB, sv, sd, total;
+};
+static GroupLayout group_layout(int n, int nb) {
+  GroupLayout L;
+  const size_t nn = (size_t)n * n;
+  L.sA = al(nn * sizeof(double2));
+  L.sQ = al(3 * nn * sizeof(double));
+  L.sWi = al(dc_ws_ints(n) * sizeof(int));
+  L.sWd = al(dc_ws_doubles(n) * sizeof(double));
+  L.sB = al(bt_scratch_elems(n) * sizeof(double2));
+  L.sv = al((size_t)nb * n * sizeof(double2));
+  L.sd = al((size_t)nb * n * sizeof(double));
+  L.total = (size_t)nb * (3 * L.sA + L.sQ + L.sWi + L.sWd + L.sB) + 5 * L.sv + 2 * L.sd;
+  return L;
+}
+static size_t tree_bytes(int n) { return std::max<size_t>((size_t)4 * n, 4) * sizeof(int); }
+
+size_t slrx::engine_problem_bytes(int n) { return group_layout(n, 1).total + tree_bytes(n); }
+
+size_t slrx::BatchEig::allocated() const {
+  size_t b = 0;
+  for (const auto& kv : groups) {
+    if (kv.second.mem) b += group_layout(kv.first, kv.second.cap).total;
+    if (kv.second.tree) b += tree_bytes(kv.first);
+  }
+  return b;
+}
+
+slrx_status slrx::engine_trim(BatchEig& be, const std::map<int, int>& keep) {
+  bool synced = false;
+  for (auto it = be.groups.begin(); it != be.groups.end();) {
+    const auto k = keep.find(it->first);
+    const int want = k == keep.end() ? 0 : k->second;
+    if (it->second.cap <= want) {
+      ++it;
+      continue;
+    }
+    if (!synced) {
+      if (be.stream) HIPCHK(hipStreamSynchronize(be.stream));  // no reader of the buffers is left
+      synced = true;
+    }
+    if (want == 0) {
+      it = be.groups.erase(it);  // frees the buffers and the tree
+      continue;
+    }
+    if (it->second.mem) HIPCHK(hipFree(it->second.mem));
+    it->second.mem = nullptr;
+    it->second.cap = 0;  // reserved again at the next step, for the problems present then
+    ++it;
+  }
+  return SLRX_OK;
+}
+
+// Buffers for nb problems of size n (grown on demand; engine_trim shrinks them).
 static slrx_status group_reserve(BatchEig& be, int n, int nb, EigGroup*& out) {
   if (!be.stream) {
     HIPCHK(hipStreamCreateWithFlags(&be.stream, hipStreamNonBlocking));
@@ -67,8 +124,7 @@ static slrx_status group_reserve(BatchEig& be, int n, int nb, EigGroup*& out) {
     dc_build_tree(n, nodes, G.level_start);
     G.node_sizes.resize(nodes.size() / 4);
     for (size_t q = 0; q < nodes.size() / 4; ++q) G.node_sizes[q] = nodes[4 * q + 1];
-    if (hipMalloc(&G.tree, std::max<size_t>(nodes.size(), 4) * sizeof(int)) != hipSuccess)
-      return fail(SLRX_ENOMEM, "divide-and-conquer tree");
+    if (hipMalloc(&G.tree, tree_bytes(n)) != hipSuccess) return fail(SLRX_ENOMEM, "divide-and-conquer tree");
     if (!nodes.empty())
       HIPCHK(hipMemcpy(G.tree, nodes.data(), nodes.size() * sizeof(int), hipMemcpyHostToDevice));
   }
@@ -78,11 +134,9 @@ static slrx_status group_reserve(BatchEig& be, int n, int nb, EigGroup*& out) {
     G.mem = nullptr;
     G.cap = 0;
     const size_t nn = (size_t)n * n;
-    const size_t sA = al(nn * sizeof(double2)), sQ = al(3 * nn * sizeof(double));
-    const size_t sWi = al(dc_ws_ints(n) * sizeof(int)), sWd = al(dc_ws_doubles(n) * sizeof(double));
-    const size_t sB = al(bt_scratch_elems(n) * sizeof(double2));
-    const size_t sv = al((size_t)nb * n * sizeof(double2)), sd = al((size_t)nb * n * sizeof(double));
-    const size_t total = (size_t)nb * (3 * sA + sQ + sWi + sWd + sB) + 5 * sv + 2 * sd;
+    const GroupLayout L = group_layout(n, nb);
+    const size_t sA = L.sA, sQ = L.sQ, sWi = L.sWi, sWd = L.sWd, sB = L.sB, sv = L.sv, sd = L.sd;
+    const size_t total = L.total;
     if (hipMalloc(&G.mem, total) != hipSuccess) return fail(SLRX_ENOMEM, "eigen-decomposition buffers (%zu bytes)", total);
     char* p = (char*)G.mem;
     auto take = [&](size_t b) {

@@ -1,5 +1,5 @@
 // Back-transformation of the tridiagonal eigenvectors, U = Q Z (FP64), last
-// stage of the Gram eigen-decomposition in the weight update (Sec. III.C,
+// stage of the Gram eigen-decomposition in the weight update (Sec. III.B,
 // Algorithm 1 step 1).
 //
 // The Householder reduction leaves Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k

@@ -1,6 +1,6 @@
 // Eigenpairs of the real symmetric tridiagonal matrix left by the Householder
 // reduction (FP64), middle stage of the Gram eigen-decomposition in the weight
-// update (Sec. III.C, Algorithm 1 step 1): divide and conquer.
+// update (Sec. III.B, Algorithm 1 step 1): divide and conquer.
 //
 // The index range is halved recursively down to single entries; every
 // coupling E[c-1] between the halves at a split c is torn off as a rank-one

@@ -2,7 +2,7 @@
 // IRLS weights, the filter product H = U diag(alpha) U^H on FP64 MFMA, and the
 // penalty masks E (summed power spectra of the weighted filters).
 //
-// Gram (Sec. III.C, eq. "eq:block-expression for R" and eq. "eq:P_ij modified"):
+// Gram (Sec. III.B, eq. "eq:block-expression for R" and eq. "eq:P_ij modified"):
 //   c_{m,m'}(r) = sum_{n=M-1}^{T-1} conj(rho_{n-m}(r)) rho_{n-m'}(r)
 // (the GIRAF variant: n = 0..T-1, frame indices mod T),
 //   R[(m,a),(m',a')] = F_u(c_{m,m'})[a - a'],

@@ -1,6 +1,6 @@
 // Householder reduction of the Hermitian Gram matrix to real symmetric
 // tridiagonal form, R = Q T Q^H (FP64), first stage of the eigen-decomposition
-// in the weight update (Sec. III.C, Algorithm 1 step 1).
+// in the weight update (Sec. III.B, Algorithm 1 step 1).
 //
 // Column k needs a global matrix-vector product with the trailing block, so
 // every column is one launch (the launch boundary is the grid-wide sync).  A

@@ -3,13 +3,14 @@
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <string>
 #include <vector>
 
 #include "../../include/slrx.h"
 
 namespace slrx {
 
-constexpr int kMaxS = 4096;    // largest filter size s = N1 N2 M
+constexpr int kMaxS = 3000;    // largest filter size s = N1 N2 M (own eigensolver chain)
 constexpr int kMaxCg = 10000;  // largest CG iteration count
 // info: eigensolver status per outer iteration, the single-step slot
 // (SLRX_MAX_IRLS), and a flag raised by the Gram pass on a non-finite entry
@@ -26,6 +27,15 @@ enum Buf {
 };
 
 slrx_status fail(slrx_status st, const char* fmt, ...);
+// Binds the failures of the calling thread to a plan while in scope (the plan's
+// last error; the thread's last error is always set as well).
+struct PlanScope {
+  slrx_plan* prev;
+  explicit PlanScope(slrx_plan* p);
+  ~PlanScope();
+};
+// rocSOLVER handle and workspace of the library eigensolver (created once per plan).
+slrx_status setup_libeigh(slrx_plan* pl);
 
 
 }  // namespace slrx
@@ -68,9 +78,12 @@ struct slrx_plan {
   void* coil_mem = nullptr;
   float2 *Ct = nullptr, *Bc = nullptr, *Yc = nullptr, *rho = nullptr, *dco = nullptr;
 
+  // rocSOLVER handle and workspace of the library eigensolver, a test reference
+  // selected by SLRX_FLAG_LIBEIGH; created at its first use
   rocblas_handle blas = nullptr;
   void* blas_ws = nullptr;
   size_t blas_ws_size = 0;
+  std::string last_error;  // message of this plan's last failed call
 
   hipEvent_t ev_run[2] = {nullptr, nullptr};
   hipEvent_t ev_step = nullptr;  // ordering against a shared batched eigen-decomposition
@@ -89,7 +102,7 @@ struct slrx_plan {
 
   size_t vol() const { return (size_t)d.T * d.P * d.Q; }
   int s() const { return d.N1 * d.N2 * d.M; }
-  // own tridiagonalisation unless the flag asks for the library path or s is too large
+  // the library eigensolver (test reference) instead of the own chain
   bool lib_eigh() const;
 };
 

@@ -2,7 +2,12 @@
 //
 // Requests wait in a FIFO queue and are admitted, first fit, between engine
 // steps: as soon as fewer than max_slots requests are active and a request's
-// device footprint fits the remaining HBM budget.  One scheduler thread drives
+// device footprint fits the remaining HBM budget.  A request's footprint is
+// its plan's buffers plus its share of the engine's eigen-decomposition
+// buffers; the budget covers every device byte the server holds (running
+// plans, idle plans kept for reuse, and the engine buffers, which are trimmed
+// back to the running requests' needs when an admission would not fit
+// otherwise).  One scheduler thread drives
 // the lock-step engine: each step advances every active request by one outer
 // IRLS iteration, with one launch sequence of the eigen-decomposition per
 // group of equal Gram size and all other kernels on each request's own stream.  A request
@@ -16,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <condition_variable>
 #include <deque>
@@ -25,6 +31,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "engine.h"
@@ -43,7 +50,9 @@ struct Req {
   uint64_t id = 0;
   slrx_plan* plan = nullptr;
   bool owned = false;       // plan created by the server at admission
-  size_t bytes = 0;
+  size_t bytes = 0;         // plan footprint + engine share, charged while running
+  size_t eig = 0;           // engine share (part of bytes)
+  int s = 0;                // Gram size
   int state = 0;            // 0 queued, 1 running, 2 done
   bool holds_budget = false;
   slrx_status status = SLRX_OK;
@@ -71,6 +80,13 @@ struct slrx_server {
   std::unordered_map<uint64_t, Req*> reqs;
   size_t used = 0;          // footprint of admitted (running) requests
   size_t pooled = 0;        // footprint of idle plans kept for reuse
+  size_t eig_alloc = 0;     // engine buffers allocated (scheduler's last report)
+  size_t eig_need = 0;      // engine shares of the running requests
+  std::map<int, int> running_by_s;  // running requests per Gram size
+  double queue_timeout = 0; // seconds a request may wait for admission (0: no limit)
+  int waiters = 0;          // threads inside slrx_wait / slrx_wait_for
+  std::condition_variable cv_idle;
+  std::unordered_set<slrx_plan*> busy;  // caller plans queued or running
   std::multimap<ShapeKey, std::pair<slrx_plan*, size_t>> pool;  // idle server-owned plans
   uint64_t next_id = 1;
   bool stop = false;
@@ -81,41 +97,79 @@ struct slrx_server {
 static void release_budget(slrx_server* s, Req* r) {
   if (r->holds_budget) {
     s->used -= r->bytes;
+    s->eig_need -= r->eig;
+    if (--s->running_by_s[r->s] == 0) s->running_by_s.erase(r->s);
     r->holds_budget = false;
   }
 }
 
-// Pick the first queued request that can run (caller holds mu): a server-owned
-// request takes an idle plan of its shape from the pool if there is one;
-// otherwise its footprint must fit the budget next to the running requests,
-// evicting idle plans of other shapes if needed.  Evicted plans are returned
-// through `evict` and destroyed by the caller outside the lock.
-static Req* take_admissible(slrx_server* s, std::vector<slrx_plan*>& evict) {
+// Engine bytes allocated beyond what the running requests are charged for.
+static size_t eig_excess(const slrx_server* s) { return s->eig_alloc > s->eig_need ? s->eig_alloc - s->eig_need : 0; }
+
+// Device bytes the server holds (caller holds mu).
+static size_t held(const slrx_server* s) { return s->used + s->pooled + eig_excess(s); }
+
+// Pick the first queued request that can run (caller holds mu; called by the
+// scheduler thread, which owns the engine).  A server-owned request takes an
+// idle plan of its shape from the pool if there is one (then only its engine
+// share is new); otherwise its whole footprint must fit the budget next to
+// what the server holds, evicting idle plans of other shapes and trimming the
+// engine's buffers to the running requests' needs if that is what it takes.
+// Evicted plans are returned through `evict` and destroyed by the caller
+// outside the lock.
+static Req* take_admissible(slrx_server* s, BatchEig& eig, std::vector<slrx_plan*>& evict) {
   for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
     Req* r = *it;
-    if (r->owned) {
-      auto pit = s->pool.find(key_of(r->dims));
-      if (pit != s->pool.end()) {
-        r->plan = pit->second.first;
-        s->pooled -= pit->second.second;
-        s->pool.erase(pit);
-        s->queue.erase(it);
-        return r;
-      }
+    auto pit = s->pool.end();
+    if (r->owned) pit = s->pool.find(key_of(r->dims));
+    const size_t plan_new = pit != s->pool.end() ? 0 : r->bytes - r->eig;
+    const size_t plan_reused = pit != s->pool.end() ? pit->second.second : 0;
+    auto fits = [&]() { return held(s) + plan_new + r->eig <= s->budget; };
+    if (s->used + r->bytes > s->budget) continue;  // cannot fit next to the running requests
+    if (!fits() && eig_excess(s) > 0) {
+      (void)engine_trim(eig, s->running_by_s);
+      s->eig_alloc = eig.allocated();
     }
-    if (s->used + r->bytes > s->budget) continue;
-    while (s->used + s->pooled + r->bytes > s->budget && !s->pool.empty()) {
+    while (!fits() && !s->pool.empty()) {
       auto victim = s->pool.begin();
+      if (victim == pit) {
+        if (++victim == s->pool.end()) break;
+      }
       evict.push_back(victim->second.first);
       s->pooled -= victim->second.second;
       s->pool.erase(victim);
     }
-    if (s->used + s->pooled + r->bytes <= s->budget) {
-      s->queue.erase(it);
-      return r;
+    if (!fits()) continue;
+    if (pit != s->pool.end()) {
+      r->plan = pit->second.first;
+      s->pooled -= plan_reused;
+      s->pool.erase(pit);
     }
+    s->queue.erase(it);
+    return r;
   }
   return nullptr;
+}
+
+// Complete queued requests whose wait for admission exceeded the queue timeout
+// (caller holds mu).
+static void expire_queued(slrx_server* s) {
+  if (!(s->queue_timeout > 0)) return;
+  const double now = now_s();
+  for (auto it = s->queue.begin(); it != s->queue.end();) {
+    Req* r = *it;
+    if (now - r->t_submit > s->queue_timeout) {
+      r->state = 2;
+      r->status = SLRX_ETIMEDOUT;
+      r->err = "request waited longer than the queue timeout";
+      r->t_done = now;
+      if (!r->owned) s->busy.erase(r->plan);
+      it = s->queue.erase(it);
+      s->cv_done.notify_all();
+    } else {
+      ++it;
+    }
+  }
 }
 
 // Bind a newly admitted request to its plan and start it on the engine.
@@ -153,7 +207,7 @@ static slrx_status collect_request(Req* r) {
 
 // Mark a request done, release its budget, keep its plan idle for reuse.
 static void complete_request(slrx_server* s, Req* r, slrx_status st) {
-  std::string err = st != SLRX_OK ? std::string(slrx_last_error()) : std::string();
+  std::string err = st != SLRX_OK ? std::string(slrx_last_error(nullptr)) : std::string();
   if (r->owned && r->plan && st != SLRX_OK) {
     slrx_plan_destroy(r->plan);
     r->plan = nullptr;
@@ -164,6 +218,7 @@ static void complete_request(slrx_server* s, Req* r, slrx_status st) {
   r->t_done = now_s();
   r->state = 2;
   release_budget(s, r);
+  if (!r->owned) s->busy.erase(r->plan);
   if (r->owned && r->plan) {
     s->pool.emplace(key_of(r->dims), std::make_pair(r->plan, r->bytes));
     s->pooled += r->bytes;
@@ -184,10 +239,14 @@ static void scheduler_main(slrx_server* s) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
       for (;;) {
+        expire_queued(s);
+        s->eig_alloc = s->eig.allocated();
         while (!s->stop && (int)(active.size() + admitted.size()) < s->max_slots) {
-          Req* r = take_admissible(s, evict);
+          Req* r = take_admissible(s, s->eig, evict);
           if (!r) break;
           s->used += r->bytes;
+          s->eig_need += r->eig;
+          ++s->running_by_s[r->s];
           r->holds_budget = true;
           r->state = 1;
           r->t_admit = now_s();
@@ -195,7 +254,10 @@ static void scheduler_main(slrx_server* s) {
         }
         stopping = s->stop;
         if (!admitted.empty() || !active.empty() || !finishing.empty() || stopping) break;
-        s->cv_work.wait(lk);
+        if (s->queue_timeout > 0 && !s->queue.empty())
+          s->cv_work.wait_for(lk, std::chrono::duration<double>(s->queue_timeout / 4));
+        else
+          s->cv_work.wait(lk);
       }
     }
     for (slrx_plan* p : evict) slrx_plan_destroy(p);
@@ -211,6 +273,10 @@ static void scheduler_main(slrx_server* s) {
       std::vector<slrx_plan*> plans;
       for (Req* r : active) plans.push_back(r->plan);
       slrx_status st = engine_step(plans, s->eig);
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->eig_alloc = s->eig.allocated();
+      }
       for (Req* r : active) {
         slrx_plan* pl = r->plan;
         if (st == SLRX_OK && hipEventRecord(pl->ev_iter[(pl->it_next - 1) & 1], pl->stream) != hipSuccess)
@@ -282,13 +348,21 @@ extern "C" void slrx_server_destroy(slrx_server* s) {
     // queued requests are cancelled
     for (Req* r : s->queue) {
       r->state = 2;
-      r->status = SLRX_ESTATE;
+      r->status = SLRX_ECANCELED;
       r->err = "server destroyed before admission";
+      r->t_done = now_s();
     }
     s->queue.clear();
   }
+  s->cv_done.notify_all();
   s->cv_work.notify_all();
-  if (s->scheduler.joinable()) s->scheduler.join();
+  if (s->scheduler.joinable()) s->scheduler.join();  // running requests complete
+  {
+    // threads still inside slrx_wait leave before the server goes away
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.notify_all();
+    s->cv_idle.wait(lk, [&] { return s->waiters == 0; });
+  }
   for (auto& kv : s->pool) slrx_plan_destroy(kv.second.first);
   for (auto& kv : s->reqs) {
     Req* r = kv.second;
@@ -320,12 +394,25 @@ static slrx_status enqueue(slrx_server* s, Req* r, uint64_t* ticket) {
 
 extern "C" slrx_status slrx_submit(slrx_server* s, slrx_plan* plan, uint64_t* ticket) {
   if (!s || !plan || !ticket) return fail(SLRX_EINVAL, "NULL argument");
-  if (!plan->has_b || !plan->has_S) return fail(SLRX_ESTATE, "plan has no k-space or mask");
+  if (!(plan->has_b || plan->ncoils > 0) || !plan->has_S) return fail(SLRX_ESTATE, "plan has no k-space or mask");
+  if (plan->lib_eigh()) return fail(SLRX_EINVAL, "the library eigensolver is a test reference and is not served");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->busy.count(plan)) return fail(SLRX_EBUSY, "plan is already queued or running on this server");
+    s->busy.insert(plan);
+  }
   Req* r = new Req();
   r->plan = plan;
   r->owned = false;
-  r->bytes = slrx_footprint(&plan->cap);
-  return enqueue(s, r, ticket);
+  r->s = plan->s();
+  r->eig = engine_problem_bytes(r->s);
+  r->bytes = slrx_footprint(&plan->cap) + r->eig;
+  const slrx_status st = enqueue(s, r, ticket);
+  if (st != SLRX_OK) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->busy.erase(plan);
+  }
+  return st;
 }
 
 extern "C" slrx_status slrx_submit_data(slrx_server* s, const slrx_dims* dims, const slrx_params* params,
@@ -339,9 +426,15 @@ extern "C" slrx_status slrx_submit_data(slrx_server* s, const slrx_dims* dims, c
   if (params) r->prm = *params;
   else slrx_default_params(&r->prm);
   const size_t V = (size_t)dims->T * dims->P * dims->Q;
+  if (r->prm.flags & SLRX_FLAG_LIBEIGH) {
+    delete r;
+    return fail(SLRX_EINVAL, "the library eigensolver is a test reference and is not served");
+  }
   r->b.assign((const float2*)b, (const float2*)b + V);
   r->S.assign(S, S + V);
-  r->bytes = slrx_footprint(dims);
+  r->s = dims->N1 * dims->N2 * dims->M;
+  r->eig = engine_problem_bytes(r->s);
+  r->bytes = slrx_footprint(dims) + r->eig;
   return enqueue(s, r, ticket);
 }
 
@@ -359,13 +452,60 @@ extern "C" slrx_status slrx_poll(slrx_server* s, uint64_t ticket, int32_t* done)
   return SLRX_OK;
 }
 
-extern "C" slrx_status slrx_wait(slrx_server* s, uint64_t ticket) {
+// Block until the request is done or `timeout_s` seconds have passed (< 0: no limit).
+static slrx_status wait_request(slrx_server* s, uint64_t ticket, double timeout_s) {
   if (!s) return fail(SLRX_EINVAL, "NULL argument");
   std::unique_lock<std::mutex> lk(s->mu);
   Req* r = find(s, ticket);
   if (!r) return fail(SLRX_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
-  s->cv_done.wait(lk, [&] { return r->state == 2; });
-  if (r->status != SLRX_OK) return fail(r->status, "%s", r->err.c_str());
+  ++s->waiters;
+  auto done = [&] { return r->state == 2 || s->stop; };
+  bool ok = true;
+  if (timeout_s < 0) s->cv_done.wait(lk, done);
+  else ok = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done);
+  const int state = r->state;
+  const slrx_status rst = r->status;
+  const std::string err = r->err;
+  if (--s->waiters == 0) s->cv_idle.notify_all();
+  if (!ok || state != 2) return fail(SLRX_ENOTREADY, "request %llu not finished", (unsigned long long)ticket);
+  if (rst != SLRX_OK) return fail(rst, "%s", err.c_str());
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_wait(slrx_server* s, uint64_t ticket) { return wait_request(s, ticket, -1.0); }
+
+extern "C" slrx_status slrx_wait_for(slrx_server* s, uint64_t ticket, double timeout_s) {
+  if (!(timeout_s >= 0.0)) return fail(SLRX_EINVAL, "timeout must be >= 0");
+  return wait_request(s, ticket, timeout_s);
+}
+
+extern "C" slrx_status slrx_cancel(slrx_server* s, uint64_t ticket) {
+  if (!s) return fail(SLRX_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  Req* r = find(s, ticket);
+  if (!r) return fail(SLRX_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  if (r->state == 2) return fail(SLRX_ESTATE, "request %llu already finished", (unsigned long long)ticket);
+  if (r->state == 1) return fail(SLRX_EBUSY, "request %llu is running", (unsigned long long)ticket);
+  for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
+    if (*it == r) {
+      s->queue.erase(it);
+      break;
+    }
+  r->state = 2;
+  r->status = SLRX_ECANCELED;
+  r->err = "request canceled before admission";
+  r->t_done = now_s();
+  if (!r->owned) s->busy.erase(r->plan);
+  s->cv_done.notify_all();
+  return SLRX_OK;
+}
+
+extern "C" slrx_status slrx_server_set_queue_timeout(slrx_server* s, double seconds) {
+  if (!s) return fail(SLRX_EINVAL, "NULL argument");
+  if (!(seconds >= 0.0) || !std::isfinite(seconds)) return fail(SLRX_EINVAL, "timeout must be finite and >= 0");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->queue_timeout = seconds;
+  s->cv_work.notify_all();
   return SLRX_OK;
 }
 
@@ -386,7 +526,7 @@ extern "C" slrx_status slrx_get_request_info(slrx_server* s, uint64_t ticket, sl
 extern "C" slrx_status slrx_server_usage(slrx_server* s, size_t* used, int32_t* queued) {
   if (!s) return fail(SLRX_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
-  if (used) *used = s->used + s->pooled;
+  if (used) *used = held(s);
   if (queued) *queued = (int32_t)s->queue.size();
   return SLRX_OK;
 }

@@ -104,7 +104,8 @@ slrx_status slrx::step_gram(slrx_plan* pl, bool colmajor, double2* R_out) {
 
 // Eigen-decomposition of the Gram matrix: Householder tridiagonalisation,
 // divide and conquer on the real tridiagonal, blocked back-transformation
-// (eigenvectors into UZ); or rocSOLVER zheevd on Rm (SLRX_FLAG_LIBEIGH).
+// (eigenvectors into UZ); or, as a test reference only, rocSOLVER zheevd on Rm
+// (SLRX_FLAG_LIBEIGH).
 // Tree of the divide-and-conquer solver for the current s (host table copied
 // to the device; called while the plan is idle).
 slrx_status slrx::dc_prepare(slrx_plan* pl) {
@@ -204,6 +205,7 @@ slrx_status slrx::step_eigh(slrx_plan* pl, int it) {
   const int s = pl->s();
   rocblas_int* info = pl->info + (it < 0 ? SLRX_MAX_IRLS : it);
   if (pl->lib_eigh()) {
+    STCHK(setup_libeigh(pl));
     KTimer kt(pl, SLRX_K_TDEIG);
     rocblas_status rs = rocsolver_zheevd(pl->blas, rocblas_evect_original, rocblas_fill_lower, s,
                                          (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework, info);

@@ -50,6 +50,7 @@ def test_default_params():
     ((64, 64, 8, 65, 5, 3), "does not fit"),
     ((64, 64, 8, 5, 0, 3), "does not fit"),
     ((256, 256, 32, 40, 40, 8), "exceeds"),
+    ((256, 256, 32, 25, 25, 5), "exceeds"),  # s = 3125: beyond the eigensolver chain (3000)
 ])
 def test_invalid_dims_rejected(dims, msg):
     with pytest.raises(slrx.SlrxError) as ei:
@@ -91,12 +92,27 @@ def test_status_strings():
     assert L.slrx_status_str(0) == b"ok"
     assert L.slrx_status_str(-1) == b"invalid argument"
     assert L.slrx_status_str(-7) == b"not ready"
+    assert L.slrx_status_str(-8) == b"canceled"
+    assert L.slrx_status_str(-9) == b"timed out"
+
+
+def test_thread_last_error_without_a_plan():
+    L = slrx.lib()
+    assert L.slrx_validate(None, None) == -1
+    msg = L.slrx_last_error(None)
+    assert b"dims is NULL" in msg
+    # a failure on another thread leaves this thread's message alone
+    import threading
+    t = threading.Thread(target=lambda: L.slrx_footprint(None))
+    t.start()
+    t.join()
+    assert L.slrx_last_error(None) == msg
 
 
 def test_null_arguments_rejected():
     L = slrx.lib()
     assert L.slrx_validate(None, None) == -1
-    assert b"NULL" in L.slrx_last_error()
+    assert b"NULL" in L.slrx_last_error(None)
     assert L.slrx_plan_create(None, None, None, None) == -1
     assert L.slrx_run(None) == -1
     assert L.slrx_sync(None) == -1

@@ -165,3 +165,129 @@ def test_server_rejects_request_larger_than_budget():
         assert ei.value.name == "SLRX_ENOMEM"
     finally:
         srv.close()
+
+
+def _long_problem(seed=301):
+    """A request that keeps the device busy for a while (about 0.2 s)."""
+    return workload.make_problem(seed=seed, P=256, Q=256, T=20, K=2, R=8, N1=15, N2=15, M=5,
+                                 n_irls=20, n_cg=15, name="long")
+
+
+def test_server_budget_bounds_device_memory():
+    """The budget covers the engine's eigen-decomposition buffers too: what the server
+    reports never exceeds it, and neither does the device memory it actually holds
+    (hipMemGetInfo), beyond a small runtime allowance for streams and events."""
+    import torch
+    pbs = problems()
+    say(f"server device memory within the budget, {len(pbs)} requests x 2")
+    dims = [slrx.Dims(pb.b.shape[1], pb.b.shape[2], pb.b.shape[0], pb.N1, pb.N2, pb.M) for pb in pbs]
+    fps = [slrx.footprint(d) for d in dims]
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    budget = int(max(fps) * 2.5)
+    srv = slrx.Server(budget, max_slots=4)
+    slack = 64 << 20
+    try:
+        tickets = []
+        for rep in range(2):
+            for pb in pbs:
+                prm = slrx.make_params(lam=pb.lam, n_irls=N_IRLS, n_cg=N_CG)
+                tickets.append(srv.submit_data(pb.b, pb.S, pb.N1, pb.N2, pb.M, prm))
+        peak_srv, peak_dev = 0, 0
+        deadline = time.time() + 180.0
+        while not all(srv.poll(t) for t in tickets):
+            peak_srv = max(peak_srv, srv.usage()[0])
+            free, _ = torch.cuda.mem_get_info()
+            peak_dev = max(peak_dev, free0 - free)
+            assert time.time() < deadline, "server did not finish within 180 s"
+            time.sleep(0.002)
+        infos = [srv.info(t) for t in tickets]
+        for t in tickets:
+            srv.wait(t)
+    finally:
+        srv.close()
+    say(f"budget {budget >> 20} MiB: server peak {peak_srv >> 20} MiB, device peak {peak_dev >> 20} MiB")
+    assert peak_srv <= budget
+    assert peak_dev <= budget + slack
+    # every request is charged more than its plan: its share of the engine buffers
+    for i, f in zip(infos, fps * 2):
+        assert i["bytes"] > f
+
+
+def test_server_rejects_a_plan_already_queued():
+    pb = _long_problem()
+    T, P, Q = pb.b.shape
+    say("server: the same plan submitted twice")
+    srv = slrx.Server(8 << 30, max_slots=2)
+    pl = slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg))
+    try:
+        pl.set_kspace(pb.b)
+        pl.set_mask(pb.S)
+        t = srv.submit(pl)
+        with pytest.raises(slrx.SlrxError) as ei:
+            srv.submit(pl)
+        assert ei.value.name == "SLRX_EBUSY"
+        srv.wait(t)
+        t2 = srv.submit(pl)  # free again once done
+        srv.wait(t2)
+    finally:
+        srv.close()
+        pl.close()
+
+
+def test_server_cancel_and_queue_timeout():
+    pb = _long_problem()
+    small = problems()[0]
+    say("server: cancel a queued request, time out another")
+    srv = slrx.Server(8 << 30, max_slots=1)
+    try:
+        prm = slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg)
+        sp = slrx.make_params(lam=small.lam, n_irls=N_IRLS, n_cg=N_CG)
+        ta = srv.submit_data(pb.b, pb.S, pb.N1, pb.N2, pb.M, prm)
+        tb = srv.submit_data(small.b, small.S, small.N1, small.N2, small.M, sp)
+        srv.cancel(tb)
+        with pytest.raises(slrx.SlrxError) as ei:
+            srv.wait(tb)
+        assert ei.value.name == "SLRX_ECANCELED"
+        srv.set_queue_timeout(0.02)
+        tc = srv.submit_data(small.b, small.S, small.N1, small.N2, small.M, sp)
+        with pytest.raises(slrx.SlrxError) as ei:
+            srv.wait(tc)
+        assert ei.value.name == "SLRX_ETIMEDOUT"
+        srv.set_queue_timeout(0.0)
+        assert srv.wait_for(ta, 60.0)
+        with pytest.raises(slrx.SlrxError) as ei:
+            srv.cancel(ta)  # finished
+        assert ei.value.name == "SLRX_ESTATE"
+        td = srv.submit_data(small.b, small.S, small.N1, small.N2, small.M, sp)
+        srv.wait(td)
+        np.testing.assert_array_equal(srv.fetch(td, small.b.shape), alone(small))
+    finally:
+        srv.close()
+
+
+def test_server_destroy_releases_waiting_threads():
+    import threading
+    pb = _long_problem()
+    small = problems()[0]
+    say("server destroyed while a thread waits on a queued request")
+    srv = slrx.Server(8 << 30, max_slots=1)
+    ta = srv.submit_data(pb.b, pb.S, pb.N1, pb.N2, pb.M, slrx.make_params(lam=pb.lam, n_irls=4, n_cg=15))
+    tb = srv.submit_data(small.b, small.S, small.N1, small.N2, small.M,
+                         slrx.make_params(lam=small.lam, n_irls=N_IRLS, n_cg=N_CG))
+    result = {}
+
+    def waiter():
+        try:
+            srv.wait(tb)
+            result["status"] = "SLRX_OK"
+        except slrx.SlrxError as e:
+            result["status"] = e.name
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    time.sleep(0.01)
+    srv.close()  # cancels tb, lets ta finish, waits for the waiter to leave
+    th.join(timeout=60)
+    assert not th.is_alive()
+    assert result.get("status") in ("SLRX_ECANCELED", "SLRX_OK")

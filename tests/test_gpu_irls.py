@@ -43,8 +43,11 @@ def check(pb, n_irls=None, n_cg=None, tol=TOL):
     img, st = run_gpu(pb, n_irls, n_cg)
     ref, tr = run_oracle(pb, n_irls, n_cg)
     e = nrmse(img, ref)
-    print(f"  NRMSE vs oracle {e:.3e}; vs truth gpu {nrmse(img, pb.truth):.4f} oracle {nrmse(ref, pb.truth):.4f}")
+    per_frame = [nrmse(img[t], ref[t]) for t in range(ref.shape[0])]
+    print(f"  NRMSE vs oracle {e:.3e} (worst frame {max(per_frame):.3e}); vs truth gpu "
+          f"{nrmse(img, pb.truth):.4f} oracle {nrmse(ref, pb.truth):.4f}")
     assert e <= tol, e
+    assert max(per_frame) <= tol, per_frame
     n = len(tr["eps"])
     np.testing.assert_allclose(st["eps"][:n], tr["eps"], rtol=1e-5)
     np.testing.assert_allclose(st["lambda_max"][:n], tr["lambda_max"], rtol=1e-5)
