@@ -3,8 +3,9 @@
 // in the weight update (Sec. III.B, Algorithm 1 step 1).
 //
 // Column k needs a global matrix-vector product with the trailing block, so
-// every column is one launch (the launch boundary is the grid-wide sync).  A
-// launch for column k:
+// every column is one launch (the launch boundary is the grid-wide sync; a
+// software barrier between persistent workgroups costs as much or more on this
+// part).  A launch for column k:
 //   * in every workgroup (redundantly, identical arithmetic): finishes the
 //     previous reflector's w = tau p - |tau|^2/2 (p^H v) v from the previous
 //     launch's p = A v, corrects row k with the pending rank-2 update
@@ -13,6 +14,15 @@
 //     of LAPACK's zlarfg);
 //   * on its rows i > k: applies the pending rank-2 update and accumulates
 //     p_i = sum_j A_ij v_j for the next launch.
+// The time of a launch is the serial chain of the reflector, not the traffic
+// of the trailing block, so the chain is kept short: thread t holds the
+// entries j = k + t + 256 u of every vector in registers (the same entries of
+// every row it updates), and a launch makes exactly three block reductions
+// (p^H v, the norm of the column, the row products), each a fixed DPP tree in
+// every wave plus the four wave sums added in order, with the scalars other
+// threads need (p_k, v_k, the subdiagonal entry, the rows' own coefficients)
+// passed through the same exchange.  Results are bit-reproducible and do not
+// depend on how many workgroups run or which rows a workgroup takes.
 // The last columns, once the trailing block fits in the LDS of one workgroup,
 // are reduced in a single launch (k_tri_tail).
 // The working matrix Aw is full (both triangles) and row-major; reflectors are
@@ -25,151 +35,167 @@
 namespace slrx {
 
 constexpr int kTriNT = 256;
-constexpr int kTriRows = 4;  // rows of the trailing block per workgroup: one per wave
-constexpr int kTriUnroll = 4;  // row elements in flight per lane beyond the prefetched part
-constexpr int kTriCrit = 5;    // elements of row k / v / p per thread loaded up front
+constexpr int kTriRB = 4;      // rows of a workgroup whose elements are loaded at kernel entry
+constexpr int kTriRMax = 12;   // rows per workgroup at most (n <= 3000, at most 256 workgroups)
 
 SLRX_DEV double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 SLRX_DEV double2 dscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
-// Deterministic block sum of a complex value (fixed shuffle/tree order).
-SLRX_DEV double2 block_sum2(double2 v, double2* red) {
-  const int tid = threadIdx.x;
-  for (int off = 32; off > 0; off >>= 1) {
-    v.x += __shfl_down(v.x, off, 64);
-    v.y += __shfl_down(v.y, off, 64);
-  }
-  if ((tid & 63) == 0) red[tid >> 6] = v;
-  __syncthreads();
-  if (tid == 0) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int w = 0; w < kTriNT / 64; ++w) s = dadd(s, red[w]);
-    red[kTriNT / 64] = s;
-  }
-  __syncthreads();
-  v = red[kTriNT / 64];
-  __syncthreads();
-  return v;
+// Copy of v from the lane selected by a DPP control (rows masked by RM keep 0).
+template <int CTRL, int RM>
+SLRX_DEV double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RM, 0xf, false);
+  return __hiloint2double(hi, lo);
 }
 
-// NU: row elements per lane loaded at kernel entry (the whole row when the
-// trailing block is at most 64 NU wide), so the row's load latency overlaps
-// the reflector computation.
-template <int NU>
-__global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
-  extern __shared__ double2 sm[];
-  __shared__ double2 red[kTriNT / 64 + 1];
-  __shared__ double2 at_k[2];  // raw p_{k-1}[k], v_{k-1}[k]
+// Sum over the 64 lanes of a wave in a fixed tree (pairs, quads, half rows,
+// rows, then rows 0+1 and 2+3 and the two halves); every lane gets the total.
+// Call with all 64 lanes active.
+SLRX_DEV double wave_total(double v) {
+  v += dpp_mov<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_mov<0x140, 0xf>(v);  // row_mirror
+  v += dpp_mov<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+SLRX_DEV double2 wave_total2(double2 v) { return make_double2(wave_total(v.x), wave_total(v.y)); }
+// The four wave sums of an exchange slot, added in wave order.
+SLRX_DEV double2 sum4(const double2* s, int stride) {
+  double2 r = s[0];
+  r = dadd(r, s[stride]);
+  r = dadd(r, s[2 * stride]);
+  return dadd(r, s[3 * stride]);
+}
+
+// One column of the reduction.  U: vector entries per thread (n - k <= 256 U);
+// rows: rows of the trailing block per workgroup (blockIdx.x * rows + k + 1 ..).
+template <int U>
+__global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
+  // exchange slots: [wave][item] for the three reductions
+  __shared__ double2 xa[4][3];
+  __shared__ double2 xb[4][3];
+  __shared__ double2 xc[4][kTriRMax];
+  __shared__ double2 coef[kTriRMax][2];  // v_{k-1}(i), w_{k-1}(i) of the workgroup's rows
   const int n = a.n, k = a.k;
   const int b = blockIdx.y;  // problem in a batch
   double2* Aw = a.Aw + (size_t)b * a.strideA;
-  double2* vp = sm;           // v_{k-1}, indices >= k
-  double2* wp = sm + n;       // w_{k-1}
-  double2* col = sm + 2 * n;  // column k of the current matrix, then v_k
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool pending = k > 0;
+  const double2 zero = make_double2(0.0, 0.0);
+  const int row0 = k + 1 + blockIdx.x * rows;
+  const int nrow = min(rows, n - row0);  // >= 1 by the grid size
 
-  // 0. issue every independent global load first: v_{k-1}, p_{k-1} and row k
-  //    (needed at once), then this wave's row of the trailing block (needed last).
-  const int my_row = k + 1 + blockIdx.x * kTriRows + wave;  // one row per wave
-  const bool has_row = my_row < n;
-  double2* row = Aw + (size_t)(has_row ? my_row : 0) * n;
-  const double2 t = pending ? a.tau[(size_t)b * n + (k - 1)] : make_double2(0.0, 0.0);
+  // 0. every independent load first: row k, v_{k-1}, p_{k-1}, the first rows of the block
+  const double2 t = pending ? a.tau[(size_t)b * n + (k - 1)] : zero;
   const double2* rowk = Aw + (size_t)k * n;
   const double2* vprev = a.vbuf[(k + 1) & 1] + (size_t)b * n;  // written by launch k-1
   const double2* pprev = a.pbuf[(k + 1) & 1] + (size_t)b * n;
-  double2 kv[kTriCrit], rv[kTriCrit], pv[kTriCrit];
+  double2 rk[U], vp[U], pp[U];
 #pragma unroll
-  for (int u = 0; u < kTriCrit; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int j = k + tid + kTriNT * u;
+    rk[u] = vp[u] = pp[u] = zero;
     if (j < n) {
-      kv[u] = rowk[j];
+      rk[u] = rowk[j];
       if (pending) {
-        rv[u] = vprev[j];
-        pv[u] = pprev[j];
+        vp[u] = vprev[j];
+        pp[u] = pprev[j];
       }
     }
   }
-  double2 xpre[NU];
+  double2 xr[kTriRB][U];
 #pragma unroll
-  for (int u = 0; u < NU; ++u) {
-    const int j = k + 1 + lane + 64 * u;
-    xpre[u] = (has_row && j < n) ? row[j] : make_double2(0.0, 0.0);
-  }
-  double2 d = make_double2(0.0, 0.0);
-  auto stage = [&](int j, double2 kj, double2 rj, double2 pj) {
-    col[j] = dconj(kj);  // A(j, k) = conj(A(k, j))
-    if (pending) {
-      vp[j] = rj;
-      wp[j] = pj;
-      d = dadd(d, dcmul(pj, rj));
-      if (j == k) {
-        at_k[0] = pj;
-        at_k[1] = rj;
-      }
+  for (int r = 0; r < kTriRB; ++r)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = k + tid + kTriNT * u;
+      xr[r][u] = (r < nrow && j > k && j < n) ? Aw[(size_t)(row0 + r) * n + j] : zero;
     }
-  };
-#pragma unroll
-  for (int u = 0; u < kTriCrit; ++u) {
-    const int j = k + tid + kTriNT * u;
-    if (j < n) stage(j, kv[u], rv[u], pv[u]);
-  }
-  for (int j = k + tid + kTriNT * kTriCrit; j < n; j += kTriNT)  // n - k > kTriCrit * kTriNT only
-    stage(j, rowk[j], pending ? vprev[j] : make_double2(0.0, 0.0), pending ? pprev[j] : make_double2(0.0, 0.0));
 
-  // 1. pending reflector k-1: w = tau p + c v, c = -|tau|^2/2 (p^H v); apply it to
-  //    column k: A(j,k) - v_j conj(w_k) - w_j conj(v_k); partial norm for step 3.
+  // 1. d = p^H v of the pending reflector; p_{k-1}(k), v_{k-1}(k) ride along
+  double2 d = zero;
+#pragma unroll
+  for (int u = 0; u < U; ++u) d = dadd(d, dcmul(pp[u], vp[u]));
+  d = wave_total2(d);
+  if (lane == 0) xa[wave][0] = d;
+  if (tid == 0) {
+    xa[0][1] = pp[0];  // entry j = k
+    xa[0][2] = vp[0];
+  }
+  __syncthreads();
+  d = sum4(&xa[0][0], 3);
+  const double2 pk = xa[0][1], vk = xa[0][2];
+
+  // 2. w = tau p + c d v, c = -|tau|^2 / 2; column k with the pending update; its norm below k+1
+  const double c = -0.5 * (t.x * t.x + t.y * t.y);
+  const double2 cd = dscale(d, c);
+  const double2 wk = dadd(dmul(t, pk), dmul(cd, vk));
+  double2 w[U], col[U];
   double xn = 0.0;
-  if (pending) {
-    d = block_sum2(d, red);  // also orders at_k and the LDS vectors
-    const double c = -0.5 * (t.x * t.x + t.y * t.y);
-    const double2 cd = dscale(d, c);
-    const double2 vk0 = at_k[1];
-    const double2 wk0 = dadd(dmul(t, at_k[0]), dmul(cd, vk0));
-    for (int j = k + tid; j < n; j += kTriNT) {
-      const double2 w = dadd(dmul(t, wp[j]), dmul(cd, vp[j]));
-      wp[j] = w;
-      const double2 x = dsub(col[j], dadd(dmul(vp[j], dconj(wk0)), dmul(w, dconj(vk0))));
-      col[j] = x;
-      if (j >= k + 2) xn += x.x * x.x + x.y * x.y;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = k + tid + kTriNT * u;
+    w[u] = dadd(dmul(t, pp[u]), dmul(cd, vp[u]));
+    double2 x = dconj(rk[u]);  // A(j, k) = conj(A(k, j))
+    if (pending) x = dsub(x, dadd(dmul(vp[u], dconj(wk)), dmul(w[u], dconj(vk))));
+    col[u] = x;
+    if (j >= k + 2 && j < n) xn += x.x * x.x + x.y * x.y;
+  }
+  xn = wave_total(xn);
+  if (lane == 0) xb[wave][0] = make_double2(xn, 0.0);
+  if (tid == 1) xb[0][1] = col[0];  // alpha = column entry k + 1
+  if (tid == 0) xb[0][2] = col[0];  // diagonal entry k
+  // coefficients of the workgroup's rows i: held by the thread with i = k + t + 256 u
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = k + tid + kTriNT * u;
+    const int r = j - row0;
+    if (r >= 0 && r < nrow) {
+      coef[r][0] = vp[u];
+      coef[r][1] = w[u];
     }
-  } else {
-    __syncthreads();
-    for (int j = k + 2 + tid; j < n; j += kTriNT) xn += col[j].x * col[j].x + col[j].y * col[j].y;
   }
-  const double2 xn2 = block_sum2(make_double2(xn, 0.0), red);  // also orders col / wp
-  if (k == n - 1) {  // last diagonal entry, no reflector left
-    if (blockIdx.x == 0 && tid == 0) a.D[(size_t)b * n + k] = col[k].x;
-    return;
-  }
+  __syncthreads();
+  const double xn2 = sum4(&xb[0][0], 3).x;
+  const double2 alpha = xb[0][1];
+  const double dk = xb[0][2].x;
 
-  // 3. reflector k on x = col[k+1 .. n-1]
-  const double2 alpha = col[k + 1];
+  // 3. reflector k on x = column k rows k+1 .. n-1
   double beta;
   double2 tau, scale;
-  if (xn2.x == 0.0 && alpha.y == 0.0) {
-    tau = make_double2(0.0, 0.0);
+  if (xn2 == 0.0 && alpha.y == 0.0) {
+    tau = zero;
     beta = alpha.x;
-    scale = make_double2(0.0, 0.0);
+    scale = zero;
   } else {
-    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2.x);
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
     beta = alpha.x >= 0.0 ? -nrm : nrm;
     tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-    // scale = 1 / (alpha - beta)
-    const double2 den = make_double2(alpha.x - beta, alpha.y);
+    const double2 den = make_double2(alpha.x - beta, alpha.y);  // scale = 1 / (alpha - beta)
     const double dd = den.x * den.x + den.y * den.y;
     scale = make_double2(den.x / dd, -den.y / dd);
   }
-  const double dk = col[k].x;
-  __syncthreads();
-  for (int i = k + 1 + tid; i < n; i += kTriNT) col[i] = (i == k + 1) ? make_double2(1.0, 0.0) : dmul(col[i], scale);
-  __syncthreads();
+  double2 v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = k + tid + kTriNT * u;
+    v[u] = j == k + 1 ? make_double2(1.0, 0.0) : (j >= k + 2 && j < n ? dmul(col[u], scale) : zero);
+  }
   if (blockIdx.x == 0) {
     double2* vout = a.vbuf[k & 1] + (size_t)b * n;
     double2* Vst = a.Vst + (size_t)b * a.strideA;
-    for (int i = k + 1 + tid; i < n; i += kTriNT) {
-      vout[i] = col[i];
-      Vst[(size_t)k * n + i] = (i == k + 1) ? make_double2(beta, 0.0) : col[i];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = k + tid + kTriNT * u;
+      if (j > k && j < n) {
+        vout[j] = v[u];
+        Vst[(size_t)k * n + j] = j == k + 1 ? make_double2(beta, 0.0) : v[u];
+      }
     }
     if (tid == 0) {
       a.D[(size_t)b * n + k] = dk;
@@ -178,49 +204,45 @@ __global__ __launch_bounds__(kTriNT) void k_tri_step(TriArgs a) {
     }
   }
 
-  // 4. this wave's row of the trailing block: pending update, then
-  //    p_i = sum_j A_ij v_j (the first elements are already in registers)
-  if (!has_row) return;
+  // 4. the workgroup's rows: pending update (written back), p_i = sum_j A_ij v_j,
+  //    each row's partials summed over the wave at once (nrow is uniform)
   double2* pout = a.pbuf[k & 1] + (size_t)b * n;
-  const double2 vpi = pending ? vp[my_row] : make_double2(0.0, 0.0);
-  const double2 wpi = pending ? wp[my_row] : make_double2(0.0, 0.0);
-  double2 acc = make_double2(0.0, 0.0);
+  auto row_work = [&](int r, const double2 (&x)[U]) {
+    const int i = row0 + r;
+    const double2 vi = coef[r][0], wi = coef[r][1];
+    double2 acc = zero;
 #pragma unroll
-  for (int u = 0; u < NU; ++u) {
-    const int j = k + 1 + lane + 64 * u;
-    if (j < n) {
-      double2 x = xpre[u];
-      if (pending) {
-        x = dsub(x, dadd(dmul(vpi, dconj(wp[j])), dmul(wpi, dconj(vp[j]))));
-        row[j] = x;
-      }
-      acc = dadd(acc, dmul(x, col[j]));
-    }
-  }
-  for (int j0 = k + 1 + lane + 64 * NU; j0 < n; j0 += 64 * kTriUnroll) {
-    double2 x[kTriUnroll];
-#pragma unroll
-    for (int u = 0; u < kTriUnroll; ++u) {
-      const int j = j0 + 64 * u;
-      x[u] = j < n ? row[j] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int u = 0; u < kTriUnroll; ++u) {
-      const int j = j0 + 64 * u;
-      if (j < n) {
+    for (int u = 0; u < U; ++u) {
+      const int j = k + tid + kTriNT * u;
+      if (j > k && j < n) {
+        double2 e = x[u];
         if (pending) {
-          x[u] = dsub(x[u], dadd(dmul(vpi, dconj(wp[j])), dmul(wpi, dconj(vp[j]))));
-          row[j] = x[u];
+          e = dsub(e, dadd(dmul(vi, dconj(w[u])), dmul(wi, dconj(vp[u]))));
+          Aw[(size_t)i * n + j] = e;
         }
-        acc = dadd(acc, dmul(x[u], col[j]));
+        acc = dadd(acc, dmul(e, v[u]));
       }
     }
+    acc = wave_total2(acc);
+    if (lane == 0) xc[wave][r] = acc;
+  };
+#pragma unroll
+  for (int r = 0; r < kTriRB; ++r)
+    if (r < nrow) row_work(r, xr[r]);
+  for (int r0 = kTriRB; r0 < nrow; r0 += kTriRB) {  // rows beyond the prefetched ones
+#pragma unroll
+    for (int r = 0; r < kTriRB; ++r)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = k + tid + kTriNT * u;
+        xr[r][u] = (r0 + r < nrow && j > k && j < n) ? Aw[(size_t)(row0 + r0 + r) * n + j] : zero;
+      }
+#pragma unroll
+    for (int r = 0; r < kTriRB; ++r)
+      if (r0 + r < nrow) row_work(r0 + r, xr[r]);
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    acc.x += __shfl_down(acc.x, off, 64);
-    acc.y += __shfl_down(acc.y, off, 64);
-  }
-  if (lane == 0) pout[my_row] = acc;
+  __syncthreads();
+  if (tid < nrow) pout[row0 + tid] = sum4(&xc[0][tid], kTriRMax);
 }
 
 // The last kTriTail columns in one launch: the trailing block (rows and columns
@@ -373,26 +395,16 @@ int tri_max_n() { return 3000; }
 
 static size_t tail_lds(int L) { return (size_t)(2 * L * L + 3 * L) * sizeof(double2) + 2 * (size_t)L * sizeof(double); }
 
-template <int NU>
-static hipError_t tri_attr() {
-  return hipFuncSetAttribute((const void*)k_tri_step<NU>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)((size_t)3 * tri_max_n() * sizeof(double2)));
+template <int U>
+static void launch_col(const TriArgs& a, int nbatch, int rows, hipStream_t s) {
+  const int nr = a.n - a.k - 1;
+  const dim3 grid((nr + rows - 1) / rows, nbatch);
+  k_tri_col<U><<<grid, kTriNT, 0, s>>>(a, rows);
 }
 
 hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s) {
   const int n = base.n;
-  const size_t lds = (size_t)3 * n * sizeof(double2);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = tri_attr<1>();
-    if (e == hipSuccess) e = tri_attr<2>();
-    if (e == hipSuccess) e = tri_attr<4>();
-    if (e == hipSuccess) e = tri_attr<8>();
-    if (e == hipSuccess) e = tri_attr<12>();
-    if (e == hipSuccess) e = tri_attr<16>();
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  if (n > tri_max_n()) return hipErrorInvalidValue;
   static bool tail_attr = false;
   if (!tail_attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_tri_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -404,16 +416,17 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s) {
   TriArgs a = base;
   for (int k = 0; k < k0; ++k) {
     a.k = k;
-    const int rows = n - k - 1;
-    const int gx = rows > 0 ? (rows + kTriRows - 1) / kTriRows : 1;
-    const dim3 grid(gx, nbatch);
-    const int chunks = (rows + 63) / 64;  // row elements per lane
-    if (chunks <= 1) k_tri_step<1><<<grid, kTriNT, lds, s>>>(a);
-    else if (chunks <= 2) k_tri_step<2><<<grid, kTriNT, lds, s>>>(a);
-    else if (chunks <= 4) k_tri_step<4><<<grid, kTriNT, lds, s>>>(a);
-    else if (chunks <= 8) k_tri_step<8><<<grid, kTriNT, lds, s>>>(a);
-    else if (chunks <= 12) k_tri_step<12><<<grid, kTriNT, lds, s>>>(a);
-    else k_tri_step<16><<<grid, kTriNT, lds, s>>>(a);
+    const int nr = n - k - 1;                        // trailing rows
+    const int rows = (nr + kTriNT - 1) / kTriNT;      // at most 256 workgroups per problem
+    const int u = (n - k + kTriNT - 1) / kTriNT;      // vector entries per thread
+    if (u <= 1) launch_col<1>(a, nbatch, rows, s);
+    else if (u <= 2) launch_col<2>(a, nbatch, rows, s);
+    else if (u <= 3) launch_col<3>(a, nbatch, rows, s);
+    else if (u <= 4) launch_col<4>(a, nbatch, rows, s);
+    else if (u <= 5) launch_col<5>(a, nbatch, rows, s);
+    else if (u <= 6) launch_col<6>(a, nbatch, rows, s);
+    else if (u <= 8) launch_col<8>(a, nbatch, rows, s);
+    else launch_col<12>(a, nbatch, rows, s);
   }
   const int L = n - k0;
   k_tri_tail<<<dim3(1, nbatch), kTailNT, tail_lds(L), s>>>(a, k0);

@@ -219,9 +219,10 @@ static void complete_request(slrx_server* s, Req* r, slrx_status st) {
   r->state = 2;
   release_budget(s, r);
   if (!r->owned) s->busy.erase(r->plan);
-  if (r->owned && r->plan) {
-    s->pool.emplace(key_of(r->dims), std::make_pair(r->plan, r->bytes));
-    s->pooled += r->bytes;
+  if (r->owned && r->plan) {  // the plan alone: its engine share stays with the engine's buffers
+    const size_t plan_bytes = r->bytes - r->eig;
+    s->pool.emplace(key_of(r->dims), std::make_pair(r->plan, plan_bytes));
+    s->pooled += plan_bytes;
     r->plan = nullptr;
   }
   s->cv_done.notify_all();
