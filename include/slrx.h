@@ -304,6 +304,27 @@ slrx_status slrx_fetch_images(slrx_server* srv, uint64_t ticket, void* out_host)
 /* Forget a done request, freeing whatever it still holds. */
 slrx_status slrx_release(slrx_server* srv, uint64_t ticket);
 
+/* --- the normal operator without allocation ------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
+ * out = S o v + lambda F G F^-1 v, the operator of slrx_step_apply, without a
+ * plan: dims gives P, Q, T and M (N1, N2 are not used); S uint8 [T][P][Q], E
+ * the masks complex64 [W][P][Q] (W = M(M+1)/2, pairs m <= m' in row-major
+ * upper-triangle order), v and out complex64 [T][P][Q] k-space; every pointer
+ * is device memory, read and written on hip_stream (NULL: the default stream)
+ * in stream order; the call returns once the work is enqueued.  flags: 0 or
+ * SLRX_FLAG_GIRAF.  Its scratch (the transposed volume and masks, twiddles,
+ * partial sums) is one device array inside the library, held by each GPU it
+ * runs on until the process ends: 8 (T P Q + W P Q) bytes (each rounded up to
+ * 256) must not exceed slrx_apply_noalloc_limit() = 24 MiB, else SLRX_EINVAL.
+ * The call makes no device allocation.  Calls on one GPU share that array, so
+ * calls that overlap on one GPU (different streams, different threads) race;
+ * nothing in it has to start at zero.  Same errors as slrx_validate for the
+ * sizes, SLRX_EINVAL for NULL pointers or bad flags. */
+size_t slrx_apply_noalloc_limit(void);
+slrx_status slrx_apply_noalloc(const slrx_dims* dims, double lambda, uint32_t flags, const uint8_t* S,
+                               const void* E, const void* v, void* out, void* hip_stream);
+
 const char* slrx_status_str(slrx_status s);
 /* Message of the last failed call on `plan`, or of the calling thread's last
  * failed call when plan is NULL ("" if none).  Valid until the next call. */

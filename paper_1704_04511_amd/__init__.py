@@ -22,7 +22,7 @@ import torch  # noqa: F401
 
 __all__ = [
     "Dims", "Params", "Stats", "RequestInfo", "Plan", "Server", "SlrxError", "lib", "library_path",
-    "footprint", "validate", "default_params", "run_batch", "exported_symbols",
+    "footprint", "validate", "default_params", "run_batch", "exported_symbols", "apply_noalloc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -127,6 +127,8 @@ _SIGS = {
     "slrx_wait_for": (_I, [_P, ctypes.c_uint64, ctypes.c_double]),
     "slrx_cancel": (_I, [_P, ctypes.c_uint64]),
     "slrx_server_set_queue_timeout": (_I, [_P, ctypes.c_double]),
+    "slrx_apply_noalloc_limit": (ctypes.c_size_t, []),
+    "slrx_apply_noalloc": (_I, [ctypes.POINTER(Dims), ctypes.c_double, ctypes.c_uint32, _P, _P, _P, _P, _P]),
     "slrx_status_str": (ctypes.c_char_p, [_I]),
     "slrx_last_error": (ctypes.c_char_p, [_P]),
 }
@@ -388,6 +390,23 @@ class Plan:
         d = self.dims
         Ep, _, Ek = _ptr(E, np.complex64, (self.W, d.P, d.Q))
         self._c(lib().slrx_step_cg(self._h, Ep, int(n_cg)))
+
+
+def apply_noalloc(dims: Dims, lam: float, S, E, v, out, stream=None, giraf: bool = False):
+    """``slrx_apply_noalloc``: out = S o v + lam F G F^-1 v on device tensors (S uint8,
+    E complex64 [W][P][Q], v and out complex64 [T][P][Q]), without a plan or any
+    device allocation; enqueued on ``stream`` (a hipStream_t handle, None: default)."""
+    shape = (dims.T, dims.P, dims.Q)
+    W = dims.M * (dims.M + 1) // 2
+    ptrs = []
+    for a, dt, shp in ((S, np.uint8, shape), (E, np.complex64, (W, dims.P, dims.Q)), (v, np.complex64, shape),
+                       (out, np.complex64, shape)):
+        if not (isinstance(a, torch.Tensor) and a.is_cuda):
+            raise TypeError("slrx_apply_noalloc takes device tensors")
+        p, _, _ = _ptr(a, dt, shp)
+        ptrs.append(p)
+    st = None if stream is None else ctypes.c_void_p(int(stream))
+    _check(lib().slrx_apply_noalloc(ctypes.byref(dims), float(lam), SLRX_FLAG_GIRAF if giraf else 0, *ptrs, st))
 
 
 def run_batch(plans, stream=None, sync=True):
