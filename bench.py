@@ -41,16 +41,17 @@ def algorithmic_bytes(kind: str, T: int, P: int, Q: int, M: int, N1: int, N2: in
     c = 8
     if kind == "rows":     # read r, p_old; write p and the row-transformed volume t
         return 4 * V * c
-    if kind == "cols":     # read t and the masks E; write t (coils: read rho and the coil
-        if nc:             # combination d instead of t)
-            return 3 * V * c + W * P * Q * c
+    if kind == "cols":     # read t (coils: the image rho) and the masks E; write t
         return 2 * V * c + W * P * Q * c
-    if kind == "fin":      # read t, p, S (1 B); write q (coils: no S)
-        return 3 * V * c + (0 if nc else V)
-    if kind == "coil":     # coil columns: read t and the maps, write rho and nc volumes; coil
-        return ((2 + nc) * V * c + nc * P * Q * c    # rows: nc volumes both ways + S; combine: read
-                + 2 * nc * V * c + V                 # nc volumes and the maps, write d
-                + (nc + 1) * V * c + nc * P * Q * c)
+    if kind == "fin":      # read t, p, S (1 B); write q (coils: no S; the complex128 group
+        if nc:             # sums of the coil combination instead)
+            return 3 * V * c + min(nc, 4) * V * 16
+        return 3 * V * c + V
+    if kind == "coil":     # columns: read t and the maps, write rho and nc volumes (complex64);
+        g = min(nc, 4)     # rows: read the nc volumes and S, write them in complex128;
+        return ((2 + nc) * V * c + nc * P * Q * c     # combine: read the complex128 volumes and
+                + nc * V * c + V + nc * V * 16        # the maps, write the group sums (complex128)
+                + nc * V * 16 + nc * P * Q * c + g * V * 16)
     if kind == "update":   # read x, p, r, q; write x, r
         return 6 * V * c
     if kind == "gram":     # images (read x, write/read t, write img), read img, write R

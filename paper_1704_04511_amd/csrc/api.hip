@@ -439,16 +439,21 @@ extern "C" slrx_status slrx_set_coils(slrx_plan* pl, int32_t ncoils, const void*
     if (pl->coil_mem) HIPCHK(hipFree(pl->coil_mem));
     pl->coil_mem = nullptr;
     pl->ncoils_cap = 0;
-    pl->Ct = pl->Bc = pl->Yc = pl->rho = pl->dco = nullptr;
+    pl->Ct = pl->Bc = pl->Yc = pl->rho = nullptr;
+    pl->Yc64 = pl->dco = nullptr;
     if (ncoils > 0) {
-      const size_t elems = (size_t)ncoils * pq + 2 * (size_t)ncoils * V + (1 + (size_t)coil_groups(ncoils)) * V;
-      HIPCHK(hipMalloc(&pl->coil_mem, elems * sizeof(float2)));
+      // complex64 units: maps, coil k-space, forward-half volumes, image; then
+      // complex128: adjoint-half volumes, group sums
+      const size_t n32 = (size_t)ncoils * pq + 2 * (size_t)ncoils * V + V;
+      const size_t n64 = (size_t)ncoils * V + (size_t)coil_groups(ncoils) * V;
+      HIPCHK(hipMalloc(&pl->coil_mem, n32 * sizeof(float2) + n64 * sizeof(double2)));
       pl->ncoils_cap = ncoils;
       pl->Ct = (float2*)pl->coil_mem;
       pl->Bc = pl->Ct + (size_t)ncoils * pq;
       pl->Yc = pl->Bc + (size_t)ncoils * V;
       pl->rho = pl->Yc + (size_t)ncoils * V;
-      pl->dco = pl->rho + V;
+      pl->Yc64 = (double2*)(pl->rho + V);
+      pl->dco = pl->Yc64 + (size_t)ncoils * V;
     }
   }
   pl->ncoils = 0;

@@ -18,22 +18,75 @@
 #pragma once
 #include "common.h"
 
+// ------------------------------------------------ complex64 / complex128
+// The passes below are written once for a complex type C (float2 or double2);
+// the complex64 instances are the operator's transforms, the complex128 ones
+// the adjoint half of the multichannel data term.
+SLRX_DEV double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+SLRX_DEV double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+SLRX_DEV double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+SLRX_DEV double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+SLRX_DEV double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+template <int SIGN> SLRX_DEV double2 cmul_i(double2 a) {
+  return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+template <class C> struct Cx;
+template <> struct Cx<float2> {
+  using S = float;
+  static SLRX_DEV float2 make(float x, float y) { return make_float2(x, y); }
+  // sqrt(3)/2; cos, sin (2 pi/5), cos, sin (4 pi/5); cos/sin(pi j / 8), j = 0..7
+  static constexpr float h3 = 0.86602540378443865f;
+  static constexpr float c51 = 0.30901699437494742f, c52 = -0.80901699437494742f;
+  static constexpr float s51 = 0.95105651629515357f, s52 = 0.58778525229247313f;
+  static constexpr float r2 = 0.70710678118654752f;
+  static SLRX_DEV float cs16(int j) {
+    constexpr float t[8] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f,
+                            0.0f, -0.38268343236508978f, -0.70710678118654752f, -0.92387953251128674f};
+    return t[j];
+  }
+  static SLRX_DEV float sn16(int j) {
+    constexpr float t[8] = {0.0f, 0.38268343236508978f, 0.70710678118654752f, 0.92387953251128674f,
+                            1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f};
+    return t[j];
+  }
+};
+template <> struct Cx<double2> {
+  using S = double;
+  static SLRX_DEV double2 make(double x, double y) { return make_double2(x, y); }
+  static constexpr double h3 = 0.86602540378443864676;
+  static constexpr double c51 = 0.30901699437494742410, c52 = -0.80901699437494742410;
+  static constexpr double s51 = 0.95105651629515357212, s52 = 0.58778525229247312917;
+  static constexpr double r2 = 0.70710678118654752440;
+  static SLRX_DEV double cs16(int j) {
+    constexpr double t[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                             0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
+    return t[j];
+  }
+  static SLRX_DEV double sn16(int j) {
+    constexpr double t[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                             1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+    return t[j];
+  }
+};
+
 // ------------------------------------------------------------ small DFTs
 // X[k] = sum_j x[j] e^{SIGN 2 pi i j k / R}, in place on a register array.
 template <int R, int SIGN> struct Dft;
 
 template <int SIGN> struct Dft<2, SIGN> {
-  static SLRX_DEV void run(float2* v) {
-    float2 a = v[0], b = v[1];
+  template <class C> static SLRX_DEV void run(C* v) {
+    C a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
   }
 };
 
 template <int SIGN> struct Dft<4, SIGN> {
-  static SLRX_DEV void run(float2* v) {
-    float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
-    float2 a2 = cadd(v[1], v[3]), a3 = cmul_i<SIGN>(csub(v[1], v[3]));
+  template <class C> static SLRX_DEV void run(C* v) {
+    C a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    C a2 = cadd(v[1], v[3]), a3 = cmul_i<SIGN>(csub(v[1], v[3]));
     v[0] = cadd(a0, a2);
     v[2] = csub(a0, a2);
     v[1] = cadd(a1, a3);
@@ -42,11 +95,12 @@ template <int SIGN> struct Dft<4, SIGN> {
 };
 
 template <int SIGN> struct Dft<3, SIGN> {
-  static SLRX_DEV void run(float2* v) {
-    const float h = 0.86602540378443865f;  // sqrt(3)/2
-    float2 t = cadd(v[1], v[2]);
-    float2 d = cmul_i<SIGN>(cscale(csub(v[1], v[2]), h));
-    float2 m = csub(v[0], cscale(t, 0.5f));
+  template <class C> static SLRX_DEV void run(C* v) {
+    using K = Cx<C>;
+    using S = typename K::S;
+    C t = cadd(v[1], v[2]);
+    C d = cmul_i<SIGN>(cscale(csub(v[1], v[2]), K::h3));
+    C m = csub(v[0], cscale(t, (S)0.5));
     v[0] = cadd(v[0], t);
     v[1] = cadd(m, d);
     v[2] = csub(m, d);
@@ -54,18 +108,16 @@ template <int SIGN> struct Dft<3, SIGN> {
 };
 
 template <int SIGN> struct Dft<5, SIGN> {
-  static SLRX_DEV void run(float2* v) {
-    const float c1 = 0.30901699437494742f;   // cos(2 pi/5)
-    const float c2 = -0.80901699437494742f;  // cos(4 pi/5)
-    const float s1 = 0.95105651629515357f;   // sin(2 pi/5)
-    const float s2 = 0.58778525229247313f;   // sin(4 pi/5)
-    float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-    float2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
-    float2 x0 = v[0];
-    float2 a1 = make_float2(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
-    float2 a2 = make_float2(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
-    float2 b1 = cmul_i<SIGN>(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
-    float2 b2 = cmul_i<SIGN>(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+  template <class C> static SLRX_DEV void run(C* v) {
+    using K = Cx<C>;
+    const auto c1 = K::c51, c2 = K::c52, s1 = K::s51, s2 = K::s52;
+    C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    C d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+    C x0 = v[0];
+    C a1 = K::make(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
+    C a2 = K::make(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
+    C b1 = cmul_i<SIGN>(K::make(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+    C b2 = cmul_i<SIGN>(K::make(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
     v[0] = cadd(x0, cadd(t1, t2));
     v[1] = cadd(a1, b1);
     v[4] = csub(a1, b1);
@@ -77,18 +129,19 @@ template <int SIGN> struct Dft<5, SIGN> {
 // Radix 8 and 16 by one decimation-in-frequency split into two halves:
 // X[2k] = DFT_{R/2}(x_j + x_{j+R/2}), X[2k+1] = DFT_{R/2}((x_j - x_{j+R/2}) w^j).
 template <int SIGN> struct Dft<8, SIGN> {
-  static SLRX_DEV void run(float2* v) {
-    const float c = 0.70710678118654752f;
-    float2 a[4], b[4];
+  template <class C> static SLRX_DEV void run(C* v) {
+    using K = Cx<C>;
+    const auto c = K::r2;
+    C a[4], b[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       a[j] = cadd(v[j], v[j + 4]);
       b[j] = csub(v[j], v[j + 4]);
     }
     // w8^j = e^{SIGN i pi j / 4}
-    b[1] = cmul(b[1], make_float2(c, SIGN * c));
+    b[1] = cmul(b[1], K::make(c, SIGN * c));
     b[2] = cmul_i<SIGN>(b[2]);
-    b[3] = cmul(b[3], make_float2(-c, SIGN * c));
+    b[3] = cmul(b[3], K::make(-c, SIGN * c));
     Dft<4, SIGN>::run(a);
     Dft<4, SIGN>::run(b);
 #pragma unroll
@@ -100,18 +153,14 @@ template <int SIGN> struct Dft<8, SIGN> {
 };
 
 template <int SIGN> struct Dft<16, SIGN> {
-  static SLRX_DEV void run(float2* v) {
-    // cos/sin(pi j / 8), j = 0..7
-    const float cs[8] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f,
-                         0.0f, -0.38268343236508978f, -0.70710678118654752f, -0.92387953251128674f};
-    const float sn[8] = {0.0f, 0.38268343236508978f, 0.70710678118654752f, 0.92387953251128674f,
-                         1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f};
-    float2 a[8], b[8];
+  template <class C> static SLRX_DEV void run(C* v) {
+    using K = Cx<C>;
+    C a[8], b[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       a[j] = cadd(v[j], v[j + 8]);
-      float2 d = csub(v[j], v[j + 8]);
-      b[j] = (j == 0) ? d : (j == 4) ? cmul_i<SIGN>(d) : cmul(d, make_float2(cs[j], SIGN * sn[j]));
+      C d = csub(v[j], v[j + 8]);
+      b[j] = (j == 0) ? d : (j == 4) ? cmul_i<SIGN>(d) : cmul(d, K::make(K::cs16(j), SIGN * K::sn16(j)));
     }
     Dft<8, SIGN>::run(a);
     Dft<8, SIGN>::run(b);
@@ -153,10 +202,10 @@ template <int N> constexpr int fft_tw_size() {
 // Fill the per-pass tables from tw[t] = e^{-2 pi i t / N}: entry OFF + r NS + k
 // of the pass (NS, R) is w^{r k} with w = e^{-2 pi i / (NS R)}.
 template <int N, int NT, int OFF, int NS, int... Rs> struct TwFill {
-  static SLRX_DEV void run(float2*, const float2*) {}
+  template <class C> static SLRX_DEV void run(C*, const C*) {}
 };
 template <int N, int NT, int OFF, int NS, int R, int... Rest> struct TwFill<N, NT, OFF, NS, R, Rest...> {
-  static SLRX_DEV void run(float2* twt, const float2* tw) {
+  template <class C> static SLRX_DEV void run(C* twt, const C* tw) {
     if (NS > 1)
       for (int i = threadIdx.x; i < NS * R; i += NT) {
         const int r = i / NS, k = i % NS;
@@ -165,24 +214,24 @@ template <int N, int NT, int OFF, int NS, int R, int... Rest> struct TwFill<N, N
     TwFill<N, NT, OFF + (NS > 1 ? NS * R : 0), NS * R, Rest...>::run(twt, tw);
   }
 };
-template <int N, int NT, int... Rs> SLRX_DEV void tw_fill_of(float2* twt, const float2* tw, Radices<Rs...>) {
+template <int N, int NT, class C, int... Rs> SLRX_DEV void tw_fill_of(C* twt, const C* tw, Radices<Rs...>) {
   TwFill<N, NT, 0, 1, Rs...>::run(twt, tw);
 }
 // Called by all NT threads; the tables are valid after the next barrier.
-template <int N, int NT> SLRX_DEV void fft_twiddles(float2* twt, const float2* tw) {
+template <int N, int NT, class C> SLRX_DEV void fft_twiddles(C* twt, const C* tw) {
   tw_fill_of<N, NT>(twt, tw, typename FftPlan<N>::L{});
 }
 
 // One radix-R pass over nb <= MAXB transforms (transform index slowest across
 // threads, butterfly index fastest).
-template <int N, int R, int NS, int OFF, int SIGN, int MAXB, int NT>
-SLRX_DEV void fft_pass(float2* lds, const float2* twt, int nb) {
+template <int N, int R, int NS, int OFF, int SIGN, int MAXB, int NT, class C>
+SLRX_DEV void fft_pass(C* lds, const C* twt, int nb) {
   constexpr int NBF = N / R;                 // butterflies per transform
   constexpr int MAXTOT = MAXB * NBF;
   constexpr int PER = (MAXTOT + NT - 1) / NT;
   constexpr int BS = fft_stride(N);
   const int tot = nb * NBF;
-  float2 v[PER][R];
+  C v[PER][R];
   int base[PER], jj[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
@@ -205,7 +254,7 @@ SLRX_DEV void fft_pass(float2* lds, const float2* twt, int nb) {
       if (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = twt[OFF + r * NS + k];
+          C w = twt[OFF + r * NS + k];
           if (SIGN > 0) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
         }
@@ -219,24 +268,43 @@ SLRX_DEV void fft_pass(float2* lds, const float2* twt, int nb) {
   __syncthreads();
 }
 
-template <int N, int SIGN, int MAXB, int NT, int NS, int OFF, int R, int... Rest>
-SLRX_DEV void fft_passes(float2* lds, const float2* twt, int nb) {
+template <int N, int SIGN, int MAXB, int NT, int NS, int OFF, class C, int R, int... Rest>
+SLRX_DEV void fft_passes(C* lds, const C* twt, int nb) {
   fft_pass<N, R, NS, OFF, SIGN, MAXB, NT>(lds, twt, nb);
   if constexpr (sizeof...(Rest) > 0)
-    fft_passes<N, SIGN, MAXB, NT, NS * R, OFF + (NS > 1 ? NS * R : 0), Rest...>(lds, twt, nb);
+    fft_passes<N, SIGN, MAXB, NT, NS * R, OFF + (NS > 1 ? NS * R : 0), C, Rest...>(lds, twt, nb);
 }
 
-template <int N, int SIGN, int MAXB, int NT, int... Rs>
-SLRX_DEV void fft_run(float2* lds, const float2* twt, int nb, Radices<Rs...>) {
-  fft_passes<N, SIGN, MAXB, NT, 1, 0, Rs...>(lds, twt, nb);
+template <int N, int SIGN, int MAXB, int NT, class C, int... Rs>
+SLRX_DEV void fft_run(C* lds, const C* twt, int nb, Radices<Rs...>) {
+  fft_passes<N, SIGN, MAXB, NT, 1, 0, C, Rs...>(lds, twt, nb);
 }
 
 // Unnormalised length-N DFTs (sign SIGN) of nb <= MAXB transforms held in LDS
 // in the padded layout; twt holds the tables of fft_twiddles.  Must be called
 // by all NT threads.
-template <int N, int SIGN, int MAXB, int NT>
-SLRX_DEV void fft_lds(float2* lds, const float2* twt, int nb) {
+template <int N, int SIGN, int MAXB, int NT, class C>
+SLRX_DEV void fft_lds(C* lds, const C* twt, int nb) {
   fft_run<N, SIGN, MAXB, NT>(lds, twt, nb, typename FftPlan<N>::L{});
+}
+
+// Rows r0 .. r0+RB-1 of the frame at offset fo, each the sum of `groups`
+// planes of the transposed layout (plane g at g * gstride, entry (row r,
+// column c) at c P + r), added in plane order, into LDS rows, then their
+// forward row DFTs of length N.  Called by all NT threads; twt must have been
+// filled before the call (the first barrier here orders it).
+template <int N, int MAXB, int NT, class C>
+SLRX_DEV void rows_sum_fwd(C* lds, const C* twt, const C* d, int groups, long gstride, long fo, int P, int r0,
+                           int RB) {
+  constexpr int BS = fft_stride(N);
+  for (int e = threadIdx.x; e < RB * N; e += NT) {  // consecutive threads walk a column
+    const long src = fo + (long)(e / RB) * P + r0 + e % RB;
+    C v = d[src];
+    for (int g = 1; g < groups; ++g) v = cadd(v, d[(long)g * gstride + src]);
+    lds[(e % RB) * BS + fft_pidx(e / RB)] = v;
+  }
+  __syncthreads();
+  fft_lds<N, -1, MAXB, NT>(lds, twt, RB);
 }
 
 // Host dispatch of a launch template over the supported transform lengths.

@@ -13,9 +13,9 @@
 //               frame of its columns in LDS;
 //   3. rows:    forward row DFT back to row-major, plus S o v and the partial
 //               dot product <v, A v> (or r = b - A x for the initial residual).
-// With coil maps (k_coil.hip) the column pass takes the image and the coil
-// combination from the coil passes instead of inverting the columns itself,
-// and pass 3 omits S o v.  With the GIRAF option G is circulant along the
+// With coil maps (k_coil.hip) the column pass takes the image from the coil
+// passes instead of inverting the columns itself, and pass 3 adds the data
+// term A^H A v (its complex128 last row transform) in place of S o v.  With the GIRAF option G is circulant along the
 // frames.  Plain unitary 2-D transforms (images for the Gram matrix, outputs)
 // reuse pass 1 and a column pass that writes row-major.
 #include "common.h"
@@ -311,15 +311,6 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
 #pragma unroll
     for (int m = 0; m < M - 1; ++m) lds[(T - 1 - m) * per_t + pl] = cscale(acc[m + 1], sc);
   }
-  if (coil) {  // multichannel data term: the coil combination of k_coil_combine
-    __syncthreads();  // the windowed sum writes every frame of a pixel from one thread
-    if (has_pix)
-      for (int t = h; t < T; t += 2) {
-        float2 s = lds[t * per_t + pl];
-        for (int g = 0; g < a.dparts; ++g) s = cadd(s, a.d[(long)g * a.dstride + (long)t * fs + po]);
-        lds[t * per_t + pl] = s;
-      }
-  }
   __syncthreads();
   fft_lds<N, -1, MAXB, kPenNT>(lds, twt, T * CB);
   if (has_pix)
@@ -354,12 +345,16 @@ __global__ __launch_bounds__(kNT) void k_cols_plain(ColArgs a) {
 // ----------------------------------------------- pass 3: rows + combine + dot
 // Forward row DFT of RB rows of frame t read from the transposed layout, then
 //   init: r = b - (S o x + pen), partial <r, r>;   else: q = S o p + pen, partial <p, q>.
-template <int N>
+// COIL (multichannel data term): no S o x; instead the complex128 forward row
+// DFT of the coil combination's group sums is added to pen before rounding.
+template <int N, bool COIL>
 __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
   constexpr int RBMAX = kRowB;
   constexpr int BS = fft_stride(N);
   __shared__ float2 lds[RBMAX * BS];
   __shared__ float2 twt[fft_tw_size<N>()];
+  __shared__ double2 lds64[COIL ? RBMAX * BS : 1];
+  __shared__ double2 twt64[COIL ? fft_tw_size<N>() : 1];
   __shared__ double red[kNT / 64];
   const int P = a.P, Q = a.Q;
   const int RB = row_block(P);
@@ -399,13 +394,28 @@ __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
       yv[u] = a.init ? a.y[g0 + e] : make_float2(0.f, 0.f);
     }
   }
+  if constexpr (COIL) fft_twiddles<N, kNT>(twt64, a.tw64);
   __syncthreads();
   fft_lds<N, -1, RBMAX, kNT>(lds, twt, RB);
+  if constexpr (COIL) rows_sum_fwd<N, RBMAX, kNT>(lds64, twt64, a.d64, a.dparts, a.dstride, fo, P, r0, RB);
   double dot = 0.0;
   auto combine = [&](int e, float2 v, uint8_t sm, float2 bv) {
     const long g = g0 + e;
     const float2 pen = lds[(e / N) * BS + fft_pidx(e % N)];
-    const float2 av = (sm && !a.coil) ? make_float2(v.x + pen.x, v.y + pen.y) : pen;
+    if constexpr (COIL) {  // data term + penalty in complex128, rounded once
+      const double2 av = cadd(f2d(pen), lds64[(e / N) * BS + fft_pidx(e % N)]);
+      if (a.init) {
+        const float2 rv = make_float2((float)((double)bv.x - av.x), (float)((double)bv.y - av.y));
+        a.out[g] = rv;
+        dot += (double)rv.x * rv.x + (double)rv.y * rv.y;
+      } else {
+        const float2 q = make_float2((float)av.x, (float)av.y);
+        a.out[g] = q;
+        dot += (double)v.x * q.x + (double)v.y * q.y;
+      }
+      return;
+    }
+    const float2 av = sm ? make_float2(v.x + pen.x, v.y + pen.y) : pen;
     if (a.init) {
       const float2 rv = make_float2(bv.x - av.x, bv.y - av.y);
       a.out[g] = rv;
@@ -564,7 +574,8 @@ hipError_t launch_pen(const PenArgs& a, hipStream_t s) { SLRX_DISPATCH_N(a.P, pe
 template <int N>
 static hipError_t fin_n(const FinArgs& a, hipStream_t s) {
   dim3 grid(a.P / row_block(a.P), a.T);
-  k_rows_fin<N><<<grid, kNT, 0, s>>>(a);
+  if (a.coil) k_rows_fin<N, true><<<grid, kNT, 0, s>>>(a);
+  else k_rows_fin<N, false><<<grid, kNT, 0, s>>>(a);
   return hipGetLastError();
 }
 hipError_t launch_fin(const FinArgs& a, hipStream_t s) { SLRX_DISPATCH_N(a.Q, fin_n, a, s) }

@@ -53,13 +53,10 @@ struct PenArgs {
   const float2* Et;      // masks, transposed planes [w][c][r]
   float scale;           // lam / (P Q)
   const float2* tw;      // e^{-2 pi i t / P}
-  // multichannel data term (nc > 0): input rho instead of buf, and the coil
-  // combination d (k_coil_combine) added before the forward transform
+  // multichannel data term (nc > 0): input rho (the coil column pass's image)
+  // instead of inverting the columns of buf
   int nc;
   const float2* rho;     // image rho_u, transposed
-  const float2* d;       // per-group coil sums, transposed, group g at g * dstride
-  int dparts;            // number of groups
-  long dstride;
   int circ;              // G circulant along the frames (GIRAF)
 };
 hipError_t launch_pen(const PenArgs& a, hipStream_t s);
@@ -77,7 +74,14 @@ struct FinArgs {
   double* part;          // per-block partials
   int* flag;             // CG stop flag (cleared by block 0 when init)
   const float2* tw;      // e^{-2 pi i t / Q}
-  int coil;              // 1: the data term is already in t (multichannel); no S o v
+  // multichannel data term (coil = 1): no S o v; the complex128 forward row DFT
+  // of the coil combination (d64: dparts group sums, column-transformed,
+  // transposed, group g at g * dstride) is added to the penalty before rounding
+  int coil;
+  const double2* d64;
+  int dparts;
+  long dstride;
+  const double2* tw64;   // e^{-2 pi i t / Q}, complex128
 };
 hipError_t launch_fin(const FinArgs& a, hipStream_t s);
 int fin_blocks(int P, int T);
@@ -95,30 +99,34 @@ struct UpdArgs {
 hipError_t launch_update(const UpdArgs& a, hipStream_t s);
 int update_blocks(long n);
 
-// Multichannel data term (k_coil.hip): coil column pass and coil row pass.
+// Multichannel data term (k_coil.hip): complex64 forward half, complex128
+// adjoint half after the sampling mask.
 struct CoilArgs {
   int P, Q, T, nc;
   const float2* t;       // row pass output (transposed)
   float2* rho;           // out: image rho_u (transposed)
   const float2* Ct;      // coil maps, transposed per coil [j][c][r]
-  float2* Y;             // per-coil volumes (transposed), coil j at j * vstride
+  float2* Y;             // per-coil volumes after the forward half (transposed), coil j at j * vstride
+  double2* Y64;          // per-coil volumes after the inverse row DFT (transposed), complex128
   long vstride;
   const uint8_t* S;      // sampling mask, row-major [t][kr][kc]
   const float2* tw;      // twiddles of the pass's transform length (P: columns, Q: rows)
-  float2* d;             // out of the combine pass: per-group coil sums (transposed), group g at g * vstride
-  float cscale;          // (P Q)^-2
+  const double2* tw64;   // the same in complex128
+  double2* d64;          // combine pass out: per-group sums, column-transformed (transposed), group g at g * vstride
+  double cscale64;       // (P Q)^-2 in the operator, (P Q)^-1 for the right-hand side
   int groups;            // coil groups of the combine pass (coil_groups(nc))
+  const float2* B;       // right-hand side: coil k-space, row-major [j][t][kr][kc], coil j at j * vstride
+  float2* out;           // right-hand side: A^H b, row-major k-space
 };
-// Coils are combined in up to kCoilGroups groups in parallel, their sums added
-// in group order by the column pass.
+// Coils are combined in up to kCoilGroups groups in parallel; the finishing
+// pass adds their sums in group order.
 constexpr int kCoilGroups = 4;
 inline int coil_groups(int nc) { return nc < kCoilGroups ? nc : kCoilGroups; }
 hipError_t launch_coil_cols(const CoilArgs& a, hipStream_t s);
 hipError_t launch_coil_rows(const CoilArgs& a, hipStream_t s);
 hipError_t launch_coil_combine(const CoilArgs& a, hipStream_t s);
-// acc (+)= conj(C) o w, row-major volume, C transposed [c][r] (assign: first coil)
-hipError_t launch_coil_acc(long n, int P, int Q, const float2* Ct, const float2* w, float2* acc, bool assign,
-                           hipStream_t s);
+hipError_t launch_coil_rhs_rows(const CoilArgs& a, hipStream_t s);
+hipError_t launch_coil_rhs_fin(const CoilArgs& a, hipStream_t s);
 
 // Mono-exponential fit per pixel (k_fit.hip); te holds the T echo times.
 struct FitArgs {

@@ -73,10 +73,12 @@ struct slrx_plan {
 
   // multichannel data (slrx_set_coils): one allocation holding the coil maps
   // (transposed per coil), the coil k-space, the per-coil volumes of the
-  // operator, the image rho_u and the coil combination d
+  // operator's forward half (complex64) and adjoint half (complex128), the
+  // image rho_u and the coil combination's group sums (complex128)
   int ncoils = 0, ncoils_cap = 0;
   void* coil_mem = nullptr;
-  float2 *Ct = nullptr, *Bc = nullptr, *Yc = nullptr, *rho = nullptr, *dco = nullptr;
+  float2 *Ct = nullptr, *Bc = nullptr, *Yc = nullptr, *rho = nullptr;
+  double2 *Yc64 = nullptr, *dco = nullptr;
 
   // rocSOLVER handle and workspace of the library eigensolver, a test reference
   // selected by SLRX_FLAG_LIBEIGH; created at its first use

@@ -54,20 +54,31 @@ slrx_status slrx::fft2(slrx_plan* pl, const float2* src, float2* dst, int sign, 
 
 // Right-hand side bm = S o b and the initial iterate x = S o b (zero-filled
 // k-space, Algorithm 1 initialisation) or the user's x0.  With coils the
-// right-hand side is A^H b = F sum_j C_j^* F^-1 (S o b_j) (Sec. II.A), formed
-// one coil at a time (images in img, their combination in q).
+// right-hand side is A^H b = F sum_j C_j^* F^-1 (S o b_j) (Sec. II.A), the
+// adjoint half of the coil data term in complex128 (k_coil.hip), rounded once.
 slrx_status slrx::prepare(slrx_plan* pl) {
   if (!(pl->has_b || pl->ncoils > 0) || !pl->has_S)
     return fail(SLRX_ESTATE, "k-space (or coil data) and mask must be set before running");
   const long V = (long)pl->vol();
   if (pl->ncoils > 0) {
     const slrx_dims& d = pl->d;
-    const long pq = (long)d.P * d.Q;
-    for (int j = 0; j < pl->ncoils; ++j) {
-      STCHK(fft2(pl, pl->Bc + (long)j * V, pl->img, +1, pl->S));
-      HIPCHK(launch_coil_acc(V, d.P, d.Q, pl->Ct + (long)j * pq, pl->img, pl->q, j == 0, pl->stream));
-    }
-    STCHK(fft2(pl, pl->q, pl->bm, -1, nullptr));
+    CoilArgs ca{};
+    ca.P = d.P; ca.Q = d.Q; ca.T = d.T; ca.nc = pl->ncoils;
+    ca.Ct = pl->Ct;
+    ca.Y64 = pl->Yc64;
+    ca.vstride = V;
+    ca.S = pl->S;
+    ca.B = pl->Bc;
+    ca.d64 = pl->dco;
+    ca.groups = coil_groups(pl->ncoils);
+    ca.out = pl->bm;
+    ca.tw64 = pl->twQd;
+    HIPCHK(launch_coil_rhs_rows(ca, pl->stream));
+    ca.tw64 = pl->twPd;
+    ca.cscale64 = 1.0 / ((double)d.P * d.Q);
+    HIPCHK(launch_coil_combine(ca, pl->stream));
+    ca.tw64 = pl->twQd;
+    HIPCHK(launch_coil_rhs_fin(ca, pl->stream));
   } else {
     HIPCHK(launch_mask_data(V, pl->S, pl->b, pl->bm, pl->stream));
   }
@@ -288,8 +299,9 @@ slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma, 
 }
 
 // The coil passes of the multichannel operator on the row pass output t:
-// rho_u, per coil the masked round trip through k-space, and their
-// combination d (added to the penalty by the column pass).
+// rho_u, per coil the masked round trip through k-space (complex128 after the
+// mask), and their combination's group sums, column-transformed (added to the
+// penalty by the finishing pass).
 slrx_status slrx::coil_pass(slrx_plan* pl) {
   const slrx_dims& d = pl->d;
   CoilArgs ca{};
@@ -298,19 +310,31 @@ slrx_status slrx::coil_pass(slrx_plan* pl) {
   ca.rho = pl->rho;
   ca.Ct = pl->Ct;
   ca.Y = pl->Yc;
+  ca.Y64 = pl->Yc64;
   ca.vstride = (long)pl->vol();
   ca.S = pl->S;
   ca.tw = pl->twPf;
   HIPCHK(launch_coil_cols(ca, pl->stream));
   ca.tw = pl->twQf;
+  ca.tw64 = pl->twQd;
   HIPCHK(launch_coil_rows(ca, pl->stream));
   const double pq = (double)d.P * d.Q;
-  ca.tw = pl->twPf;
-  ca.d = pl->dco;
-  ca.cscale = (float)(1.0 / (pq * pq));
+  ca.tw64 = pl->twPd;
+  ca.d64 = pl->dco;
+  ca.cscale64 = 1.0 / (pq * pq);
   ca.groups = coil_groups(pl->ncoils);
   HIPCHK(launch_coil_combine(ca, pl->stream));
   return SLRX_OK;
+}
+
+// The multichannel fields of the finishing pass.
+static void fin_coil(slrx_plan* pl, FinArgs& fa) {
+  fa.coil = pl->ncoils > 0 ? 1 : 0;
+  if (!fa.coil) return;
+  fa.d64 = pl->dco;
+  fa.dparts = coil_groups(pl->ncoils);
+  fa.dstride = (long)pl->vol();
+  fa.tw64 = pl->twQd;
 }
 
 // A v = S o v + lam F G F^-1 v in k-space (init: out = bm - A v); with coils
@@ -339,7 +363,7 @@ slrx_status slrx::apply_op(slrx_plan* pl, const float2* v, float2* out, bool ini
   fa.part = part;
   fa.flag = pl->flag;
   fa.tw = pl->twQf;
-  fa.coil = pl->ncoils > 0 ? 1 : 0;
+  fin_coil(pl, fa);
   HIPCHK(launch_fin(fa, pl->stream));
   return SLRX_OK;
 }
@@ -356,9 +380,6 @@ slrx_status slrx::penalty_pass(slrx_plan* pl) {
   if (pl->ncoils > 0) {
     pa.nc = pl->ncoils;
     pa.rho = pl->rho;
-    pa.d = pl->dco;
-    pa.dparts = coil_groups(pl->ncoils);
-    pa.dstride = (long)pl->vol();
   }
   HIPCHK(launch_pen(pa, pl->stream));
   return SLRX_OK;
@@ -409,7 +430,7 @@ slrx_status slrx::run_cg(slrx_plan* pl, int n_cg, int it) {
     fa.part = pl->partA;
     fa.flag = pl->flag;
     fa.tw = pl->twQf;
-    fa.coil = pl->ncoils > 0 ? 1 : 0;
+    fin_coil(pl, fa);
     {
       KTimer kt(pl, SLRX_K_FIN);
       HIPCHK(launch_fin(fa, pl->stream));
