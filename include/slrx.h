@@ -167,9 +167,10 @@ slrx_status slrx_clear_init(slrx_plan* plan);
  *   C: complex64 [ncoils][P][Q] sensitivities, row-major frames;
  *   b: complex64 [ncoils][T][P][Q] coil k-space, DC at [0][0] (entries off
  *      the mask are ignored).
- * Copies both (host or device memory per mem).  Allocates 8 ((2 ncoils + 1 +
- * min(ncoils, 4)) T P Q + ncoils P Q) bytes of device memory beyond
- * slrx_footprint, released by
+ * Copies both (host or device memory per mem).  Allocates 8 (ncoils P Q +
+ * (2 ncoils + 1) T P Q) + 16 (ncoils + min(ncoils, 4)) T P Q bytes of device
+ * memory beyond slrx_footprint (the adjoint half of the coil data term runs in
+ * complex128), released by
  * slrx_plan_destroy or a later call.  SLRX_EINVAL for ncoils out of range,
  * NULL pointers or a bad mem; SLRX_EBUSY while the plan runs.  Plans with coils
  * can be run alone or in slrx_run_batch; servers take single-channel requests. */
