@@ -92,6 +92,14 @@ typedef struct {
                                as well as in space (all T shifts, frame indices mod T)
                                in the Gram matrix and the penalty; default: the hybrid
                                lifting, linear along the parameter axis (Sec. III.A) */
+#define SLRX_FLAG_NO_GRAPH 32u /* launch the CG kernels one by one; default for a plan run
+                                 alone (slrx_run, slrx_step_cg): the CG of every
+                                 least-squares step (initial residual and n_cg iterations)
+                                 is captured once per plan as a HIP graph and replayed (same
+                                 kernels, same results), except when a CG kernel class is
+                                 timed under SLRX_FLAG_KTIME; lock-step batches and servers
+                                 launch one by one (graph launches on their many
+                                 concurrent streams measured slower) */
 /* With SLRX_FLAG_KTIME: time only the classes whose bits are set here (none set:
  * every class).  Each timed region adds two events to the stream. */
 #define SLRX_FLAG_KTIME_CLASS(c) (1u << (16 + (c)))
@@ -304,6 +312,17 @@ slrx_status slrx_server_usage(slrx_server* srv, size_t* used, int32_t* queued);
 slrx_status slrx_fetch_images(slrx_server* srv, uint64_t ticket, void* out_host);
 /* Forget a done request, freeing whatever it still holds. */
 slrx_status slrx_release(slrx_server* srv, uint64_t ticket);
+
+/* --- launch configuration tuning -----------------------------------------
+ * The library times the candidate launch configurations of its kernels on the
+ * first calls for each shape and keeps the fastest (only configurations that
+ * leave results bit for bit unchanged are tuned; the calls made while tuning
+ * are ordinary calls).  With the environment variable SLRX_TUNE_CACHE naming a
+ * file, choices are appended to it and read back by later processes.
+ * slrx_tri_workgroup_budget: the workgroups per column launch chosen for the
+ * tridiagonalisation of nbatch problems of Gram size n (decompositions run
+ * together in a batch), or 0 while that shape is still being tuned. */
+int32_t slrx_tri_workgroup_budget(int32_t n, int32_t nbatch);
 
 /* --- the normal operator without allocation ------------------------------
  * For callers that cannot allocate device memory: code under HIP graph

@@ -36,6 +36,7 @@ SLRX_FLAG_TIMING = 1
 SLRX_FLAG_KTIME = 2
 SLRX_FLAG_LIBEIGH = 4
 SLRX_FLAG_GIRAF = 8
+SLRX_FLAG_NO_GRAPH = 32
 MAX_IRLS = 256
 KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "tri", "tdeig", "backtr", "filter", "masks", "coil")
 
@@ -127,6 +128,7 @@ _SIGS = {
     "slrx_wait_for": (_I, [_P, ctypes.c_uint64, ctypes.c_double]),
     "slrx_cancel": (_I, [_P, ctypes.c_uint64]),
     "slrx_server_set_queue_timeout": (_I, [_P, ctypes.c_double]),
+    "slrx_tri_workgroup_budget": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
     "slrx_apply_noalloc_limit": (ctypes.c_size_t, []),
     "slrx_apply_noalloc": (_I, [ctypes.POINTER(Dims), ctypes.c_double, ctypes.c_uint32, _P, _P, _P, _P, _P]),
     "slrx_status_str": (ctypes.c_char_p, [_I]),
@@ -172,11 +174,13 @@ def default_params() -> Params:
 
 
 def make_params(lam=1e-3, n_irls=15, n_cg=10, p=0.6, gamma=1.4, eps0_frac=0.01, timing=False,
-                ktime=False, lib_eigh=False, ktime_classes=None, giraf=False) -> Params:
+                ktime=False, lib_eigh=False, ktime_classes=None, giraf=False, no_graph=False) -> Params:
     """ktime_classes: names from KERNEL_CLASSES to time (default: all, when ktime is set);
-    giraf: the lifting circular along the parameter axis too (SLRX_FLAG_GIRAF)."""
+    giraf: the lifting circular along the parameter axis too (SLRX_FLAG_GIRAF);
+    no_graph: CG kernels launched one by one instead of a replayed graph (SLRX_FLAG_NO_GRAPH)."""
     flags = ((SLRX_FLAG_TIMING if timing else 0) | (SLRX_FLAG_KTIME if ktime else 0)
-             | (SLRX_FLAG_LIBEIGH if lib_eigh else 0) | (SLRX_FLAG_GIRAF if giraf else 0))
+             | (SLRX_FLAG_LIBEIGH if lib_eigh else 0) | (SLRX_FLAG_GIRAF if giraf else 0)
+             | (SLRX_FLAG_NO_GRAPH if no_graph else 0))
     for c in ktime_classes or ():
         flags |= 1 << (16 + KERNEL_CLASSES.index(c))
     return Params(float(lam), float(p), float(gamma), float(eps0_frac), int(n_irls), int(n_cg), flags)

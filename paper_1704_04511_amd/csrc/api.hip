@@ -372,6 +372,8 @@ extern "C" void slrx_plan_destroy(slrx_plan* pl) {
   if (pl->ev_step) (void)hipEventDestroy(pl->ev_step);
   for (int i = 0; i < 2; ++i)
     if (pl->ev_iter[i]) (void)hipEventDestroy(pl->ev_iter[i]);
+  cg_graph_reset(pl);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
   if (pl->blas) rocblas_destroy_handle(pl->blas);
   if (pl->blas_ws) (void)hipFree(pl->blas_ws);
   if (pl->coil_mem) (void)hipFree(pl->coil_mem);

@@ -202,7 +202,7 @@ static slrx_status step_single(slrx_plan* pl) {
   STCHK(step_gram(pl));
   STCHK(step_eigh(pl, it));
   STCHK(step_weights(pl, it, it == 0, pl->prm.gamma));
-  STCHK(run_cg(pl, pl->prm.n_cg, it));
+  STCHK(run_cg(pl, pl->prm.n_cg, it, false));
   pl->it_next = it + 1;
   return SLRX_OK;
 }
@@ -242,7 +242,7 @@ slrx_status slrx::engine_step(const std::vector<slrx_plan*>& plans, BatchEig& be
       STCHK(step_weights(pl, it, it == 0, pl->prm.gamma, e.Z + (size_t)i * e.sZ, e.D + (size_t)i * n));
       HIPCHK(hipEventRecord(pl->ev_step, pl->stream));
       HIPCHK(hipStreamWaitEvent(be.stream, pl->ev_step, 0));
-      STCHK(run_cg(pl, pl->prm.n_cg, it));
+      STCHK(run_cg(pl, pl->prm.n_cg, it, false));
       pl->it_next = it + 1;
     }
     used = true;

@@ -36,7 +36,7 @@ namespace slrx {
 
 constexpr int kTriNT = 256;
 constexpr int kTriRB = 4;      // rows of a workgroup whose elements are loaded at kernel entry
-constexpr int kTriRMax = 12;   // rows per workgroup at most (n <= 3000, at most 256 workgroups)
+constexpr int kTriRMax = 32;   // rows per workgroup at most
 
 SLRX_DEV double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 SLRX_DEV double2 dscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
@@ -402,7 +402,15 @@ static void launch_col(const TriArgs& a, int nbatch, int rows, hipStream_t s) {
   k_tri_col<U><<<grid, kTriNT, 0, s>>>(a, rows);
 }
 
-hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s) {
+// Workgroup budgets per column launch (all problems of a batch together) the
+// tuner chooses from: each workgroup recomputes the reflector, so many small
+// problems want more rows per workgroup than one large one.
+static const int kTriBudget1[] = {128, 256};
+static const int kTriBudgetN[] = {256, 512, 1024, 2048, 4096};
+int tri_budget_candidates(int nbatch) { return nbatch > 1 ? 5 : 2; }
+int tri_budget(int nbatch, int cand) { return nbatch > 1 ? kTriBudgetN[cand] : kTriBudget1[cand]; }
+
+hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int budget) {
   const int n = base.n;
   if (n > tri_max_n()) return hipErrorInvalidValue;
   static bool tail_attr = false;
@@ -417,7 +425,10 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s) {
   for (int k = 0; k < k0; ++k) {
     a.k = k;
     const int nr = n - k - 1;                        // trailing rows
-    const int rows = (nr + kTriNT - 1) / kTriNT;      // at most 256 workgroups per problem
+    // rows per workgroup: at most 256 workgroups per problem and about `budget` in all
+    int rows = (nr + kTriNT - 1) / kTriNT;
+    const int rb = (int)(((long)nr * nbatch + budget - 1) / budget);
+    if (rb > rows) rows = rb < kTriRMax ? rb : kTriRMax;
     const int u = (n - k + kTriNT - 1) / kTriNT;      // vector entries per thread
     if (u <= 1) launch_col<1>(a, nbatch, rows, s);
     else if (u <= 2) launch_col<2>(a, nbatch, rows, s);

@@ -190,7 +190,11 @@ struct TriArgs {
   double2* vbuf[2];
   double2* pbuf[2];
 };
-hipError_t launch_tridiag(const TriArgs& a, int nbatch, hipStream_t s);
+// budget: workgroups per column launch across the batch (tri_budget); results
+// do not depend on it.
+hipError_t launch_tridiag(const TriArgs& a, int nbatch, hipStream_t s, int budget);
+int tri_budget_candidates(int nbatch);
+int tri_budget(int nbatch, int cand);
 int tri_max_n();
 
 // U = Q Z from the reflectors of launch_tridiag (all column-major n x n).

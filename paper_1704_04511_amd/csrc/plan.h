@@ -27,6 +27,12 @@ enum Buf {
 };
 
 slrx_status fail(slrx_status st, const char* fmt, ...);
+// What a captured CG graph depends on beyond the plan's fixed buffers.
+struct CgGraphKey {
+  int P, Q, T, M, n_cg, circ, ncoils, pad;
+  double lambda;
+  void* coil_mem;
+};
 // Binds the failures of the calling thread to a plan while in scope (the plan's
 // last error; the thread's last error is always set as well).
 struct PlanScope {
@@ -86,6 +92,12 @@ struct slrx_plan {
   void* blas_ws = nullptr;
   size_t blas_ws_size = 0;
   std::string last_error;  // message of this plan's last failed call
+
+  // the CG body of run_cg captured as a graph, and what it was captured for
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t cg_graph = nullptr;
+  hipGraphExec_t cg_exec = nullptr;
+  slrx::CgGraphKey cg_key{};
 
   hipEvent_t ev_run[2] = {nullptr, nullptr};
   hipEvent_t ev_step = nullptr;  // ordering against a shared batched eigen-decomposition
@@ -148,7 +160,11 @@ slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma, const 
                          const double* lamv = nullptr, bool want_H = false);
 slrx_status apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part);
 slrx_status coil_pass(slrx_plan* pl);
-slrx_status run_cg(slrx_plan* pl, int n_cg, int it);
+// graph: replay the CG body from a captured graph where allowed (plans run
+// alone); the lock-step engine launches one by one (graph launches on its many
+// concurrent streams measured slower than the launches themselves)
+slrx_status run_cg(slrx_plan* pl, int n_cg, int it, bool graph = true);
+void cg_graph_reset(slrx_plan* pl);
 slrx_status enqueue_run(slrx_plan* pl);
 slrx_status finish(slrx_plan* pl);
 }  // namespace slrx

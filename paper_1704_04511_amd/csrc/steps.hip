@@ -7,9 +7,11 @@
 #include <rocsolver/rocsolver.h>
 
 #include <cmath>
+#include <cstring>
 
 #include "kernels.h"
 #include "plan.h"
+#include "tune.h"
 
 using namespace slrx;
 
@@ -171,7 +173,12 @@ hipError_t slrx::eigh_tri(const EighBufs& e, hipStream_t st) {
   ta.vbuf[1] = e.triv[1];
   ta.pbuf[0] = e.trip[0];
   ta.pbuf[1] = e.trip[1];
-  return launch_tridiag(ta, e.nb, st);
+  // workgroups per launch: tuned per (n, problems) on the first decompositions
+  TuneTicket tk;
+  const int cand = tune_begin(TUNE_TRI, e.n, e.nb, 0, tri_budget_candidates(e.nb), st, tk);
+  const hipError_t err = launch_tridiag(ta, e.nb, st, tri_budget(e.nb, cand));
+  tune_end(tk, st);
+  return err;
 }
 
 hipError_t slrx::eigh_tdeig(const EighBufs& e, hipStream_t st) {
@@ -386,8 +393,9 @@ slrx_status slrx::penalty_pass(slrx_plan* pl) {
 }
 
 // n_cg iterations of CG on (S + lam F G F^-1) x = S o b (with coils:
-// (A^H A + lam F G F^-1) x = A^H b), warm-started at x.
-slrx_status slrx::run_cg(slrx_plan* pl, int n_cg, int it) {
+// (A^H A + lam F G F^-1) x = A^H b), warm-started at x: the initial residual
+// and the iterations, enqueued on pl->stream.
+static slrx_status cg_body(slrx_plan* pl, int n_cg) {
   const slrx_dims& d = pl->d;
   const long V = (long)pl->vol();
   const int nfin = fin_blocks(d.P, d.T);
@@ -452,7 +460,86 @@ slrx_status slrx::run_cg(slrx_plan* pl, int n_cg, int it) {
       HIPCHK(launch_update(ua, pl->stream));
     }
   }
+  return SLRX_OK;
+}
+
+// Everything the CG body's launches depend on besides the plan's fixed buffers.
+static CgGraphKey cg_key(const slrx_plan* pl, int n_cg) {
+  CgGraphKey k{};
+  k.P = pl->d.P; k.Q = pl->d.Q; k.T = pl->d.T; k.M = pl->d.M;
+  k.n_cg = n_cg;
+  k.lambda = pl->prm.lambda;
+  k.circ = (pl->prm.flags & SLRX_FLAG_GIRAF) ? 1 : 0;
+  k.ncoils = pl->ncoils;
+  k.coil_mem = pl->coil_mem;
+  return k;
+}
+
+// The CG body is replayed from a captured graph unless the caller asked for
+// launches one by one or times any of its kernel classes.
+static bool cg_graph_allowed(const slrx_plan* pl) {
+  if (pl->prm.flags & SLRX_FLAG_NO_GRAPH) return false;
+  if (!pl->ktime) return true;
+  const uint32_t mask = pl->prm.flags >> 16;
+  const uint32_t cg = (1u << SLRX_K_ROWS) | (1u << SLRX_K_COLS) | (1u << SLRX_K_FIN) | (1u << SLRX_K_UPDATE) |
+                      (1u << SLRX_K_COIL);
+  return mask != 0 && (mask & cg) == 0;
+}
+
+void slrx::cg_graph_reset(slrx_plan* pl) {
+  if (pl->cg_exec) (void)hipGraphExecDestroy(pl->cg_exec);
+  if (pl->cg_graph) (void)hipGraphDestroy(pl->cg_graph);
+  pl->cg_exec = nullptr;
+  pl->cg_graph = nullptr;
+}
+
+// Capture the CG body on the plan's capture stream (kernel launches only: no
+// memory set or copy nodes) and instantiate it.
+static slrx_status capture_cg(slrx_plan* pl, int n_cg, const CgGraphKey& key) {
+  cg_graph_reset(pl);
+  if (!pl->cap_stream) HIPCHK(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+  hipStream_t own = pl->stream;
+  pl->stream = pl->cap_stream;
+  HIPCHK(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+  const slrx_status st = cg_body(pl, n_cg);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(pl->cap_stream, &g);
+  pl->stream = own;
+  if (st != SLRX_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != SLRX_OK ? st : fail(SLRX_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(SLRX_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+  }
+  pl->cg_graph = g;
+  pl->cg_exec = x;
+  pl->cg_key = key;
+  return SLRX_OK;
+}
+
+slrx_status slrx::run_cg(slrx_plan* pl, int n_cg, int it, bool graph) {
+  const slrx_dims& d = pl->d;
+  const long V = (long)pl->vol();
+  if (graph && cg_graph_allowed(pl)) {
+    const CgGraphKey key = cg_key(pl, n_cg);
+    if (pl->cg_exec && std::memcmp(&key, &pl->cg_key, sizeof key) == 0) {
+      HIPCHK(hipGraphLaunch(pl->cg_exec, pl->stream));
+    } else {
+      // this time one by one (first launches set up kernel attributes outside any
+      // capture), replayed from the next call on
+      STCHK(cg_body(pl, n_cg));
+      STCHK(capture_cg(pl, n_cg, key));
+    }
+  } else {
+    STCHK(cg_body(pl, n_cg));
+  }
   if (it >= 0) {
+    const int nfin = fin_blocks(d.P, d.T);
+    const int nupd = update_blocks(V);
     HIPCHK(launch_store_sum(n_cg == 0 ? pl->partA : pl->partB, n_cg == 0 ? nfin : nupd,
                             pl->stats + 2 * SLRX_MAX_IRLS + it, pl->stream));
   }
