@@ -46,7 +46,8 @@ __all__ = [
     "dft2", "idft2", "filter_offsets", "pair_index", "lift", "gram",
     "eig_weights", "weight_matrix", "filter_spectra", "penalty_masks",
     "penalty_apply", "penalty_value", "normal_apply", "coil_forward", "coil_adjoint",
-    "coil_normal", "cg", "irls", "t2_fit",
+    "coil_normal", "cg", "irls", "t2_fit", "voxel_lift", "voxel_gram", "voxel_weights", "voxel_masks",
+    "irls_voxel",
 ]
 
 
@@ -311,6 +312,82 @@ def irls(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
         if trace is not None:
             trace.setdefault("eps", []).append(eps)
             trace.setdefault("lambda_max", []).append(float(lamR.max()))
+            trace.setdefault("cg_rr", []).append(cg_trace)
+        eps = eps / gamma
+    return x if return_kspace else idft2(x)
+
+
+# ------------------------------------------------ HLR-Voxel (Sec. II.E)
+def voxel_lift(xhat: np.ndarray, M: int) -> np.ndarray:
+    """Per-pixel Toeplitz matrices of eq. ``eq: MORASA-objective`` / ``eq:Toeplitz_g``:
+    T(rho(r)) in C^{(T-M+1) x M}, row n = M-1..T-1, column m holding rho_{n-m}(r),
+    rho = F^-1 xhat the images.  Returned as [P][Q][T-M+1][M].  Tiny inputs only."""
+    rho = idft2(xhat)
+    T, P, Q = rho.shape
+    out = np.zeros((P, Q, T - M + 1, M), dtype=np.complex128)
+    for r1 in range(P):
+        for r2 in range(Q):
+            for n in range(M - 1, T):
+                for m in range(M):
+                    out[r1, r2, n - M + 1, m] = rho[n - m, r1, r2]
+    return out
+
+
+def voxel_gram(xhat: np.ndarray, M: int) -> np.ndarray:
+    """Per-pixel Gram matrices G_r = T(rho(r))^H T(rho(r)) (M x M, the filter side):
+    G_r[m, m'] = sum_{n=M-1}^{T-1} conj(rho_{n-m}(r)) rho_{n-m'}(r).  [P][Q][M][M]."""
+    rho = idft2(xhat)
+    T = rho.shape[0]
+    G = np.zeros(rho.shape[1:] + (M, M), dtype=np.complex128)
+    for m in range(M):
+        for mp in range(M):
+            G[..., m, mp] = sum(np.conj(rho[n - m]) * rho[n - mp] for n in range(M - 1, T))
+    return G
+
+
+def voxel_weights(G: np.ndarray, eps: float, p: float):
+    """IRLS weights of the pixel-wise Hankel low-rank prior (HLR-Voxel, Sec. II.E; solved
+    by IRLS as in Sec. IV): per pixel, H_r = (G_r + eps I)^(p/2-1) from the eigen-
+    decomposition of G_r, eigenvalues clamped at 0.  The penalty
+    sum_r ||T_r H_r^(1/2)||_F^2 = sum_r sum_n z^H E_r z (z_m = rho_{n-m}(r)) has
+    E_r = conj(H_r), the per-pixel masks the CG operator takes.  G: [P][Q][M][M].
+    Returns (E [M][M][P][Q], eigenvalues [P][Q][M] ascending)."""
+    lam, U = np.linalg.eigh(G)                   # per pixel, eigenvector i in U[..., :, i]
+    alpha = (np.maximum(lam, 0.0) + eps) ** (p / 2.0 - 1.0)
+    E = np.einsum("...i,...mi,...ni->...mn", alpha, np.conj(U), U)   # sum_i alpha_i conj(U_mi) U_ni
+    return np.moveaxis(E, (-2, -1), (0, 1)).copy(), lam
+
+
+def voxel_masks(xhat: np.ndarray, M: int, eps: float, p: float):
+    """E [M][M][P][Q] of voxel_weights for the per-pixel Gram matrices of xhat, and the
+    largest eigenvalue over all pixels."""
+    E, lam = voxel_weights(voxel_gram(xhat, M), eps, p)
+    return E, float(lam[..., -1].max())
+
+
+def irls_voxel(b: np.ndarray, S: np.ndarray, M: int, lam: float, n_irls: int, n_cg: int,
+               p: float = 0.6, gamma: float = 1.4, eps0_frac: float = 0.01,
+               trace: dict | None = None, return_kspace: bool = False) -> np.ndarray:
+    """HLR-Voxel (the comparison system of Sec. II.E / Sec. IV) by the IRLS loop of
+    Algorithm 1 with per-pixel weights: each outer iteration forms every pixel's Gram
+    matrix, eps^(0) = eps0_frac times the largest eigenvalue over all pixels (first
+    iteration), the masks E_r of voxel_weights, n_cg CG iterations on
+    (S + lam F G F^*) xhat = S o b with those masks, then eps <- eps / gamma."""
+    S = S.astype(np.float64)
+    b = S * b.astype(np.complex128)
+    x = b.copy()
+    eps = None
+    for _ in range(n_irls):
+        G = voxel_gram(x, M)
+        lmax = float(np.linalg.eigvalsh(G)[..., -1].max())
+        if eps is None:
+            eps = eps0_frac * lmax
+        E, _ = voxel_weights(G, eps, p)
+        cg_trace = [] if trace is not None else None
+        x = cg(lambda v: normal_apply(v, S, E, lam), b, x, n_cg, cg_trace)
+        if trace is not None:
+            trace.setdefault("eps", []).append(eps)
+            trace.setdefault("lambda_max", []).append(lmax)
             trace.setdefault("cg_rr", []).append(cg_trace)
         eps = eps / gamma
     return x if return_kspace else idft2(x)

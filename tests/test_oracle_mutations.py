@@ -57,11 +57,21 @@ GIRAF_MUTATIONS = {
     "giraf_penalty_wrap": ("out[(n - m) % T] += E[m, mp] * rho[(n - mp) % T]",
                            "out[(n - m) % T] += E[m, mp] * rho[max(n - mp, 0)]"),
 }
+# mistakes in the pixel-wise (HLR-Voxel) prior, checked against its own pins
+VOXEL_MUTATIONS = {
+    "voxel_mask_conj": ('E = np.einsum("...i,...mi,...ni->...mn", alpha, np.conj(U), U)',
+                        'E = np.einsum("...i,...mi,...ni->...mn", alpha, U, np.conj(U))'),
+    "voxel_gram_range": ("for n in range(M - 1, T))", "for n in range(M, T))"),
+    "voxel_gram_conj": ("sum(np.conj(rho[n - m]) * rho[n - mp]", "sum(rho[n - m] * np.conj(rho[n - mp])"),
+    "voxel_lambda_max": ("lmax = float(np.linalg.eigvalsh(G)[..., -1].max())",
+                         "lmax = float(np.linalg.eigvalsh(G)[..., -1].mean())"),
+}
 PIN_FILE = {name: "tests/test_oracle_pins.py" for name in MUTATIONS}
 PIN_FILE.update({name: "tests/test_oracle_giraf.py" for name in GIRAF_MUTATIONS})
 PIN_FILE.update({name: "tests/test_oracle_coils.py" for name in COIL_MUTATIONS})
 PIN_FILE.update({name: "tests/test_oracle_t2.py" for name in T2_MUTATIONS})
-ALL = dict(MUTATIONS, **COIL_MUTATIONS, **T2_MUTATIONS, **GIRAF_MUTATIONS)
+PIN_FILE.update({name: "tests/test_oracle_voxel.py" for name in VOXEL_MUTATIONS})
+ALL = dict(MUTATIONS, **COIL_MUTATIONS, **T2_MUTATIONS, **GIRAF_MUTATIONS, **VOXEL_MUTATIONS)
 
 
 @pytest.mark.parametrize("name", sorted(ALL))
