@@ -62,6 +62,8 @@ def algorithmic_bytes(kind: str, T: int, P: int, Q: int, M: int, N1: int, N2: in
         return lag + W * P * Q * c
     if kind == "filter":   # read U (s^2 complex128); write H (2 s^2 doubles)
         return s * s * 16 + 2 * s * s * 8
+    if kind == "voxel":    # pixel-wise weights: read the images, write the masks (the masks
+        return V * c + W * P * Q * c   # pass; FP64 Jacobi arithmetic per pixel sets its time)
     return 0.0
 
 
@@ -527,6 +529,80 @@ def bench_mc(args) -> int:
     return 0
 
 
+def bench_hlr(args) -> int:
+    """The 256x256x20 data under the pixel-wise prior (HLR-Voxel, 1x1x5 filter per
+    pixel, 20 x 15): IRLS iterations/s, the per-class breakdown, NRMSE against the
+    FP64 oracle on the first outer iterations, and the oracle's time for them."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1704_04511_amd as slrx
+    import workload
+
+    torch.cuda.set_device(0)
+    pb = workload.config_problem("hlr")
+    T, P, Q = pb.b.shape
+    mk = lambda kt, n_irls=pb.n_irls: slrx.make_params(lam=pb.lam, n_irls=n_irls, n_cg=pb.n_cg, p=pb.p,
+                                                        gamma=pb.gamma, eps0_frac=pb.eps0_frac, ktime=kt,
+                                                        voxel=True)
+    plan = slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, mk(False))
+    plan.set_kspace(pb.b)
+    plan.set_mask(pb.S)
+    for _ in range(args.warmup):
+        plan.run()
+        plan.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run()
+        plan.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    img = plan.images()
+    plan.set_params(mk(True))  # one more reconstruction with every class timed
+    plan.run()
+    plan.sync()
+    st = plan.stats()
+    kms, kcnt = st["kernel_ms"], st["kernel_count"]
+    own = [k for k in ("rows", "cols", "fin", "update", "voxel") if kcnt[k] > 0]
+    roofs = {k: roofline(k, kms[k] / kcnt[k], T, P, Q, pb.M, pb.N1, pb.N2) for k in own}
+    dom = max(own, key=lambda k: kms[k])
+    out = {
+        "metric": "IRLS iters/s (256x256x20, HLR-Voxel 1x1x5 per pixel)",
+        "value": round(pb.n_irls * args.steps / dt, 3), "unit": "IRLS iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {"workload": "the 256x256 x 20-echo T2 series (K=2, smooth phase, R=8) under the pixel-wise "
+                               "Hankel prior (Sec. II.E): 65536 per-pixel 5x5 Gram eigen-decompositions per "
+                               "outer iteration, 20 IRLS x 15 CG", "n_irls": pb.n_irls, "n_cg": pb.n_cg},
+        "roofline": roofs[dom],
+        "roofline_by_kernel": {k: {kk: v for kk, v in r.items() if kk in ("bound", "achieved", "unit", "frac")}
+                               for k, r in roofs.items()},
+        "phases_ms_per_step": {k: round(kms[k], 3) for k in kms if kcnt[k] > 0},
+        "voxel_weight_update_ms": round(kms["voxel"] / max(kcnt["voxel"], 1), 4),
+        "recon_nrmse_vs_truth": round(float(np.linalg.norm(img - pb.truth) / np.linalg.norm(pb.truth)), 5),
+    }
+    if not args.no_cpu_baseline:
+        n_out = 2
+        plan.set_params(mk(False, n_out))
+        plan.run()
+        plan.sync()
+        part = plan.images()
+        cores = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        ora = oracle.irls_voxel(pb.b, pb.S, pb.M, pb.lam, n_out, pb.n_cg, p=pb.p, gamma=pb.gamma,
+                                eps0_frac=pb.eps0_frac)
+        dto = time.perf_counter() - t0
+        out["nrmse_vs_oracle_first_outer"] = float(f"{np.linalg.norm(part - ora) / np.linalg.norm(ora):.3e}")
+        out["cpu_baseline"] = {"value": n_out / dto, "unit": "IRLS iter/s", "cores": cores, "kind": "oracle",
+                               "sample": f"the first {n_out} outer iterations of the same workload, {dto:.1f} s wall"}
+    plan.close()
+    print(json.dumps(out))
+    return 0
+
+
 def bench_calib(args) -> int:
     """Plain device-to-device copy of a known size (--calib-mb MiB read and written
     per launch), to calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE against bytes."""
@@ -575,7 +651,7 @@ def main() -> int:
     ap.add_argument("--cpu-outer", type=int, default=3, help="outer iterations in the CPU oracle sample")
     ap.add_argument("--n-irls", type=int, default=None,
                     help="override the outer iteration count (profiling runs only; changes the workload)")
-    ap.add_argument("--workload", choices=("c3", "c2", "mc", "batch", "serve", "calib"), default="c3",
+    ap.add_argument("--workload", choices=("c3", "c2", "mc", "hlr", "batch", "serve", "calib"), default="c3",
                     help="c3: the 256x256x20 headline line (default); c2: 128x128x16 with T2 maps; "
                          "mc: 12-coil 128x128x12; batch: 32 uneven slices; serve: Poisson request stream; "
                          "calib: the plain copy that calibrates the HBM counters")
@@ -592,6 +668,8 @@ def main() -> int:
         return bench_calib(args)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "hlr":
+        return bench_hlr(args)
     if args.workload == "mc":
         return bench_mc(args)
     if args.workload == "c2":

@@ -100,6 +100,17 @@ typedef struct {
                                  timed under SLRX_FLAG_KTIME; lock-step batches and servers
                                  launch one by one (graph launches on their many
                                  concurrent streams measured slower) */
+#define SLRX_FLAG_HLR_VOXEL 64u /* the pixel-wise Hankel low-rank prior the paper compares with
+                                  (HLR-Voxel; Sec. II.E, eq. "eq: MORASA-objective", solved by
+                                  IRLS, Sec. IV): every pixel's series gets its own
+                                  (T-M+1) x M Toeplitz matrix T_r and its own weight
+                                  H_r = (T_r^H T_r + eps I)^(p/2-1) (eigenvalues clamped at 0),
+                                  the penalty is sum_r ||T_r H_r^(1/2)||_F^2, and eps^(0) is
+                                  eps0_frac times the largest eigenvalue over all pixels.
+                                  Requires N1 = N2 = 1 (a filter of M taps per pixel); not
+                                  combinable with SLRX_FLAG_GIRAF or SLRX_FLAG_LIBEIGH.  There
+                                  is no global Gram matrix: slrx_step_gram and the lam / H
+                                  outputs of slrx_step_weights are rejected */
 /* With SLRX_FLAG_KTIME: time only the classes whose bits are set here (none set:
  * every class).  Each timed region adds two events to the stream. */
 #define SLRX_FLAG_KTIME_CLASS(c) (1u << (16 + (c)))
@@ -121,7 +132,9 @@ enum {
   SLRX_K_COIL = 10,   /* multichannel data term (with coil maps only): coil images
                          and their forward DFT, sampling mask, inverse DFT and
                          coil combination */
-  SLRX_K_NCLASS = 11
+  SLRX_K_VOXEL = 11,  /* SLRX_FLAG_HLR_VOXEL: per-pixel Gram matrices, eigen-decompositions
+                         and masks, and the eps schedule on their eigenvalues */
+  SLRX_K_NCLASS = 12
 };
 
 /* Per-run statistics, filled by slrx_get_stats after a completed run. */

@@ -367,14 +367,23 @@ def voxel_masks(xhat: np.ndarray, M: int, eps: float, p: float):
 
 def irls_voxel(b: np.ndarray, S: np.ndarray, M: int, lam: float, n_irls: int, n_cg: int,
                p: float = 0.6, gamma: float = 1.4, eps0_frac: float = 0.01,
-               trace: dict | None = None, return_kspace: bool = False) -> np.ndarray:
+               trace: dict | None = None, return_kspace: bool = False,
+               coils: np.ndarray | None = None) -> np.ndarray:
     """HLR-Voxel (the comparison system of Sec. II.E / Sec. IV) by the IRLS loop of
     Algorithm 1 with per-pixel weights: each outer iteration forms every pixel's Gram
     matrix, eps^(0) = eps0_frac times the largest eigenvalue over all pixels (first
     iteration), the masks E_r of voxel_weights, n_cg CG iterations on
-    (S + lam F G F^*) xhat = S o b with those masks, then eps <- eps / gamma."""
+    (S + lam F G F^*) xhat = S o b with those masks, then eps <- eps / gamma.
+    With ``coils`` the least-squares step is the multichannel one of Sec. II.A, as
+    in ``irls`` (the paper compares HLR-Voxel on multichannel data too, Sec. IV)."""
     S = S.astype(np.float64)
-    b = S * b.astype(np.complex128)
+    if coils is None:
+        b = S * b.astype(np.complex128)
+        normal = lambda v, E: normal_apply(v, S, E, lam)
+    else:
+        C = coils.astype(np.complex128)
+        b = coil_adjoint(S[None] * b.astype(np.complex128), S, C)
+        normal = lambda v, E: coil_normal(v, S, C, E, lam)
     x = b.copy()
     eps = None
     for _ in range(n_irls):
@@ -384,7 +393,7 @@ def irls_voxel(b: np.ndarray, S: np.ndarray, M: int, lam: float, n_irls: int, n_
             eps = eps0_frac * lmax
         E, _ = voxel_weights(G, eps, p)
         cg_trace = [] if trace is not None else None
-        x = cg(lambda v: normal_apply(v, S, E, lam), b, x, n_cg, cg_trace)
+        x = cg(lambda v: normal(v, E), b, x, n_cg, cg_trace)
         if trace is not None:
             trace.setdefault("eps", []).append(eps)
             trace.setdefault("lambda_max", []).append(lmax)

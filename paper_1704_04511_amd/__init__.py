@@ -37,8 +37,10 @@ SLRX_FLAG_KTIME = 2
 SLRX_FLAG_LIBEIGH = 4
 SLRX_FLAG_GIRAF = 8
 SLRX_FLAG_NO_GRAPH = 32
+SLRX_FLAG_HLR_VOXEL = 64
 MAX_IRLS = 256
-KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "tri", "tdeig", "backtr", "filter", "masks", "coil")
+KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "tri", "tdeig", "backtr", "filter", "masks", "coil",
+                  "voxel")
 
 STATUS = {0: "SLRX_OK", -1: "SLRX_EINVAL", -2: "SLRX_ENOMEM", -3: "SLRX_EDEVICE", -4: "SLRX_ESTATE",
           -5: "SLRX_ENUMERIC", -6: "SLRX_EBUSY", -7: "SLRX_ENOTREADY", -8: "SLRX_ECANCELED",
@@ -174,13 +176,15 @@ def default_params() -> Params:
 
 
 def make_params(lam=1e-3, n_irls=15, n_cg=10, p=0.6, gamma=1.4, eps0_frac=0.01, timing=False,
-                ktime=False, lib_eigh=False, ktime_classes=None, giraf=False, no_graph=False) -> Params:
+                ktime=False, lib_eigh=False, ktime_classes=None, giraf=False, no_graph=False,
+                voxel=False) -> Params:
     """ktime_classes: names from KERNEL_CLASSES to time (default: all, when ktime is set);
     giraf: the lifting circular along the parameter axis too (SLRX_FLAG_GIRAF);
-    no_graph: CG kernels launched one by one instead of a replayed graph (SLRX_FLAG_NO_GRAPH)."""
+    no_graph: CG kernels launched one by one instead of a replayed graph (SLRX_FLAG_NO_GRAPH);
+    voxel: the pixel-wise prior HLR-Voxel (SLRX_FLAG_HLR_VOXEL; needs an N1 = N2 = 1 filter)."""
     flags = ((SLRX_FLAG_TIMING if timing else 0) | (SLRX_FLAG_KTIME if ktime else 0)
              | (SLRX_FLAG_LIBEIGH if lib_eigh else 0) | (SLRX_FLAG_GIRAF if giraf else 0)
-             | (SLRX_FLAG_NO_GRAPH if no_graph else 0))
+             | (SLRX_FLAG_NO_GRAPH if no_graph else 0) | (SLRX_FLAG_HLR_VOXEL if voxel else 0))
     for c in ktime_classes or ():
         flags |= 1 << (16 + KERNEL_CLASSES.index(c))
     return Params(float(lam), float(p), float(gamma), float(eps0_frac), int(n_irls), int(n_cg), flags)
@@ -366,6 +370,14 @@ class Plan:
                                        H.ctypes.data_as(ctypes.c_void_p), E.ctypes.data_as(ctypes.c_void_p),
                                        SLRX_MEM_HOST))
         return lam, H, E
+
+    def step_voxel_masks(self, eps: float):
+        """HLR-Voxel plans: the per-pixel masks E [W][P][Q] for the given eps (no lam or H)."""
+        d = self.dims
+        E = np.empty((self.W, d.P, d.Q), np.complex64)
+        self._c(lib().slrx_step_weights(self._h, float(eps), None, None, E.ctypes.data_as(ctypes.c_void_p),
+                                       SLRX_MEM_HOST))
+        return E
 
     def step_tdeig(self, D, E):
         """Eigenpairs of the real symmetric tridiagonal (D, E) of size s (divide and conquer)."""

@@ -135,9 +135,23 @@ static slrx_status validate_params(const slrx_params* p) {
   return SLRX_OK;
 }
 
+// Flags that constrain the dims or each other.
+static slrx_status validate_combo(const slrx_dims& d, const slrx_params& p) {
+  if (p.flags & SLRX_FLAG_HLR_VOXEL) {
+    if (d.N1 != 1 || d.N2 != 1)
+      return fail(SLRX_EINVAL, "SLRX_FLAG_HLR_VOXEL needs N1 = N2 = 1 (got %dx%d)", d.N1, d.N2);
+    if (p.flags & (SLRX_FLAG_GIRAF | SLRX_FLAG_LIBEIGH))
+      return fail(SLRX_EINVAL, "SLRX_FLAG_HLR_VOXEL does not combine with SLRX_FLAG_GIRAF or SLRX_FLAG_LIBEIGH");
+  }
+  return SLRX_OK;
+}
+
 extern "C" slrx_status slrx_validate(const slrx_dims* dims, const slrx_params* params) {
   STCHK(validate_dims(dims));
-  if (params) STCHK(validate_params(params));
+  if (params) {
+    STCHK(validate_params(params));
+    STCHK(validate_combo(*dims, *params));
+  }
   return SLRX_OK;
 }
 
@@ -312,6 +326,7 @@ extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params
   slrx_params prm;
   if (params) {
     STCHK(validate_params(params));
+    STCHK(validate_combo(*dims, *params));
     prm = *params;
   } else {
     slrx_default_params(&prm);
@@ -504,6 +519,7 @@ extern "C" slrx_status slrx_set_filter(slrx_plan* pl, int32_t N1, int32_t N2, in
   d.N2 = N2;
   d.M = M;
   STCHK(validate_dims(&d));
+  STCHK(validate_combo(d, pl->prm));
   if (N1 > pl->cap.N1 || N2 > pl->cap.N2 || M > pl->cap.M)
     return fail(SLRX_EINVAL, "filter %dx%dx%d exceeds the plan's capacity %dx%dx%d", N1, N2, M, pl->cap.N1,
                 pl->cap.N2, pl->cap.M);
@@ -516,6 +532,7 @@ extern "C" slrx_status slrx_set_params(slrx_plan* pl, const slrx_params* prm) {
   PlanScope scope(pl);
   STCHK(check_idle(pl));
   STCHK(validate_params(prm));
+  STCHK(validate_combo(pl->d, *prm));
   pl->prm = *prm;
   return SLRX_OK;
 }
@@ -538,11 +555,17 @@ slrx_status slrx::enqueue_run(slrx_plan* pl) {
   HIPCHK(hipEventRecord(pl->ev_run[0], pl->stream));
   for (int it = 0; it < nirls; ++it) {
     if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it], pl->stream));
-    STCHK(step_gram(pl));
-    if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 1], pl->stream));
-    STCHK(step_eigh(pl, it));
-    if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 2], pl->stream));
-    STCHK(step_weights(pl, it, it == 0, pl->prm.gamma));
+    if (pl->voxel()) {  // the whole per-pixel weight update counts as the weights phase
+      if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 1], pl->stream));
+      if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 2], pl->stream));
+      STCHK(step_voxel(pl, it, it == 0, pl->prm.gamma));
+    } else {
+      STCHK(step_gram(pl));
+      if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 1], pl->stream));
+      STCHK(step_eigh(pl, it));
+      if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 2], pl->stream));
+      STCHK(step_weights(pl, it, it == 0, pl->prm.gamma));
+    }
     if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 3], pl->stream));
     STCHK(run_cg(pl, pl->prm.n_cg, it));
   }
@@ -755,6 +778,7 @@ static slrx_status ensure_prepared(slrx_plan* pl) {
 
 extern "C" slrx_status slrx_step_gram(slrx_plan* pl, void* R_out, slrx_mem mem) {
   PlanScope scope(pl);
+  if (pl && pl->voxel()) return fail(SLRX_EINVAL, "SLRX_FLAG_HLR_VOXEL has no global Gram matrix");
   STCHK(ensure_prepared(pl));
   STCHK(step_gram(pl, true));
   const size_t s = (size_t)pl->d.N1 * pl->d.N2 * pl->d.M;
@@ -763,10 +787,34 @@ extern "C" slrx_status slrx_step_gram(slrx_plan* pl, void* R_out, slrx_mem mem) 
   return SLRX_OK;
 }
 
+// slrx_step_weights of the pixel-wise prior: the masks alone.
+static slrx_status step_weights_voxel(slrx_plan* pl, double eps, double* lam_out, void* H_out, void* E_out,
+                                      slrx_mem mem) {
+  if (lam_out || H_out)
+    return fail(SLRX_EINVAL, "SLRX_FLAG_HLR_VOXEL has per-pixel weights only: lam and H outputs must be NULL");
+  STCHK(ensure_prepared(pl));
+  HIPCHK(hipMemsetAsync(pl->info + kInfoNonfinite, 0, sizeof(rocblas_int), pl->stream));
+  HIPCHK(hipMemcpyAsync(pl->scal, &eps, sizeof(double), hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  STCHK(step_voxel(pl, -1, false, 1.0));
+  if (E_out) {
+    const slrx_dims& d = pl->d;
+    const size_t W = (size_t)d.M * (d.M + 1) / 2;
+    STCHK(store_masks(pl));
+    STCHK(copy_out(pl, E_out, pl->Estage, W * d.P * d.Q * sizeof(float2), mem));
+  }
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  int bad = 0;
+  HIPCHK(hipMemcpy(&bad, pl->info + kInfoNonfinite, sizeof(int), hipMemcpyDeviceToHost));
+  if (bad) return fail(SLRX_ENUMERIC, "non-finite Gram matrix (non-finite data, initial guess or iterate)");
+  return SLRX_OK;
+}
+
 extern "C" slrx_status slrx_step_weights(slrx_plan* pl, double eps, double* lam_out, void* H_out, void* E_out,
                                          slrx_mem mem) {
   PlanScope scope(pl);
   if (!(eps > 0.0) || !std::isfinite(eps)) return fail(SLRX_EINVAL, "eps must be finite and > 0");
+  if (pl && pl->voxel()) return step_weights_voxel(pl, eps, lam_out, H_out, E_out, mem);
   STCHK(ensure_prepared(pl));
   STCHK(step_gram(pl));
   STCHK(step_eigh(pl, -1));

@@ -199,9 +199,13 @@ slrx_status slrx::engine_end(slrx_plan* pl) {
 // One outer iteration of one problem on its own stream (the path of a plan run alone).
 static slrx_status step_single(slrx_plan* pl) {
   const int it = pl->it_next;
-  STCHK(step_gram(pl));
-  STCHK(step_eigh(pl, it));
-  STCHK(step_weights(pl, it, it == 0, pl->prm.gamma));
+  if (pl->voxel()) {
+    STCHK(step_voxel(pl, it, it == 0, pl->prm.gamma));
+  } else {
+    STCHK(step_gram(pl));
+    STCHK(step_eigh(pl, it));
+    STCHK(step_weights(pl, it, it == 0, pl->prm.gamma));
+  }
   STCHK(run_cg(pl, pl->prm.n_cg, it, false));
   pl->it_next = it + 1;
   return SLRX_OK;
@@ -211,7 +215,7 @@ slrx_status slrx::engine_step(const std::vector<slrx_plan*>& plans, BatchEig& be
   std::map<int, std::vector<slrx_plan*>> groups;
   for (slrx_plan* pl : plans) {
     if (pl->it_next >= pl->prm.n_irls) continue;
-    if (pl->lib_eigh()) STCHK(step_single(pl));
+    if (pl->lib_eigh() || pl->voxel()) STCHK(step_single(pl));
     else groups[pl->s()].push_back(pl);
   }
   bool used = false;

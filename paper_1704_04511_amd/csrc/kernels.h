@@ -161,6 +161,31 @@ struct GramArgs {
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t s);
 
+// Pixel-wise weights (HLR-Voxel): per pixel the M x M Gram matrix of its
+// Toeplitz lifting, its eigen-decomposition, and the masks conj((G + eps I)^(p/2-1)).
+struct VoxelArgs {
+  int P, Q, T, M;           // P, Q multiples of 8; M <= 8
+  const float2* img;        // images [T][P][Q]
+  double* part;             // largest eigenvalue per 8 x 8 tile (voxel_tiles entries), or null
+  const double* eps;        // eps (device), masks pass only
+  double p;
+  float2* Et;               // masks, transposed planes [W][Q][P] (masks pass only)
+  int* bad;                 // set to 1 on a non-finite Gram entry (then taken as 0), or null
+};
+int voxel_tiles(int P, int Q);
+// vec = false: eigenvalues only (tile maxima); vec = true: the masks as well.
+hipError_t launch_voxel(const VoxelArgs& a, bool vec, hipStream_t s);
+struct VoxelEpsArgs {
+  const double* part;
+  int nparts;
+  int mode;                 // 0: eps = eps0_frac * max; 1: eps = eps / gamma; 2: max record only
+  double* eps;
+  double* lam_max_out;      // may be null
+  double* eps_out;          // may be null
+  double eps0_frac, gamma;
+};
+hipError_t launch_voxel_eps(const VoxelEpsArgs& a, hipStream_t s);
+
 struct WeightArgs {
   int s;
   const double* lamv;       // eigenvalues, ascending

@@ -118,6 +118,8 @@ struct slrx_plan {
   int s() const { return d.N1 * d.N2 * d.M; }
   // the library eigensolver (test reference) instead of the own chain
   bool lib_eigh() const;
+  // the pixel-wise prior (HLR-Voxel) instead of the multi-fold Toeplitz lifting
+  bool voxel() const { return (prm.flags & SLRX_FLAG_HLR_VOXEL) != 0; }
 };
 
 namespace slrx {
@@ -158,6 +160,9 @@ hipError_t eigh_backtr(const EighBufs& e, hipStream_t s);  // Z <- Q Z (A used a
 slrx_status dc_prepare(slrx_plan* pl);
 slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma, const double2* U = nullptr,
                          const double* lamv = nullptr, bool want_H = false);
+// Weight update of the pixel-wise prior (SLRX_FLAG_HLR_VOXEL), in place of
+// step_gram, step_eigh and step_weights.
+slrx_status step_voxel(slrx_plan* pl, int it, bool first, double gamma);
 slrx_status apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part);
 slrx_status coil_pass(slrx_plan* pl);
 // graph: replay the CG body from a captured graph where allowed (plans run

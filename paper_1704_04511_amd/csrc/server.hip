@@ -406,7 +406,7 @@ extern "C" slrx_status slrx_submit(slrx_server* s, slrx_plan* plan, uint64_t* ti
   r->plan = plan;
   r->owned = false;
   r->s = plan->s();
-  r->eig = engine_problem_bytes(r->s);
+  r->eig = plan->voxel() ? 0 : engine_problem_bytes(r->s);  // voxel plans need no shared eigensolver
   r->bytes = slrx_footprint(&plan->cap) + r->eig;
   const slrx_status st = enqueue(s, r, ticket);
   if (st != SLRX_OK) {
@@ -434,7 +434,7 @@ extern "C" slrx_status slrx_submit_data(slrx_server* s, const slrx_dims* dims, c
   r->b.assign((const float2*)b, (const float2*)b + V);
   r->S.assign(S, S + V);
   r->s = dims->N1 * dims->N2 * dims->M;
-  r->eig = engine_problem_bytes(r->s);
+  r->eig = (r->prm.flags & SLRX_FLAG_HLR_VOXEL) ? 0 : engine_problem_bytes(r->s);
   r->bytes = slrx_footprint(dims) + r->eig;
   return enqueue(s, r, ticket);
 }

@@ -305,6 +305,52 @@ slrx_status slrx::step_weights(slrx_plan* pl, int it, bool first, double gamma, 
   return SLRX_OK;
 }
 
+// Weight update of the pixel-wise prior (HLR-Voxel, SLRX_FLAG_HLR_VOXEL): per
+// pixel the Gram matrix of its own Toeplitz lifting, its eigen-decomposition and
+// the masks conj((G_r + eps I)^(p/2-1)) (k_voxel.hip).  On the first outer
+// iteration a pass over the eigenvalues alone gives eps^(0) from the largest
+// eigenvalue over all pixels before the masks pass; later iterations take
+// eps <- eps / gamma first and record the largest eigenvalue from the masks
+// pass itself.  it < 0: the single-step entry point, eps already set.
+slrx_status slrx::step_voxel(slrx_plan* pl, int it, bool first, double gamma) {
+  const slrx_dims& d = pl->d;
+  STCHK(images(pl));
+  KTimer kt(pl, SLRX_K_VOXEL);
+  VoxelArgs va{};
+  va.P = d.P; va.Q = d.Q; va.T = d.T; va.M = d.M;
+  va.img = pl->img;
+  va.part = it >= 0 ? pl->partB : nullptr;
+  va.eps = pl->scal;
+  va.p = pl->prm.p;
+  va.Et = pl->Et;
+  va.bad = (int*)(pl->info + kInfoNonfinite);
+  VoxelEpsArgs ea{};
+  ea.part = pl->partB;
+  ea.nparts = voxel_tiles(d.P, d.Q);
+  ea.eps = pl->scal;
+  ea.lam_max_out = it >= 0 ? pl->stats + SLRX_MAX_IRLS + it : nullptr;
+  ea.eps_out = it >= 0 ? pl->stats + it : nullptr;
+  ea.eps0_frac = pl->prm.eps0_frac;
+  ea.gamma = gamma;
+  if (it < 0) {
+    HIPCHK(launch_voxel(va, true, pl->stream));
+    return SLRX_OK;
+  }
+  if (first) {
+    HIPCHK(launch_voxel(va, false, pl->stream));
+    ea.mode = 0;
+    HIPCHK(launch_voxel_eps(ea, pl->stream));
+    HIPCHK(launch_voxel(va, true, pl->stream));
+  } else {
+    ea.mode = 1;
+    HIPCHK(launch_voxel_eps(ea, pl->stream));
+    HIPCHK(launch_voxel(va, true, pl->stream));
+    ea.mode = 2;
+    HIPCHK(launch_voxel_eps(ea, pl->stream));
+  }
+  return SLRX_OK;
+}
+
 // The coil passes of the multichannel operator on the row pass output t:
 // rho_u, per coil the masked round trip through k-space (complex128 after the
 // mask), and their combination's group sums, column-transformed (added to the

@@ -76,6 +76,19 @@ def test_invalid_params_rejected(kw, msg):
     assert msg in str(ei.value)
 
 
+@pytest.mark.parametrize("dims,kw,msg", [
+    ((64, 64, 8, 3, 1, 3), dict(voxel=True), "N1 = N2 = 1"),
+    ((64, 64, 8, 1, 1, 3), dict(voxel=True, giraf=True), "does not combine"),
+    ((64, 64, 8, 1, 1, 3), dict(voxel=True, lib_eigh=True), "does not combine"),
+])
+def test_voxel_flag_constraints(dims, kw, msg):
+    with pytest.raises(slrx.SlrxError) as ei:
+        slrx.validate(slrx.Dims(*dims), slrx.make_params(**kw))
+    assert ei.value.name == "SLRX_EINVAL"
+    assert msg in str(ei.value)
+    slrx.validate(slrx.Dims(64, 64, 8, 1, 1, 3), slrx.make_params(voxel=True))
+
+
 def test_footprint_grows_with_problem():
     f1 = slrx.footprint(slrx.Dims(64, 64, 8, 5, 5, 3))
     f2 = slrx.footprint(slrx.Dims(128, 128, 16, 9, 9, 5))

@@ -102,3 +102,18 @@ def test_voxel_eps_schedule_over_several_pixels():
     top = max(np.linalg.svd(Tm[i, j], compute_uv=False)[0] ** 2 for i in range(P) for j in range(Q))
     assert np.isclose(tr["lambda_max"][0], top, rtol=1e-12)
     np.testing.assert_allclose(tr["eps"], [top / 100 / 1.4 ** k for k in range(3)], rtol=1e-12)
+
+
+def test_one_pixel_voxel_irls_with_coils_equals_main_irls():
+    """The multichannel least-squares step (Sec. II.A) under the pixel-wise prior: on a
+    one-pixel image it is the main loop's with the 1 x 1 x M filter and the same coils."""
+    rng = np.random.default_rng(6)
+    T, M, nc = 9, 3, 3
+    xhat = series(rng, T, 1, 1, noise=0.05)
+    C = rng.standard_normal((nc, 1, 1)) + 1j * rng.standard_normal((nc, 1, 1))
+    S = (rng.random((T, 1, 1)) < 0.7).astype(np.float64)
+    S[0] = 1.0
+    b = oracle.coil_forward(xhat, S, C)
+    a = oracle.irls_voxel(b, S, M, 0.3, 4, 4, coils=C)
+    ref = oracle.irls(b, S, 1, 1, M, 0.3, 4, 4, coils=C)
+    assert np.abs(a - ref).max() <= 1e-10 * np.abs(ref).max()

@@ -224,6 +224,9 @@ CONFIGS = {
                n_irls=15, n_cg=10, phase=False),
     "c3": dict(seed=3, P=256, Q=256, T=20, K=2, R=8, N1=15, N2=15, M=5, lam=1e-3,
                n_irls=20, n_cg=15, phase=True),
+    # the c3 data under the pixel-wise prior (HLR-Voxel): a 1 x 1 x 5 filter per pixel
+    "hlr": dict(seed=3, P=256, Q=256, T=20, K=2, R=8, N1=1, N2=1, M=5, lam=1e-3,
+                n_irls=20, n_cg=15, phase=True),
 }
 
 
