@@ -47,7 +47,8 @@ __all__ = [
     "eig_weights", "weight_matrix", "filter_spectra", "penalty_masks",
     "penalty_apply", "penalty_value", "normal_apply", "coil_forward", "coil_adjoint",
     "coil_normal", "cg", "irls", "t2_fit", "voxel_lift", "voxel_gram", "voxel_weights", "voxel_masks",
-    "irls_voxel",
+    "irls_voxel", "linear_rows", "lift_linear", "lift_linear_adjoint", "gram_direct",
+    "direct_normal_apply", "irls_direct",
 ]
 
 
@@ -309,6 +310,96 @@ def irls(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
         E = penalty_masks(U, alpha, N1, N2, M, P, Q)
         cg_trace = [] if trace is not None else None
         x = cg(lambda v: normal(v, E), b, x, n_cg, cg_trace)
+        if trace is not None:
+            trace.setdefault("eps", []).append(eps)
+            trace.setdefault("lambda_max", []).append(float(lamR.max()))
+            trace.setdefault("cg_rr", []).append(cg_trace)
+        eps = eps / gamma
+    return x if return_kspace else idft2(x)
+
+
+# ------------------------------------------- IRLS-direct (Sec. IV, Fig. 2)
+def linear_rows(P: int, Q: int, N1: int, N2: int) -> tuple[np.ndarray, np.ndarray]:
+    """Valid shifts w of the linear lifting: the N1 x N2 support w - a stays inside the
+    P x Q grid (centred k-space coordinates), row-major.  (P-N1+1)(Q-N2+1) of them."""
+    a1, a2 = filter_offsets(N1, N2)
+    w1 = np.arange(a1.max(), P + a1.min())
+    w2 = np.arange(a2.max(), Q + a2.min())
+    W1, W2 = np.meshgrid(w1, w2, indexing="ij")
+    return W1.ravel(), W2.ravel()
+
+
+def lift_linear(xhat: np.ndarray, N1: int, N2: int, M: int) -> np.ndarray:
+    """The lifted matrix without the circular approximation (the IRLS-direct method the
+    paper compares with in Sec. IV / Fig. 2): linear convolutions in all three
+    dimensions.  k-space is taken in centred order (DC at index (P/2, Q/2), i.e.
+    fftshift of the DFT order); rows (n, w) for n = M-1..T-1 and the valid shifts w of
+    ``linear_rows``, columns (m, a) as in ``lift``; entry xc[n-m][w - a].
+    Shape ((T-M+1)(P-N1+1)(Q-N2+1), s)."""
+    T, P, Q = xhat.shape
+    xc = np.fft.fftshift(xhat, axes=(1, 2))
+    a1, a2 = filter_offsets(N1, N2)
+    w1, w2 = linear_rows(P, Q, N1, N2)
+    NN, nw = N1 * N2, w1.size
+    out = np.zeros(((T - M + 1) * nw, M * NN), dtype=np.complex128)
+    for n in range(M - 1, T):
+        rows = slice((n - M + 1) * nw, (n - M + 2) * nw)
+        for m in range(M):
+            for ia in range(NN):
+                out[rows, m * NN + ia] = xc[n - m][w1 - a1[ia], w2 - a2[ia]]
+    return out
+
+
+def lift_linear_adjoint(Y: np.ndarray, T: int, P: int, Q: int, N1: int, N2: int, M: int) -> np.ndarray:
+    """Adjoint of ``lift_linear`` (Frobenius inner product): every entry of Y is added
+    back to the k-space sample it was read from.  Returns [T][P][Q] in DFT order."""
+    a1, a2 = filter_offsets(N1, N2)
+    w1, w2 = linear_rows(P, Q, N1, N2)
+    NN, nw = N1 * N2, w1.size
+    xc = np.zeros((T, P, Q), dtype=np.complex128)
+    for n in range(M - 1, T):
+        rows = slice((n - M + 1) * nw, (n - M + 2) * nw)
+        for m in range(M):
+            for ia in range(NN):
+                np.add.at(xc[n - m], (w1 - a1[ia], w2 - a2[ia]), Y[rows, m * NN + ia])
+    return np.fft.ifftshift(xc, axes=(1, 2))
+
+
+def gram_direct(xhat: np.ndarray, N1: int, N2: int, M: int) -> np.ndarray:
+    """R = T^H T of the linear lifting, formed from the explicit matrix."""
+    X = lift_linear(xhat, N1, N2, M)
+    return X.conj().T @ X
+
+
+def direct_normal_apply(v: np.ndarray, S: np.ndarray, H: np.ndarray, lam: float,
+                        N1: int, N2: int, M: int) -> np.ndarray:
+    """S o v + lam T^*(T(v) H): the normal operator of the least-squares step with the
+    penalty tr(T(v) H T(v)^H) = sum_i alpha_i ||T(v) u_i||^2 of the linear lifting."""
+    T, P, Q = v.shape
+    return S * v + lam * lift_linear_adjoint(lift_linear(v, N1, N2, M) @ H, T, P, Q, N1, N2, M)
+
+
+def irls_direct(b: np.ndarray, S: np.ndarray, N1: int, N2: int, M: int, lam: float,
+                n_irls: int, n_cg: int, p: float = 0.6, gamma: float = 1.4,
+                eps0_frac: float = 0.01, trace: dict | None = None,
+                return_kspace: bool = False) -> np.ndarray:
+    """IRLS-direct: Algorithm 1 with both sub-problems solved on the explicit linear
+    lifting, without the FFT-based approximations (Sec. IV): R = T^H T from the explicit
+    matrix, H = U (Lambda + eps I)^(p/2-1) U^H, n_cg CG iterations with
+    ``direct_normal_apply``, the same eps schedule as ``irls``."""
+    S = S.astype(np.float64)
+    b = S * b.astype(np.complex128)
+    x = b.copy()
+    eps = None
+    for _ in range(n_irls):
+        R = gram_direct(x, N1, N2, M)
+        lamR, U, _ = eig_weights(R, 1.0, p)
+        if eps is None:
+            eps = eps0_frac * float(lamR.max())
+        alpha = (np.maximum(lamR, 0.0) + eps) ** (p / 2.0 - 1.0)
+        H = weight_matrix(U, alpha)
+        cg_trace = [] if trace is not None else None
+        x = cg(lambda v: direct_normal_apply(v, S, H, lam, N1, N2, M), b, x, n_cg, cg_trace)
         if trace is not None:
             trace.setdefault("eps", []).append(eps)
             trace.setdefault("lambda_max", []).append(float(lamR.max()))

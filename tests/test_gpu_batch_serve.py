@@ -81,6 +81,48 @@ def test_batch_equals_alone_and_oracle():
         assert nrmse(out[i], ora) < 1e-4
 
 
+def test_batch_of_the_32_slice_draw_at_full_counts():
+    """The batch workload itself: 32 slices of uneven sizes (96..256 squared, 8..20
+    echoes), filter 9x9x5, 15 outer x 10 CG iterations, in one lock-step batch.  Every
+    slice equals its plain single-plan run bit for bit; the smallest and the median-sized
+    slice match the FP64 oracle at the full counts."""
+    specs = workload.batch_specs(32, seed=11)
+    pbs = [workload.make_problem(name=f"slice{j}", **sp) for j, sp in enumerate(specs)]
+    assert all((pb.n_irls, pb.n_cg) == (15, 10) for pb in pbs)
+    say("batch of the 32-slice draw, 15 x 10")
+    plans = []
+    try:
+        for pb in pbs:
+            T, P, Q = pb.b.shape
+            pl = slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, slrx.make_params(lam=pb.lam, n_irls=15, n_cg=10))
+            pl.set_kspace(pb.b)
+            pl.set_mask(pb.S)
+            plans.append(pl)
+        slrx.run_batch(plans)
+        out = [pl.images() for pl in plans]
+    finally:
+        for pl in plans:
+            pl.close()
+    say("32-slice draw: single-plan runs")
+    for i, pb in enumerate(pbs):
+        T, P, Q = pb.b.shape
+        with slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, slrx.make_params(lam=pb.lam, n_irls=15, n_cg=10)) as pl:
+            pl.set_kspace(pb.b)
+            pl.set_mask(pb.S)
+            pl.run()
+            pl.sync()
+            np.testing.assert_array_equal(out[i], pl.images(), err_msg=f"slice {i} ({pb.b.shape})")
+    sizes = [pb.b.size for pb in pbs]
+    order = np.argsort(sizes, kind="stable")
+    for i in (int(order[0]), int(order[len(order) // 2])):
+        pb = pbs[i]
+        say(f"32-slice draw: slice {i} {pb.b.shape} vs the oracle")
+        ora = oracle.irls(pb.b, pb.S, pb.N1, pb.N2, pb.M, pb.lam, 15, 10)
+        e = nrmse(out[i], ora)
+        print(f"  slice {i} {pb.b.shape}: NRMSE vs oracle {e:.3e}", flush=True)
+        assert e < 1e-4
+
+
 def test_batch_with_uneven_iteration_counts():
     pbs = problems()[:3]
     n_irls = [1, 3, 2]

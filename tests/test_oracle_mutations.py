@@ -66,12 +66,23 @@ VOXEL_MUTATIONS = {
     "voxel_lambda_max": ("lmax = float(np.linalg.eigvalsh(G)[..., -1].max())",
                          "lmax = float(np.linalg.eigvalsh(G)[..., -1].mean())"),
 }
+# mistakes in the IRLS-direct functions (linear lifting), checked against their own pins
+DIRECT_MUTATIONS = {
+    "direct_lift_sign": ("out[rows, m * NN + ia] = xc[n - m][w1 - a1[ia], w2 - a2[ia]]",
+                         "out[rows, m * NN + ia] = xc[n - m][w1 - a1[ia], w2 + a2[ia] - 1]"),
+    "direct_adjoint_frame": ("np.add.at(xc[n - m], (w1 - a1[ia], w2 - a2[ia])",
+                             "np.add.at(xc[n - m - 1], (w1 - a1[ia], w2 - a2[ia])"),
+    "direct_weight_transpose": ("lift_linear(v, N1, N2, M) @ H, T, P, Q, N1, N2, M)",
+                                "lift_linear(v, N1, N2, M) @ H.T, T, P, Q, N1, N2, M)"),
+    "direct_rows_range": ("w1 = np.arange(a1.max(), P + a1.min())", "w1 = np.arange(a1.max(), P + a1.min() - 1)"),
+}
 PIN_FILE = {name: "tests/test_oracle_pins.py" for name in MUTATIONS}
 PIN_FILE.update({name: "tests/test_oracle_giraf.py" for name in GIRAF_MUTATIONS})
 PIN_FILE.update({name: "tests/test_oracle_coils.py" for name in COIL_MUTATIONS})
 PIN_FILE.update({name: "tests/test_oracle_t2.py" for name in T2_MUTATIONS})
 PIN_FILE.update({name: "tests/test_oracle_voxel.py" for name in VOXEL_MUTATIONS})
-ALL = dict(MUTATIONS, **COIL_MUTATIONS, **T2_MUTATIONS, **GIRAF_MUTATIONS, **VOXEL_MUTATIONS)
+PIN_FILE.update({name: "tests/test_oracle_direct.py" for name in DIRECT_MUTATIONS})
+ALL = dict(MUTATIONS, **COIL_MUTATIONS, **T2_MUTATIONS, **GIRAF_MUTATIONS, **VOXEL_MUTATIONS, **DIRECT_MUTATIONS)
 
 
 @pytest.mark.parametrize("name", sorted(ALL))

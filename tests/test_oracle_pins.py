@@ -346,7 +346,7 @@ def test_irls_full_sampling_noiseless_bias_is_order_lambda():
     assert errs[-1] < 1e-3
 
 
-def irls_direct(b, S, N1, N2, M, lam, n_irls, p=0.6, gamma=1.4, eps0_frac=0.01):
+def irls_explicit(b, S, N1, N2, M, lam, n_irls, p=0.6, gamma=1.4, eps0_frac=0.01):
     """IRLS with explicit matrices: explicit T(x)^H T(x), dense eigh, dense normal solve."""
     T, P, Q = b.shape
     b = S * b
@@ -370,6 +370,6 @@ def test_irls_equals_explicit_matrix_irls():
     img = exp_series(rng, T, P, Q, [0.8])
     S = (rng.random((T, P, Q)) < 0.6).astype(np.uint8)
     b = S * (oracle.dft2(img) + 0.01 * crandn(rng, T, P, Q))
-    ref = irls_direct(b, S, N1, N2, M, 0.05, 3)
+    ref = irls_explicit(b, S, N1, N2, M, 0.05, 3)
     out = oracle.irls(b, S, N1, N2, M, 0.05, 3, 300)
     np.testing.assert_allclose(out, ref, atol=1e-8 * np.abs(ref).max())
