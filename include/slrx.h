@@ -111,6 +111,22 @@ typedef struct {
                                   combinable with SLRX_FLAG_GIRAF or SLRX_FLAG_LIBEIGH.  There
                                   is no global Gram matrix: slrx_step_gram and the lam / H
                                   outputs of slrx_step_weights are rejected */
+#define SLRX_FLAG_DIRECT 128u /* IRLS-direct, the method without the FFT-based approximations
+                                 that the paper compares with (Sec. IV, Fig. 2): the lifting
+                                 linear in all three dimensions (k-space in centred order,
+                                 DC at (P/2, Q/2); rows n = M-1..T-1 and the
+                                 (P-N1+1)(Q-N2+1) shifts whose N1 x N2 support lies inside
+                                 the grid), R = T^H T from the explicit lifted matrix
+                                 (complex128) and the least-squares operator
+                                 S + lam T^*(T(.) H) on the explicit lifted matrix of the
+                                 CG direction (complex64), the same eps schedule.  Memory:
+                                 16 + 2 x 8 bytes per lifted-matrix entry
+                                 ((T-M+1)(P-N1+1)(Q-N2+1) x s entries) plus 8 s^2, allocated
+                                 at the first run outside slrx_footprint, and a rocBLAS
+                                 handle.  Single-channel only; not combinable with
+                                 SLRX_FLAG_GIRAF, SLRX_FLAG_HLR_VOXEL or SLRX_FLAG_LIBEIGH;
+                                 servers reject it; the single-step entry points other than
+                                 slrx_step_tdeig reject direct plans */
 /* With SLRX_FLAG_KTIME: time only the classes whose bits are set here (none set:
  * every class).  Each timed region adds two events to the stream. */
 #define SLRX_FLAG_KTIME_CLASS(c) (1u << (16 + (c)))
@@ -134,7 +150,9 @@ enum {
                          coil combination */
   SLRX_K_VOXEL = 11,  /* SLRX_FLAG_HLR_VOXEL: per-pixel Gram matrices, eigen-decompositions
                          and masks, and the eps schedule on their eigenvalues */
-  SLRX_K_NCLASS = 12
+  SLRX_K_DIRECT = 12, /* SLRX_FLAG_DIRECT: the CG of each least-squares step on the explicit
+                         lifting (lifting, GEMM with H, adjoint, vector updates) */
+  SLRX_K_NCLASS = 13
 };
 
 /* Per-run statistics, filled by slrx_get_stats after a completed run. */

@@ -38,9 +38,10 @@ SLRX_FLAG_LIBEIGH = 4
 SLRX_FLAG_GIRAF = 8
 SLRX_FLAG_NO_GRAPH = 32
 SLRX_FLAG_HLR_VOXEL = 64
+SLRX_FLAG_DIRECT = 128
 MAX_IRLS = 256
 KERNEL_CLASSES = ("rows", "cols", "fin", "update", "gram", "tri", "tdeig", "backtr", "filter", "masks", "coil",
-                  "voxel")
+                  "voxel", "direct")
 
 STATUS = {0: "SLRX_OK", -1: "SLRX_EINVAL", -2: "SLRX_ENOMEM", -3: "SLRX_EDEVICE", -4: "SLRX_ESTATE",
           -5: "SLRX_ENUMERIC", -6: "SLRX_EBUSY", -7: "SLRX_ENOTREADY", -8: "SLRX_ECANCELED",
@@ -177,14 +178,16 @@ def default_params() -> Params:
 
 def make_params(lam=1e-3, n_irls=15, n_cg=10, p=0.6, gamma=1.4, eps0_frac=0.01, timing=False,
                 ktime=False, lib_eigh=False, ktime_classes=None, giraf=False, no_graph=False,
-                voxel=False) -> Params:
+                voxel=False, direct=False) -> Params:
     """ktime_classes: names from KERNEL_CLASSES to time (default: all, when ktime is set);
     giraf: the lifting circular along the parameter axis too (SLRX_FLAG_GIRAF);
     no_graph: CG kernels launched one by one instead of a replayed graph (SLRX_FLAG_NO_GRAPH);
-    voxel: the pixel-wise prior HLR-Voxel (SLRX_FLAG_HLR_VOXEL; needs an N1 = N2 = 1 filter)."""
+    voxel: the pixel-wise prior HLR-Voxel (SLRX_FLAG_HLR_VOXEL; needs an N1 = N2 = 1 filter);
+    direct: IRLS-direct on the explicit linear lifting (SLRX_FLAG_DIRECT)."""
     flags = ((SLRX_FLAG_TIMING if timing else 0) | (SLRX_FLAG_KTIME if ktime else 0)
              | (SLRX_FLAG_LIBEIGH if lib_eigh else 0) | (SLRX_FLAG_GIRAF if giraf else 0)
-             | (SLRX_FLAG_NO_GRAPH if no_graph else 0) | (SLRX_FLAG_HLR_VOXEL if voxel else 0))
+             | (SLRX_FLAG_NO_GRAPH if no_graph else 0) | (SLRX_FLAG_HLR_VOXEL if voxel else 0)
+             | (SLRX_FLAG_DIRECT if direct else 0))
     for c in ktime_classes or ():
         flags |= 1 << (16 + KERNEL_CLASSES.index(c))
     return Params(float(lam), float(p), float(gamma), float(eps0_frac), int(n_irls), int(n_cg), flags)

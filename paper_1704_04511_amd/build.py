@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libslrx.so")
-SOURCES = ["k_op.hip", "k_coil.hip", "k_fit.hip", "k_gram.hip", "k_tri.hip", "k_backtr.hip", "k_dc.hip", "steps.hip", "engine.hip", "api.hip", "server.hip", "noalloc.hip", "tune.hip", "k_voxel.hip"]
+SOURCES = ["k_op.hip", "k_coil.hip", "k_fit.hip", "k_gram.hip", "k_tri.hip", "k_backtr.hip", "k_dc.hip", "steps.hip", "engine.hip", "api.hip", "server.hip", "noalloc.hip", "tune.hip", "k_voxel.hip", "k_direct.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

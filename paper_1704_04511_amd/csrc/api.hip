@@ -137,6 +137,11 @@ static slrx_status validate_params(const slrx_params* p) {
 
 // Flags that constrain the dims or each other.
 static slrx_status validate_combo(const slrx_dims& d, const slrx_params& p) {
+  if (p.flags & SLRX_FLAG_DIRECT) {
+    if (p.flags & (SLRX_FLAG_GIRAF | SLRX_FLAG_HLR_VOXEL | SLRX_FLAG_LIBEIGH))
+      return fail(SLRX_EINVAL,
+                  "SLRX_FLAG_DIRECT does not combine with SLRX_FLAG_GIRAF, SLRX_FLAG_HLR_VOXEL or SLRX_FLAG_LIBEIGH");
+  }
   if (p.flags & SLRX_FLAG_HLR_VOXEL) {
     if (d.N1 != 1 || d.N2 != 1)
       return fail(SLRX_EINVAL, "SLRX_FLAG_HLR_VOXEL needs N1 = N2 = 1 (got %dx%d)", d.N1, d.N2);
@@ -389,6 +394,8 @@ extern "C" void slrx_plan_destroy(slrx_plan* pl) {
     if (pl->ev_iter[i]) (void)hipEventDestroy(pl->ev_iter[i]);
   cg_graph_reset(pl);
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  if (pl->dblas) rocblas_destroy_handle(pl->dblas);
+  if (pl->direct_mem) (void)hipFree(pl->direct_mem);
   if (pl->blas) rocblas_destroy_handle(pl->blas);
   if (pl->blas_ws) (void)hipFree(pl->blas_ws);
   if (pl->coil_mem) (void)hipFree(pl->coil_mem);
@@ -449,6 +456,7 @@ extern "C" slrx_status slrx_set_coils(slrx_plan* pl, int32_t ncoils, const void*
     return fail(SLRX_EINVAL, "ncoils=%d out of range [0,%d]", (int)ncoils, SLRX_MAX_COILS);
   if (mem != SLRX_MEM_HOST && mem != SLRX_MEM_DEVICE) return fail(SLRX_EINVAL, "bad memory kind %d", (int)mem);
   if (ncoils > 0 && (!C || !b)) return fail(SLRX_EINVAL, "coil maps or coil data pointer is NULL");
+  if (ncoils > 0 && pl->direct()) return fail(SLRX_EINVAL, "SLRX_FLAG_DIRECT is single-channel only");
   const slrx_dims& d = pl->d;
   const size_t V = pl->vol(), pq = (size_t)d.P * d.Q;
   if (ncoils != pl->ncoils_cap) {
@@ -538,7 +546,9 @@ extern "C" slrx_status slrx_set_params(slrx_plan* pl, const slrx_params* prm) {
 }
 
 slrx_status slrx::enqueue_run(slrx_plan* pl) {
+  if (pl->direct() && pl->ncoils > 0) return fail(SLRX_EINVAL, "SLRX_FLAG_DIRECT is single-channel only");
   STCHK(prepare(pl));
+  if (pl->direct()) STCHK(direct_setup(pl));
   const bool timing = (pl->prm.flags & SLRX_FLAG_TIMING) != 0;
   const int nirls = pl->prm.n_irls;
   pl->ktime = (pl->prm.flags & SLRX_FLAG_KTIME) != 0;
@@ -555,7 +565,13 @@ slrx_status slrx::enqueue_run(slrx_plan* pl) {
   HIPCHK(hipEventRecord(pl->ev_run[0], pl->stream));
   for (int it = 0; it < nirls; ++it) {
     if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it], pl->stream));
-    if (pl->voxel()) {  // the whole per-pixel weight update counts as the weights phase
+    if (pl->direct()) {
+      STCHK(step_direct_gram(pl));
+      if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 1], pl->stream));
+      STCHK(step_eigh(pl, it));
+      if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 2], pl->stream));
+      STCHK(step_direct_weights(pl, it, it == 0, pl->prm.gamma));
+    } else if (pl->voxel()) {  // the whole per-pixel weight update counts as the weights phase
       if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 1], pl->stream));
       if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 2], pl->stream));
       STCHK(step_voxel(pl, it, it == 0, pl->prm.gamma));
@@ -567,7 +583,7 @@ slrx_status slrx::enqueue_run(slrx_plan* pl) {
       STCHK(step_weights(pl, it, it == 0, pl->prm.gamma));
     }
     if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it + 3], pl->stream));
-    STCHK(run_cg(pl, pl->prm.n_cg, it));
+    STCHK(pl->direct() ? run_cg_direct(pl, pl->prm.n_cg, it) : run_cg(pl, pl->prm.n_cg, it));
   }
   if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * nirls], pl->stream));
   HIPCHK(hipEventRecord(pl->ev_run[1], pl->stream));
@@ -779,6 +795,7 @@ static slrx_status ensure_prepared(slrx_plan* pl) {
 extern "C" slrx_status slrx_step_gram(slrx_plan* pl, void* R_out, slrx_mem mem) {
   PlanScope scope(pl);
   if (pl && pl->voxel()) return fail(SLRX_EINVAL, "SLRX_FLAG_HLR_VOXEL has no global Gram matrix");
+  if (pl && pl->direct()) return fail(SLRX_EINVAL, "SLRX_FLAG_DIRECT plans run whole reconstructions only");
   STCHK(ensure_prepared(pl));
   STCHK(step_gram(pl, true));
   const size_t s = (size_t)pl->d.N1 * pl->d.N2 * pl->d.M;
@@ -815,6 +832,7 @@ extern "C" slrx_status slrx_step_weights(slrx_plan* pl, double eps, double* lam_
   PlanScope scope(pl);
   if (!(eps > 0.0) || !std::isfinite(eps)) return fail(SLRX_EINVAL, "eps must be finite and > 0");
   if (pl && pl->voxel()) return step_weights_voxel(pl, eps, lam_out, H_out, E_out, mem);
+  if (pl && pl->direct()) return fail(SLRX_EINVAL, "SLRX_FLAG_DIRECT plans run whole reconstructions only");
   STCHK(ensure_prepared(pl));
   STCHK(step_gram(pl));
   STCHK(step_eigh(pl, -1));
@@ -869,6 +887,7 @@ extern "C" slrx_status slrx_step_tdeig(slrx_plan* pl, const double* D, const dou
 
 extern "C" slrx_status slrx_step_apply(slrx_plan* pl, const void* E, const void* v, void* out, slrx_mem mem) {
   PlanScope scope(pl);
+  if (pl && pl->direct()) return fail(SLRX_EINVAL, "SLRX_FLAG_DIRECT plans run whole reconstructions only");
   STCHK(ensure_prepared(pl));
   const slrx_dims& d = pl->d;
   const size_t W = (size_t)d.M * (d.M + 1) / 2;
@@ -884,6 +903,7 @@ extern "C" slrx_status slrx_step_apply(slrx_plan* pl, const void* E, const void*
 extern "C" slrx_status slrx_step_cg(slrx_plan* pl, const void* E, int32_t n_cg) {
   PlanScope scope(pl);
   if (n_cg < 0 || n_cg > kMaxCg) return fail(SLRX_EINVAL, "n_cg out of range");
+  if (pl && pl->direct()) return fail(SLRX_EINVAL, "SLRX_FLAG_DIRECT plans run whole reconstructions only");
   STCHK(ensure_prepared(pl));
   pl->ktime = false;
   const slrx_dims& d = pl->d;

@@ -178,7 +178,9 @@ static slrx_status group_reserve(BatchEig& be, int n, int nb, EigGroup*& out) {
 }
 
 slrx_status slrx::engine_begin(slrx_plan* pl) {
+  if (pl->direct() && pl->ncoils > 0) return fail(SLRX_EINVAL, "SLRX_FLAG_DIRECT is single-channel only");
   STCHK(prepare(pl));
+  if (pl->direct()) STCHK(direct_setup(pl));
   pl->ktime = false;
   for (int c = 0; c < SLRX_K_NCLASS; ++c) pl->kused[c] = 0;
   HIPCHK(hipMemsetAsync(pl->info, 0, kInfoEntries * sizeof(rocblas_int), pl->stream));
@@ -201,6 +203,13 @@ static slrx_status step_single(slrx_plan* pl) {
   const int it = pl->it_next;
   if (pl->voxel()) {
     STCHK(step_voxel(pl, it, it == 0, pl->prm.gamma));
+  } else if (pl->direct()) {
+    STCHK(step_direct_gram(pl));
+    STCHK(step_eigh(pl, it));
+    STCHK(step_direct_weights(pl, it, it == 0, pl->prm.gamma));
+    STCHK(run_cg_direct(pl, pl->prm.n_cg, it));
+    pl->it_next = it + 1;
+    return SLRX_OK;
   } else {
     STCHK(step_gram(pl));
     STCHK(step_eigh(pl, it));
@@ -215,7 +224,7 @@ slrx_status slrx::engine_step(const std::vector<slrx_plan*>& plans, BatchEig& be
   std::map<int, std::vector<slrx_plan*>> groups;
   for (slrx_plan* pl : plans) {
     if (pl->it_next >= pl->prm.n_irls) continue;
-    if (pl->lib_eigh() || pl->voxel()) STCHK(step_single(pl));
+    if (pl->lib_eigh() || pl->voxel() || pl->direct()) STCHK(step_single(pl));
     else groups[pl->s()].push_back(pl);
   }
   bool used = false;

@@ -186,6 +186,27 @@ struct VoxelEpsArgs {
 };
 hipError_t launch_voxel_eps(const VoxelEpsArgs& a, hipStream_t s);
 
+// IRLS-direct (k_direct.hip): the explicit linear lifting, its adjoint and CG glue.
+struct DirectArgs {
+  int P, Q, T, N1, N2, M;
+  int a1min, a2min, a1max, a2max;  // filter offsets: a in [amin, amax] per axis
+  int nw1, nw2;                    // valid shifts per axis
+  long rows;                       // (T-M+1) nw1 nw2 rows of the lifted matrix
+  double lam;
+};
+DirectArgs direct_args(int P, int Q, int T, int N1, int N2, int M, double lam);
+int direct_blocks(long V);  // blocks (and partials) of the adjoint pass for V samples
+// X = T(x), row-major rows x s (complex128 or complex64)
+hipError_t launch_dlift64(const DirectArgs& a, const float2* x, double2* X, hipStream_t s);
+hipError_t launch_dlift32(const DirectArgs& a, const float2* x, float2* X, hipStream_t s);
+// out = S o v + lam T^*(Y) (init: y - that, partials <out,out>, flag cleared); else partials <v,out>
+hipError_t launch_dadj(const DirectArgs& a, const float2* Y, const float2* v, const uint8_t* S, const float2* y,
+                       float2* out, int init, double* part, int* flag, hipStream_t s);
+// p = r + beta p with beta from the partials of rr_k and rr_hist[k-1]; records rr_hist[k]
+hipError_t launch_dpupdate(long n, const float2* r, float2* p, const double* part, int npart, double* rr_hist, int k,
+                           hipStream_t s);
+hipError_t launch_hf(long n, const double* re, const double* im, float2* out, hipStream_t s);
+
 struct WeightArgs {
   int s;
   const double* lamv;       // eigenvalues, ascending

@@ -86,6 +86,16 @@ struct slrx_plan {
   float2 *Ct = nullptr, *Bc = nullptr, *Yc = nullptr, *rho = nullptr;
   double2 *Yc64 = nullptr, *dco = nullptr;
 
+  // IRLS-direct (SLRX_FLAG_DIRECT): one allocation, made at the first direct run,
+  // holding the lifted matrix of the iterate (complex128, for the Gram matrix), the
+  // lifted matrix of the CG direction and its product with H (complex64), and H
+  // (complex64); its own rocBLAS handle for the two plain GEMMs
+  void* direct_mem = nullptr;
+  size_t direct_bytes = 0;
+  double2* X64 = nullptr;
+  float2 *Xv = nullptr, *Yd = nullptr, *Hf = nullptr;
+  rocblas_handle dblas = nullptr;
+
   // rocSOLVER handle and workspace of the library eigensolver, a test reference
   // selected by SLRX_FLAG_LIBEIGH; created at its first use
   rocblas_handle blas = nullptr;
@@ -120,6 +130,8 @@ struct slrx_plan {
   bool lib_eigh() const;
   // the pixel-wise prior (HLR-Voxel) instead of the multi-fold Toeplitz lifting
   bool voxel() const { return (prm.flags & SLRX_FLAG_HLR_VOXEL) != 0; }
+  // IRLS-direct: the explicit linear lifting instead of the FFT-based approximations
+  bool direct() const { return (prm.flags & SLRX_FLAG_DIRECT) != 0; }
 };
 
 namespace slrx {
@@ -163,6 +175,12 @@ slrx_status step_weights(slrx_plan* pl, int it, bool first, double gamma, const 
 // Weight update of the pixel-wise prior (SLRX_FLAG_HLR_VOXEL), in place of
 // step_gram, step_eigh and step_weights.
 slrx_status step_voxel(slrx_plan* pl, int it, bool first, double gamma);
+// IRLS-direct (SLRX_FLAG_DIRECT): the Gram matrix of the explicit lifting into Aw,
+// H from the eigenpairs, and the CG on the explicit operator.
+slrx_status direct_setup(slrx_plan* pl);
+slrx_status step_direct_gram(slrx_plan* pl);
+slrx_status step_direct_weights(slrx_plan* pl, int it, bool first, double gamma);
+slrx_status run_cg_direct(slrx_plan* pl, int n_cg, int it);
 slrx_status apply_op(slrx_plan* pl, const float2* v, float2* out, bool init, double* part);
 slrx_status coil_pass(slrx_plan* pl);
 // graph: replay the CG body from a captured graph where allowed (plans run

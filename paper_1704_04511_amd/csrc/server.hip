@@ -397,6 +397,7 @@ extern "C" slrx_status slrx_submit(slrx_server* s, slrx_plan* plan, uint64_t* ti
   if (!s || !plan || !ticket) return fail(SLRX_EINVAL, "NULL argument");
   if (!(plan->has_b || plan->ncoils > 0) || !plan->has_S) return fail(SLRX_ESTATE, "plan has no k-space or mask");
   if (plan->lib_eigh()) return fail(SLRX_EINVAL, "the library eigensolver is a test reference and is not served");
+  if (plan->direct()) return fail(SLRX_EINVAL, "IRLS-direct is a comparison method and is not served");
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->busy.count(plan)) return fail(SLRX_EBUSY, "plan is already queued or running on this server");
@@ -430,6 +431,10 @@ extern "C" slrx_status slrx_submit_data(slrx_server* s, const slrx_dims* dims, c
   if (r->prm.flags & SLRX_FLAG_LIBEIGH) {
     delete r;
     return fail(SLRX_EINVAL, "the library eigensolver is a test reference and is not served");
+  }
+  if (r->prm.flags & SLRX_FLAG_DIRECT) {
+    delete r;
+    return fail(SLRX_EINVAL, "IRLS-direct is a comparison method and is not served");
   }
   r->b.assign((const float2*)b, (const float2*)b + V);
   r->S.assign(S, S + V);

@@ -4,6 +4,7 @@
 // the masked data (the right-hand side A^H b of eq. "eq:grad_ls"), img the
 // images F^-1 x used by the Gram matrix and the output, Et the penalty masks.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <cmath>
@@ -348,6 +349,131 @@ slrx_status slrx::step_voxel(slrx_plan* pl, int it, bool first, double gamma) {
     ea.mode = 2;
     HIPCHK(launch_voxel_eps(ea, pl->stream));
   }
+  return SLRX_OK;
+}
+
+// IRLS-direct buffers (k_direct.hip) for the current dims: allocated at the first
+// direct run and grown when a later run needs more; a rocBLAS handle of its own.
+slrx_status slrx::direct_setup(slrx_plan* pl) {
+  const slrx_dims& d = pl->d;
+  const DirectArgs da = direct_args(d.P, d.Q, d.T, d.N1, d.N2, d.M, 0.0);
+  const size_t s = (size_t)pl->s();
+  auto up = [](size_t n) { return (n + 255) & ~(size_t)255; };
+  const size_t b64 = up((size_t)da.rows * s * 16), b32 = up((size_t)da.rows * s * 8), bh = up(s * s * 8);
+  const size_t need = b64 + 2 * b32 + bh;
+  if (need > pl->direct_bytes) {
+    if (pl->direct_mem) HIPCHK(hipFree(pl->direct_mem));
+    pl->direct_mem = nullptr;
+    pl->direct_bytes = 0;
+    if (hipMalloc(&pl->direct_mem, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SLRX_ENOMEM, "IRLS-direct buffers (%zu bytes: lifted matrices of %ld x %zu)", need, da.rows, s);
+    }
+    pl->direct_bytes = need;
+  }
+  char* m = (char*)pl->direct_mem;
+  pl->X64 = (double2*)m;
+  pl->Xv = (float2*)(m + b64);
+  pl->Yd = (float2*)(m + b64 + b32);
+  pl->Hf = (float2*)(m + b64 + 2 * b32);
+  if (!pl->dblas) {
+    if (rocblas_create_handle(&pl->dblas) != rocblas_status_success)
+      return fail(SLRX_EDEVICE, "rocblas_create_handle failed");
+  }
+  if (rocblas_set_stream(pl->dblas, pl->stream) != rocblas_status_success)
+    return fail(SLRX_EDEVICE, "rocblas_set_stream failed");
+  return SLRX_OK;
+}
+
+// R = X^H X of the explicit linear lifting X of the iterate (complex128), row-major
+// into Aw for the eigen-decomposition chain: X is stored row-major (rows x s), i.e.
+// column-major s x rows, and the column-major product X_c X_c^H is R^T, whose
+// column-major layout is R's row-major one.
+slrx_status slrx::step_direct_gram(slrx_plan* pl) {
+  const slrx_dims& d = pl->d;
+  KTimer kt(pl, SLRX_K_GRAM);
+  const DirectArgs da = direct_args(d.P, d.Q, d.T, d.N1, d.N2, d.M, 0.0);
+  const int s = pl->s();
+  HIPCHK(launch_dlift64(da, pl->x, pl->X64, pl->stream));
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  const rocblas_status st = rocblas_zgemm(pl->dblas, rocblas_operation_none, rocblas_operation_conjugate_transpose, s,
+                                          s, (rocblas_int)da.rows, &one, (const rocblas_double_complex*)pl->X64, s,
+                                          (const rocblas_double_complex*)pl->X64, s, &zero,
+                                          (rocblas_double_complex*)pl->Aw, s);
+  if (st != rocblas_status_success) return fail(SLRX_EDEVICE, "rocblas_zgemm failed (status %d)", (int)st);
+  return SLRX_OK;
+}
+
+// H = U (Lambda + eps I)^(p/2-1) U^H from the eigenpairs (the eps schedule and the
+// filter product of the main method), rounded to complex64 for the CG operator.
+slrx_status slrx::step_direct_weights(slrx_plan* pl, int it, bool first, double gamma) {
+  const int s = pl->s();
+  KTimer kt(pl, SLRX_K_FILTER);
+  WeightArgs wa{};
+  wa.s = s;
+  wa.lamv = pl->lam;
+  wa.U = pl->UZ;
+  wa.VT = pl->VT;
+  wa.eps = pl->scal;
+  wa.lam_max_out = it >= 0 ? pl->stats + SLRX_MAX_IRLS + it : nullptr;
+  wa.eps_out = it >= 0 ? pl->stats + it : nullptr;
+  wa.first = first ? 1 : 0;
+  wa.eps0_frac = pl->prm.eps0_frac;
+  wa.gamma = gamma;
+  wa.p = pl->prm.p;
+  HIPCHK(launch_weights(wa, pl->stream));
+  HIPCHK(launch_filter_product(s, pl->VT, pl->Hre, pl->Him, pl->stream));
+  HIPCHK(launch_hf((long)s * s, pl->Hre, pl->Him, pl->Hf, pl->stream));
+  return SLRX_OK;
+}
+
+// A v = S o v + lam T^*(T(v) H) on the explicit lifting; init: out = bm - A v.
+static slrx_status direct_apply(slrx_plan* pl, const float2* v, float2* out, bool init, double* part) {
+  const slrx_dims& d = pl->d;
+  const DirectArgs da = direct_args(d.P, d.Q, d.T, d.N1, d.N2, d.M, pl->prm.lambda);
+  const int s = pl->s();
+  HIPCHK(launch_dlift32(da, v, pl->Xv, pl->stream));
+  // row-major Y = Xv H: column-major Y^T = H^T Xv^T, and the row-major layouts of H
+  // and Xv are the column-major layouts of H^T and Xv^T
+  const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
+  const rocblas_status st = rocblas_cgemm(pl->dblas, rocblas_operation_none, rocblas_operation_none, s,
+                                          (rocblas_int)da.rows, s, &one, (const rocblas_float_complex*)pl->Hf, s,
+                                          (const rocblas_float_complex*)pl->Xv, s, &zero,
+                                          (rocblas_float_complex*)pl->Yd, s);
+  if (st != rocblas_status_success) return fail(SLRX_EDEVICE, "rocblas_cgemm failed (status %d)", (int)st);
+  HIPCHK(launch_dadj(da, pl->Yd, v, pl->S, pl->bm, out, init ? 1 : 0, part, pl->flag, pl->stream));
+  return SLRX_OK;
+}
+
+// n_cg CG iterations on the explicit operator, warm-started at x (the arithmetic
+// of the CG of run_cg: same scalars, same stop rule).
+slrx_status slrx::run_cg_direct(slrx_plan* pl, int n_cg, int it) {
+  const long V = (long)pl->vol();
+  const int nadj = direct_blocks(V);
+  const int nupd = update_blocks(V);
+  KTimer kt(pl, SLRX_K_DIRECT);
+  STCHK(direct_apply(pl, pl->x, pl->r, true, pl->partA));
+  for (int k = 0; k < n_cg; ++k) {
+    HIPCHK(launch_dpupdate(V, pl->r, pl->p, k == 0 ? pl->partA : pl->partB, k == 0 ? nadj : nupd, pl->rr_hist, k,
+                           pl->stream));
+    STCHK(direct_apply(pl, pl->p, pl->q, false, pl->partA));
+    UpdArgs ua{};
+    ua.n = V;
+    ua.x = pl->x;
+    ua.r = pl->r;
+    ua.p = pl->p;
+    ua.q = pl->q;
+    ua.partA = pl->partA;
+    ua.nA = nadj;
+    ua.rr_hist = pl->rr_hist;
+    ua.k = k;
+    ua.partB = pl->partB;
+    ua.flag = pl->flag;
+    HIPCHK(launch_update(ua, pl->stream));
+  }
+  if (it >= 0)
+    HIPCHK(launch_store_sum(n_cg == 0 ? pl->partA : pl->partB, n_cg == 0 ? nadj : nupd,
+                            pl->stats + 2 * SLRX_MAX_IRLS + it, pl->stream));
   return SLRX_OK;
 }
 

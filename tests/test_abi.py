@@ -80,6 +80,9 @@ def test_invalid_params_rejected(kw, msg):
     ((64, 64, 8, 3, 1, 3), dict(voxel=True), "N1 = N2 = 1"),
     ((64, 64, 8, 1, 1, 3), dict(voxel=True, giraf=True), "does not combine"),
     ((64, 64, 8, 1, 1, 3), dict(voxel=True, lib_eigh=True), "does not combine"),
+    ((64, 64, 8, 3, 3, 3), dict(direct=True, giraf=True), "does not combine"),
+    ((64, 64, 8, 1, 1, 3), dict(direct=True, voxel=True), "does not combine"),
+    ((64, 64, 8, 3, 3, 3), dict(direct=True, lib_eigh=True), "does not combine"),
 ])
 def test_voxel_flag_constraints(dims, kw, msg):
     with pytest.raises(slrx.SlrxError) as ei:
