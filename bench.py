@@ -695,6 +695,146 @@ def bench_calib(args) -> int:
     return 0
 
 
+# Kernel classes of the bench's rooflines -> the kernel names they cover and the kernel
+# whose dispatch count defines "one launch" (None: one launch = one decomposition,
+# counted by the tridiagonalisation's single-workgroup tail).
+PROFILE_CLASSES = {
+    "rows": (("k_rows_t",), "k_rows_t"),
+    "cols": (("k_cols_pen",), "k_cols_pen"),
+    "fin": (("k_rows_fin",), "k_rows_fin"),
+    "update": (("k_update",), "k_update"),
+    "gram": (("k_gram_",), "k_gram_assemble"),
+    "tri": (("k_tri_",), "k_tri_col"),
+    "tdeig": (("k_dc_",), None),
+    "backtr": (("k_bt_",), None),
+    "filter": (("k_spec_", "k_eps", "k_weights", "k_filter_product"), None),
+    "masks": (("k_mask_", "k_diagsum"), None),
+}
+
+
+def _kernel_short(name: str) -> str:
+    import re
+    name = re.sub(r"^void ", "", name)
+    name = re.sub(r"\(anonymous namespace\)::", "", name)
+    depth, out = 0, []
+    for ch in name:  # drop the argument list, keep template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def _csv_rows(root: str, sub: str, suffix: str):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(root, sub, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {os.path.join(root, sub)}")
+    rows = []
+    for fn in files:
+        with open(fn, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def _counter_per_kernel(root: str, sub: str):
+    """{kernel: [dispatches, summed counter KiB]} from a rocprofv3 --pmc csv run."""
+    agg = {}
+    for r in _csv_rows(root, sub, "counter_collection.csv"):
+        k = _kernel_short(r["Kernel_Name"])
+        a = agg.setdefault(k, [0, 0.0])
+        a[0] += 1
+        a[1] += float(r["Counter_Value"])
+    return agg
+
+
+def summarize_profiles(args) -> int:
+    """Write profiles/c3_kernel_trace.txt, c3_hbm_counters.txt and c3_traffic.json from
+    the rocprofv3 csv output of the runs named in their headers (no GPU needed)."""
+    root = args.prof_root
+    prof = os.path.join(ROOT, "profiles")
+    pre = "cd /tmp && export TMPDIR=/tmp && cd /root/repo && "
+    c3 = "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-extras"
+    c3_pmc = "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --n-irls 2"
+    calib = "python3 bench.py --workload calib --calib-mb 256"
+    # kernel traces: (folder, file, what, command)
+    traces = [
+        ("prof_c3", "c3_kernel_trace.txt", "256x256x20 workload (filter 15x15x5, s=1125; 20 outer x 15 CG): 1 "
+         "warm-up, 1 timed and 1 fully instrumented reconstruction (divide totals by 3 per reconstruction)", c3),
+        ("prof_hlr", "hlr_kernel_trace.txt", "256x256x20 data under HLR-Voxel (1x1x5 per pixel; 20 outer x 15 "
+         "CG): 1 warm-up, 1 timed and 1 fully instrumented reconstruction (divide totals by 3)",
+         "python3 bench.py --workload hlr --steps 1 --warmup 1 --no-cpu-baseline"),
+        ("prof_direct", "direct_kernel_trace.txt", "proposed vs IRLS-direct on the 64x64x8 (5x5x3) and "
+         "128x128x16 (9x9x5) workloads, 15 x 10 each: per workload and method 1 warm-up and 1 timed "
+         "reconstruction", "python3 bench.py --workload direct --steps 1 --warmup 1 --no-cpu-baseline"),
+    ]
+    for sub, fname, what, cmd in traces:
+        if not os.path.isdir(os.path.join(root, sub)):
+            continue
+        st = _csv_rows(root, sub, "kernel_stats.csv")
+        tot = sum(float(r["TotalDurationNs"]) for r in st)
+        lines = [f"# Kernel trace, {what}",
+                 f"# command: {pre}rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/{sub} -o run -- {cmd}",
+                 "# durations from the kernel trace (rocprofv3 kernel_stats)",
+                 f"{'kernel':<72} {'calls':>8} {'total_ms':>10} {'avg_us':>9} {'pct':>6}"]
+        for r in sorted(st, key=lambda r: -float(r["TotalDurationNs"])):
+            ms = float(r["TotalDurationNs"]) * 1e-6
+            lines.append(f"{_kernel_short(r['Name'])[:72]:<72} {int(r['Calls']):>8} {ms:>10.3f} "
+                         f"{float(r['AverageNs']) * 1e-3:>9.2f} {100 * ms * 1e6 / tot:>6.2f}")
+        with open(os.path.join(prof, fname), "w") as f:
+            f.write("\n".join(lines) + "\n")
+    # counters, calibrated by the copy
+    fetch = _counter_per_kernel(root, "pmc_fetch")
+    write = _counter_per_kernel(root, "pmc_write")
+    cf = _counter_per_kernel(root, "pmc_copy_fetch")
+    cw = _counter_per_kernel(root, "pmc_copy_write")
+    copy_k = max(cf, key=lambda k: cf[k][1] / cf[k][0])  # the copy reads; the buffer fill before it does not
+    kib = args.calib_mb * 1024.0
+    f_copy, w_copy = cf[copy_k][1] / cf[copy_k][0], cw[copy_k][1] / cw[copy_k][0]
+    sf, sw = kib / f_copy, kib / w_copy
+    lines = ["# HBM traffic per dispatch, 256x256x20 workload (filter 15x15x5), two outer iterations",
+             "# commands (each its own run):",
+             f"#   {pre}rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o run -- {c3_pmc}",
+             f"#   {pre}rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o run -- {c3_pmc}",
+             f"# calibration: a {args.calib_mb} MiB device copy ({copy_k}) under the same counters:",
+             f"#   {pre}rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_copy_fetch -o run -- {calib}",
+             f"#   {pre}rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_copy_write -o run -- {calib}",
+             f"# copy: FETCH_SIZE {f_copy:.1f} KiB, WRITE_SIZE {w_copy:.1f} KiB for {kib:.0f} KiB moved each way "
+             f"-> scale fetch x{sf:.3f}, write x{sw:.3f}",
+             f"# summaries written by: python3 bench.py --workload profiles --prof-root gpurun_out",
+             f"{'kernel':<52} {'n':>6} {'fetch_KiB':>11} {'write_KiB':>11} {'scaled_MB':>10}"]
+    per = {}
+    for k in fetch:
+        n = fetch[k][0]
+        fk = fetch[k][1] / n
+        wk = write.get(k, [n, 0.0])[1] / max(write.get(k, [n, 0.0])[0], 1)
+        per[k] = (n, fk, wk, (fk * sf + wk * sw) * 1024.0)
+    for k, (n, fk, wk, b) in sorted(per.items(), key=lambda kv: -kv[1][0] * kv[1][3]):
+        lines.append(f"{k[:52]:<52} {n:>6} {fk:>11.1f} {wk:>11.1f} {b / 1e6:>10.3f}")
+    with open(os.path.join(prof, "c3_hbm_counters.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    ndec = sum(v[0] for k, v in per.items() if k.startswith("slrx::k_tri_tail") or k.startswith("k_tri_tail"))
+    bpl = {}
+    for cls, (prefixes, main) in PROFILE_CLASSES.items():
+        names = [k for k in per if any(k.split("::")[-1].startswith(p) for p in prefixes)]
+        total = sum(per[k][0] * per[k][3] for k in names)
+        if main is None:
+            units = ndec
+        else:
+            units = sum(per[k][0] for k in names if k.split("::")[-1].startswith(main))
+        if names and units:
+            bpl[cls] = total / units
+    rec = {"source_sha256": kernel_source_hash(), "workload": "256x256x20 filter 15x15x5",
+           "scale_fetch": sf, "scale_write": sw, "bytes_per_launch": bpl}
+    with open(os.path.join(prof, "c3_traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps({"written": sorted(os.listdir(prof)), "bytes_per_launch": bpl}))
+    return 0
+
+
 def copy_bandwidth_gbs() -> float:
     """Device-to-device copy of 1 GiB (read + write counted), best of 5, torch's copy kernel."""
     import torch
@@ -723,7 +863,8 @@ def main() -> int:
     ap.add_argument("--cpu-outer", type=int, default=3, help="outer iterations in the CPU oracle sample")
     ap.add_argument("--n-irls", type=int, default=None,
                     help="override the outer iteration count (profiling runs only; changes the workload)")
-    ap.add_argument("--workload", choices=("c3", "c2", "mc", "hlr", "direct", "batch", "serve", "calib"),
+    ap.add_argument("--workload", choices=("c3", "c2", "mc", "hlr", "direct", "batch", "serve", "calib",
+                                           "profiles"),
                     default="c3",
                     help="c3: the 256x256x20 headline line (default); c2: 128x128x16 with T2 maps; "
                          "mc: 12-coil 128x128x12; hlr: the 256x256x20 data under HLR-Voxel; direct: "
@@ -731,6 +872,8 @@ def main() -> int:
                          "calib: the plain copy that calibrates the HBM counters")
     ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
     ap.add_argument("--calib-mb", type=int, default=256, help="calib: MiB copied per launch")
+    ap.add_argument("--prof-root", default="gpurun_out",
+                    help="profiles: folder holding the rocprofv3 csv output of the runs the summaries name")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline only: skip the serving and batch measurements (profiling runs)")
     args = ap.parse_args()
@@ -738,6 +881,8 @@ def main() -> int:
         print(json.dumps({"error": "this build measures one GPU (every box here has one); --gpus must be 1",
                           "gpus_requested": args.gpus}))
         return 2
+    if args.workload == "profiles":
+        return summarize_profiles(args)
     if args.workload == "calib":
         return bench_calib(args)
     if args.workload == "batch":
