@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
 // k0..n-1) is small enough for the LDS of one workgroup, so its columns need
 // only block barriers instead of launches.  First the pending update of
 // reflector k0-1 is applied to the block, then each column is reduced as in
-// k_tri_step (same reflector convention, same outputs), the rank-2 update
+// k_tri_col (same reflector convention, same outputs), the rank-2 update
 // applied to the whole block.  The outputs are kept in LDS and written at the
 // end: a barrier waits for the wave's outstanding stores.
 constexpr int kTriTail = 64;
