@@ -377,6 +377,15 @@ slrx_status slrx_apply_noalloc(const slrx_dims* dims, double lambda, uint32_t fl
                                const void* E, const void* v, void* out, void* hip_stream);
 
 const char* slrx_status_str(slrx_status s);
+
+/* Test hook (fault injection): the n-th device allocation of the library from now
+ * on (0 = the next one) fails as if the device were out of memory, without
+ * allocating; the call that made it returns SLRX_ENOMEM and leaves the object
+ * it was allocating for unchanged or destroyed.  n < 0 switches it off.  The
+ * environment variable SLRX_FAULT_ALLOC=n does the same from the first
+ * allocation of the process.  Other environment variables: SLRX_LOG (print every
+ * failure to stderr), SLRX_TUNE_CACHE (the tuner's cache file). */
+void slrx_fault_alloc(int32_t n);
 /* Message of the last failed call on `plan`, or of the calling thread's last
  * failed call when plan is NULL ("" if none).  Valid until the next call. */
 const char* slrx_last_error(const slrx_plan* plan);

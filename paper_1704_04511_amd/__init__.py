@@ -26,7 +26,8 @@ __all__ = [
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libslrx.so")
+# SLRX_LIBRARY: another build of the library (e.g. the host-sanitizer build the tests make)
+_LIB_PATH = os.environ.get("SLRX_LIBRARY") or os.path.join(_HERE, "libslrx.so")
 _lib = None
 _lock = threading.Lock()
 
@@ -94,6 +95,7 @@ _P = ctypes.c_void_p
 _I = ctypes.c_int
 _SIGS = {
     "slrx_default_params": (None, [ctypes.POINTER(Params)]),
+    "slrx_fault_alloc": (None, [ctypes.c_int32]),
     "slrx_validate": (_I, [ctypes.POINTER(Dims), ctypes.POINTER(Params)]),
     "slrx_footprint": (ctypes.c_size_t, [ctypes.POINTER(Dims)]),
     "slrx_plan_create": (_I, [ctypes.POINTER(Dims), ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]),

@@ -64,7 +64,8 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     link = ["g++", "-shared", "-o", tmp, *objs,
             "-L", tlib, "-l:libamdhip64.so", "-l:librocsolver.so", "-l:librocblas.so",
-            f"-Wl,-rpath,{tlib}", "-Wl,--no-undefined", "-lpthread"]
+            "-L", os.path.join(rocm_path(), "lib"), "-l:librocprofiler-sdk-roctx.so",
+            f"-Wl,-rpath,{tlib}", f"-Wl,-rpath,{os.path.join(rocm_path(), 'lib')}", "-Wl,--no-undefined", "-lpthread"]
     _run(link)
     os.replace(tmp, LIB)
     if verbose:

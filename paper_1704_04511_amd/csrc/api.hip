@@ -4,6 +4,7 @@
 // Hermitian eigensolver).
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <rocsolver/rocsolver.h>
 
 #include <cmath>
@@ -11,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <cstdlib>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -39,7 +41,37 @@ slrx_status slrx::fail(slrx_status st, const char* fmt, ...) {
   va_end(ap);
   g_last_error = buf;
   if (g_cur_plan) g_cur_plan->last_error = buf;
+  static const bool log = std::getenv("SLRX_LOG") != nullptr;  // every failure to stderr
+  if (log) std::fprintf(stderr, "[slrx] %s: %s\n", slrx_status_str(st), buf);
   return st;
+}
+
+// ------------------------------------------------------------ allocation
+// Every device allocation of the library goes through dev_malloc.  Fault
+// injection for tests: SLRX_FAULT_ALLOC=n (read at the first allocation) or
+// slrx_fault_alloc(n) makes the n-th allocation from then on (0 = the next one)
+// fail as if the device were out of memory, without allocating.
+static std::mutex g_alloc_mu;
+static long g_alloc_fault = -2;  // -2: environment not read yet; -1: off
+
+hipError_t slrx::dev_malloc(void** p, size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (g_alloc_fault == -2) {
+      const char* e = std::getenv("SLRX_FAULT_ALLOC");
+      g_alloc_fault = e ? std::atol(e) : -1;
+    }
+    if (g_alloc_fault >= 0 && g_alloc_fault-- == 0) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc(p, bytes);
+}
+
+extern "C" void slrx_fault_alloc(int32_t n) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc_fault = n < 0 ? -1 : n;
 }
 
 #define HIPCHK(expr)                                                                        \
@@ -269,7 +301,7 @@ slrx_status slrx::setup_libeigh(slrx_plan* pl) {
                    (rocblas_double_complex*)pl->Rm, s, pl->lam, pl->ework, pl->info);
   rocblas_stop_device_memory_size_query(pl->blas, &ws);
   if (ws < 1024) ws = 1024;
-  if (hipMalloc(&pl->blas_ws, ws) != hipSuccess) return fail(SLRX_ENOMEM, "eigensolver workspace (%zu bytes)", ws);
+  if (dev_malloc(&pl->blas_ws, ws) != hipSuccess) return fail(SLRX_ENOMEM, "eigensolver workspace (%zu bytes)", ws);
   pl->blas_ws_size = ws;
   if (rocblas_set_workspace(pl->blas, pl->blas_ws, ws) != rocblas_status_success)
     return fail(SLRX_EDEVICE, "rocblas_set_workspace failed");
@@ -353,7 +385,7 @@ extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params
     pl->own_stream = true;
   }
   const Layout L = plan_layout(*dims);
-  if (hipMalloc(&pl->arena, L.total) != hipSuccess) {
+  if (dev_malloc(&pl->arena, L.total) != hipSuccess) {
     (void)hipGetLastError();
     slrx_plan_destroy(pl);
     return fail(SLRX_ENOMEM, "device allocation of %zu bytes failed", L.total);
@@ -471,7 +503,14 @@ extern "C" slrx_status slrx_set_coils(slrx_plan* pl, int32_t ncoils, const void*
       // complex128: adjoint-half volumes, group sums
       const size_t n32 = (size_t)ncoils * pq + 2 * (size_t)ncoils * V + V;
       const size_t n64 = (size_t)ncoils * V + (size_t)coil_groups(ncoils) * V;
-      HIPCHK(hipMalloc(&pl->coil_mem, n32 * sizeof(float2) + n64 * sizeof(double2)));
+      const size_t cb = n32 * sizeof(float2) + n64 * sizeof(double2);
+      if (dev_malloc(&pl->coil_mem, cb) != hipSuccess) {
+        (void)hipGetLastError();
+        pl->coil_mem = nullptr;
+        pl->ncoils = 0;  // the plan is left without coil data
+        pl->prepared = false;
+        return fail(SLRX_ENOMEM, "coil buffers (%zu bytes)", cb);
+      }
       pl->ncoils_cap = ncoils;
       pl->Ct = (float2*)pl->coil_mem;
       pl->Bc = pl->Ct + (size_t)ncoils * pq;
@@ -563,7 +602,14 @@ slrx_status slrx::enqueue_run(slrx_plan* pl) {
   }
   HIPCHK(hipMemsetAsync(pl->info, 0, kInfoEntries * sizeof(rocblas_int), pl->stream));
   HIPCHK(hipEventRecord(pl->ev_run[0], pl->stream));
+  // roctx ranges (host side: they bracket the enqueueing of each outer iteration)
+  roctxRangePushA("slrx run");
+  struct PopRange {
+    ~PopRange() { roctxRangePop(); }
+  } pop_run;
   for (int it = 0; it < nirls; ++it) {
+    roctxRangePushA("slrx outer iteration");
+    PopRange pop_it;
     if (timing) HIPCHK(hipEventRecord(pl->ev_phase[4 * it], pl->stream));
     if (pl->direct()) {
       STCHK(step_direct_gram(pl));
@@ -776,12 +822,22 @@ extern "C" slrx_status slrx_run_batch(slrx_plan* const* plans, int32_t n, void* 
   std::lock_guard<std::mutex> lk(g_batch_mu);
   if (!g_batch_eig) g_batch_eig = new BatchEig();
   std::vector<slrx_plan*> v(plans, plans + n);
-  for (slrx_plan* pl : v) STCHK(engine_begin(pl));
+  slrx_status st = SLRX_OK;
+  size_t begun = 0;
+  for (; begun < v.size() && st == SLRX_OK; ++begun) st = engine_begin(v[begun]);
   int maxit = 0;
   for (slrx_plan* pl : v) maxit = pl->prm.n_irls > maxit ? pl->prm.n_irls : maxit;
-  for (int step = 0; step < maxit; ++step) STCHK(engine_step(v, *g_batch_eig));
-  for (slrx_plan* pl : v) STCHK(engine_end(pl));
-  return SLRX_OK;
+  for (int step = 0; step < maxit && st == SLRX_OK; ++step) st = engine_step(v, *g_batch_eig);
+  for (size_t i = 0; i < v.size() && st == SLRX_OK; ++i) st = engine_end(v[i]);
+  if (st != SLRX_OK) {  // no result: every begun plan drains its stream and is idle again
+    for (size_t i = 0; i < begun; ++i) {
+      (void)hipStreamSynchronize(v[i]->stream);
+      v[i]->running = false;
+      v[i]->ran = false;
+      v[i]->prepared = false;
+    }
+  }
+  return st;
 }
 
 // ------------------------------------------------------------ single steps

@@ -12,6 +12,7 @@
 // epsilon schedule), which is what the server does.  Problems that use the
 // library eigensolver take the single-problem path.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
@@ -119,14 +120,18 @@ static slrx_status group_reserve(BatchEig& be, int n, int nb, EigGroup*& out) {
   }
   EigGroup& G = be.groups[n];
   if (G.n != n) {  // first use of this size: the divide-and-conquer tree
-    G.n = n;
     std::vector<int> nodes;
     dc_build_tree(n, nodes, G.level_start);
     G.node_sizes.resize(nodes.size() / 4);
     for (size_t q = 0; q < nodes.size() / 4; ++q) G.node_sizes[q] = nodes[4 * q + 1];
-    if (hipMalloc(&G.tree, tree_bytes(n)) != hipSuccess) return fail(SLRX_ENOMEM, "divide-and-conquer tree");
+    if (!G.tree && dev_malloc((void**)&G.tree, tree_bytes(n)) != hipSuccess) {
+      (void)hipGetLastError();
+      G.tree = nullptr;
+      return fail(SLRX_ENOMEM, "divide-and-conquer tree");
+    }
     if (!nodes.empty())
       HIPCHK(hipMemcpy(G.tree, nodes.data(), nodes.size() * sizeof(int), hipMemcpyHostToDevice));
+    G.n = n;  // only once the tree is on the device
   }
   if (nb > G.cap) {
     HIPCHK(hipStreamSynchronize(be.stream));  // every reader of the old buffers has finished
@@ -137,7 +142,11 @@ static slrx_status group_reserve(BatchEig& be, int n, int nb, EigGroup*& out) {
     const GroupLayout L = group_layout(n, nb);
     const size_t sA = L.sA, sQ = L.sQ, sWi = L.sWi, sWd = L.sWd, sB = L.sB, sv = L.sv, sd = L.sd;
     const size_t total = L.total;
-    if (hipMalloc(&G.mem, total) != hipSuccess) return fail(SLRX_ENOMEM, "eigen-decomposition buffers (%zu bytes)", total);
+    if (dev_malloc(&G.mem, total) != hipSuccess) {
+      (void)hipGetLastError();
+      G.mem = nullptr;
+      return fail(SLRX_ENOMEM, "eigen-decomposition buffers (%zu bytes)", total);
+    }
     char* p = (char*)G.mem;
     auto take = [&](size_t b) {
       char* q = p;
@@ -221,6 +230,10 @@ static slrx_status step_single(slrx_plan* pl) {
 }
 
 slrx_status slrx::engine_step(const std::vector<slrx_plan*>& plans, BatchEig& be) {
+  roctxRangePushA("slrx engine step");  // host side: the enqueueing of one lock-step outer iteration
+  struct PopRange {
+    ~PopRange() { roctxRangePop(); }
+  } pop;
   std::map<int, std::vector<slrx_plan*>> groups;
   for (slrx_plan* pl : plans) {
     if (pl->it_next >= pl->prm.n_irls) continue;

@@ -27,6 +27,8 @@ enum Buf {
 };
 
 slrx_status fail(slrx_status st, const char* fmt, ...);
+// Every device allocation of the library (fault injection for tests: slrx_fault_alloc).
+hipError_t dev_malloc(void** p, size_t bytes);
 // What a captured CG graph depends on beyond the plan's fixed buffers.
 struct CgGraphKey {
   int P, Q, T, M, n_cg, circ, ncoils, pad;

@@ -365,7 +365,7 @@ slrx_status slrx::direct_setup(slrx_plan* pl) {
     if (pl->direct_mem) HIPCHK(hipFree(pl->direct_mem));
     pl->direct_mem = nullptr;
     pl->direct_bytes = 0;
-    if (hipMalloc(&pl->direct_mem, need) != hipSuccess) {
+    if (dev_malloc(&pl->direct_mem, need) != hipSuccess) {
       (void)hipGetLastError();
       return fail(SLRX_ENOMEM, "IRLS-direct buffers (%zu bytes: lifted matrices of %ld x %zu)", need, da.rows, s);
     }
