@@ -263,6 +263,38 @@ def measure_batch(steps: int, warmup: int, slices: int = 32, oracle_seconds: flo
     if check_bits:
         seq_imgs = [pl.images() for pl in plans]
         out["batch_equals_single_run_bitwise"] = all(np.array_equal(x, y) for x, y in zip(batch_imgs, seq_imgs))
+    # the CG strategy of the engine steps on this draw and on a draw of small slices
+    # (32 x 64x64x8, 5x5x3, 15 x 10): per problem, grouped, and the tuner's choice
+    def timed_batch(ps, mode, reps=3):
+        slrx.set_cg_grouping(mode)
+        try:
+            slrx.run_batch(ps)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                slrx.run_batch(ps)
+            torch.cuda.synchronize()
+            return len(ps) * reps / (time.perf_counter() - t)
+        finally:
+            slrx.set_cg_grouping(-1)
+    small = [workload.make_problem(seed=500 + i, P=64, Q=64, T=8, K=1, R=4, N1=5, N2=5, M=3, n_irls=15, n_cg=10)
+             for i in range(32)]
+    splans = []
+    for pb in small:
+        pl = slrx.Plan(64, 64, 8, 5, 5, 3, slrx.make_params(lam=pb.lam, n_irls=15, n_cg=10))
+        pl.set_kspace(pb.b)
+        pl.set_mask(pb.S)
+        splans.append(pl)
+    for _ in range(2):  # settle the tuner for the small draw
+        slrx.run_batch(splans)
+    out["cg_strategy_slices_per_s"] = {
+        "this_draw": {"per_problem": round(timed_batch(plans, 0), 2), "grouped": round(timed_batch(plans, 1), 2)},
+        "small_slices_32x64x64x8": {"per_problem": round(timed_batch(splans, 0), 2),
+                                    "grouped": round(timed_batch(splans, 1), 2),
+                                    "tuned": round(timed_batch(splans, -1), 2)},
+    }
+    for pl in splans:
+        pl.close()
     if oracle_seconds > 0:
         import oracle
         # whole slices of the same batch through the oracle until the time is up

@@ -386,6 +386,14 @@ const char* slrx_status_str(slrx_status s);
  * allocation of the process.  Other environment variables: SLRX_LOG (print every
  * failure to stderr), SLRX_TUNE_CACHE (the tuner's cache file). */
 void slrx_fault_alloc(int32_t n);
+
+/* CG strategy of lock-step batches and servers (process-wide): -1 (default)
+ * picks, per step shape, by timing both on the first steps (online tuner, after
+ * the tridiagonalisation's launch shape is settled); 0 runs each problem's CG
+ * on its own stream; 1 runs the CG of all single-channel problems of a step
+ * that share the tap count M and the CG count in one launch per pass.  Results
+ * are bit-identical either way. */
+void slrx_set_cg_grouping(int32_t mode);
 /* Message of the last failed call on `plan`, or of the calling thread's last
  * failed call when plan is NULL ("" if none).  Valid until the next call. */
 const char* slrx_last_error(const slrx_plan* plan);

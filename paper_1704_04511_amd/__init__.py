@@ -96,6 +96,7 @@ _I = ctypes.c_int
 _SIGS = {
     "slrx_default_params": (None, [ctypes.POINTER(Params)]),
     "slrx_fault_alloc": (None, [ctypes.c_int32]),
+    "slrx_set_cg_grouping": (None, [ctypes.c_int32]),
     "slrx_validate": (_I, [ctypes.POINTER(Dims), ctypes.POINTER(Params)]),
     "slrx_footprint": (ctypes.c_size_t, [ctypes.POINTER(Dims)]),
     "slrx_plan_create": (_I, [ctypes.POINTER(Dims), ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]),
@@ -193,6 +194,11 @@ def make_params(lam=1e-3, n_irls=15, n_cg=10, p=0.6, gamma=1.4, eps0_frac=0.01, 
     for c in ktime_classes or ():
         flags |= 1 << (16 + KERNEL_CLASSES.index(c))
     return Params(float(lam), float(p), float(gamma), float(eps0_frac), int(n_irls), int(n_cg), flags)
+
+
+def set_cg_grouping(mode: int) -> None:
+    """CG strategy of batches and servers: -1 tuned online (default), 0 per problem, 1 grouped."""
+    lib().slrx_set_cg_grouping(int(mode))
 
 
 def validate(dims: Dims, params: Params | None = None) -> None:

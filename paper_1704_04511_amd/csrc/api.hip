@@ -401,6 +401,8 @@ extern "C" slrx_status slrx_plan_create(const slrx_dims* dims, const slrx_params
       if (hipEventCreate(&pl->ev_run[i]) != hipSuccess) st = fail(SLRX_EDEVICE, "hipEventCreate failed");
     if (hipEventCreateWithFlags(&pl->ev_step, hipEventDisableTiming) != hipSuccess)
       st = fail(SLRX_EDEVICE, "hipEventCreate failed");
+    if (hipEventCreateWithFlags(&pl->ev_begin, hipEventDisableTiming) != hipSuccess)
+      st = fail(SLRX_EDEVICE, "hipEventCreate failed");
     for (int i = 0; i < 2; ++i)
       if (hipEventCreateWithFlags(&pl->ev_iter[i], hipEventDisableTiming) != hipSuccess)
         st = fail(SLRX_EDEVICE, "hipEventCreate failed");
@@ -422,6 +424,7 @@ extern "C" void slrx_plan_destroy(slrx_plan* pl) {
   for (int i = 0; i < 2; ++i)
     if (pl->ev_run[i]) (void)hipEventDestroy(pl->ev_run[i]);
   if (pl->ev_step) (void)hipEventDestroy(pl->ev_step);
+  if (pl->ev_begin) (void)hipEventDestroy(pl->ev_begin);
   for (int i = 0; i < 2; ++i)
     if (pl->ev_iter[i]) (void)hipEventDestroy(pl->ev_iter[i]);
   cg_graph_reset(pl);

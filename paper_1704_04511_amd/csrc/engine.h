@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/slrx.h"
+#include "kernels.h"
 #include "plan.h"
 
 namespace slrx {
@@ -20,14 +21,31 @@ struct EigGroup {
   ~EigGroup();
 };
 
-// Shared state of the batched eigen-decompositions (own stream and events).
+// Table of a grouped CG launch (kernels.h CgSlice): the device copy, a pinned
+// staging copy, and the host copy it was made from (rewritten only when the
+// problems of the group change).
+struct CgTable {
+  std::vector<CgSlice> host;
+  CgSlice* dev = nullptr;
+  CgSlice* pinned = nullptr;
+  size_t cap = 0;                // entries of dev and pinned
+  hipEvent_t copied = nullptr;   // the last upload from pinned has run
+  bool pending = false;
+  ~CgTable();
+};
+
+// Shared state of the batched eigen-decompositions and the grouped CG (own
+// streams and events).
 struct BatchEig {
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;       // eigenpairs ready
   hipEvent_t ev_free = nullptr;  // every reader of the group buffers has run
   bool have_free = false;
   std::map<int, EigGroup> groups;
-  size_t allocated() const;  // device bytes held by the groups
+  hipStream_t cg_stream = nullptr;  // grouped CG passes
+  hipEvent_t ev_cg = nullptr;       // a group's CG has run
+  std::map<std::pair<int, int>, CgTable> cg_tables;  // by (M, n_cg)
+  size_t allocated() const;  // device bytes held by the groups and tables
   ~BatchEig();
 };
 

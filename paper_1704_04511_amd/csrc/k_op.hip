@@ -47,9 +47,17 @@ __host__ __device__ inline int row_block(int P) { return P < kRowB ? P : kRowB; 
 // XCDs round-robin; consecutive work items are given to one XCD, so the two
 // halves of a 128-byte line of the transposed output (neighbouring bands)
 // meet in the same L2.
-SLRX_DEV void row_tile(int& band, int& frame) {
-  const int gx = gridDim.x, nb = gridDim.x * gridDim.y;
-  int id = blockIdx.y * gx + blockIdx.x;
+// A block's coordinates in the grid of its problem: the launch's own grid, or a
+// slice of a grouped launch covering several problems (every problem's blocks
+// then do exactly what they do in a launch of their own).
+struct Blk {
+  int bx, by, gx, gy;
+};
+SLRX_DEV Blk launch_blk() { return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y}; }
+
+SLRX_DEV void row_tile(const Blk& b, int& band, int& frame) {
+  const int gx = b.gx, nb = b.gx * b.gy;
+  int id = b.by * gx + b.bx;
   if ((nb & 7) == 0) id = (id & 7) * (nb >> 3) + (id >> 3);
   band = id % gx;
   frame = id / gx;
@@ -68,16 +76,13 @@ __host__ __device__ inline int col_block(int cap, int Q) {
 // ------------------------------------------------------------ pass 1: rows
 // Row DFT of RB rows of one frame; output transposed: dst[t][c][r].
 template <int N, int SIGN>
-__global__ __launch_bounds__(kNT) void k_rows_t(RowArgs a) {
+SLRX_DEV void rows_t_body(const RowArgs& a, const Blk& b, float2* lds, float2* twt, double* red) {
   constexpr int RBMAX = kRowB;
   constexpr int BS = fft_stride(N);
-  __shared__ float2 lds[RBMAX * BS];
-  __shared__ float2 twt[fft_tw_size<N>()];
-  __shared__ double red[kNT / 64];
   const int P = a.P, Q = a.Q;
   const int RB = row_block(P);
   int band, t;
-  row_tile(band, t);
+  row_tile(b, band, t);
   const int r0 = band * RB;
   const long fo = (long)t * P * Q;
   const long g0 = fo + (long)r0 * Q;
@@ -92,7 +97,7 @@ __global__ __launch_bounds__(kNT) void k_rows_t(RowArgs a) {
       const double prev = a.rr_hist[a.k - 1];
       beta = prev > 0.0 ? rr / prev : 0.0;
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.rr_hist[a.k] = rr;
+    if (b.bx == 0 && b.by == 0 && threadIdx.x == 0) a.rr_hist[a.k] = rr;
     const float fb = (float)beta;
     constexpr int U = 8;  // loads in flight per thread
     for (int e0 = threadIdx.x; e0 < nel; e0 += kNT * U) {
@@ -133,6 +138,14 @@ __global__ __launch_bounds__(kNT) void k_rows_t(RowArgs a) {
   }
 }
 
+template <int N, int SIGN>
+__global__ __launch_bounds__(kNT) void k_rows_t(RowArgs a) {
+  __shared__ float2 lds[kRowB * fft_stride(N)];
+  __shared__ float2 twt[fft_tw_size<N>()];
+  __shared__ double red[kNT / 64];
+  rows_t_body<N, SIGN>(a, launch_blk(), lds, twt, red);
+}
+
 // -------------------------------------------------- pass 2: columns + penalty
 // Block: CB columns of all T frames, each column a contiguous transform of
 // length N = P in the transposed layout.  Inverse column DFT, G, forward DFT.
@@ -142,17 +155,16 @@ __global__ __launch_bounds__(kNT) void k_rows_t(RowArgs a) {
 constexpr int kPenNT = 512;
 
 template <int N, int M>
-__global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
+SLRX_DEV void cols_pen_body(const PenArgs& a, const Blk& b, float2* lds, float2* twt) {
   constexpr int CAP = ColCap<N>::v;
   constexpr int MAXB = kTMax * CAP;
   constexpr int W = M * (M + 1) / 2;
   constexpr int BS = fft_stride(N);
   constexpr int ME = M > 1 ? 2 * M - 2 : 1;  // frames at each end with a partial window
-  extern __shared__ float2 lds[];  // [T][CB] transforms of length N, padded
-  __shared__ float2 twt[fft_tw_size<N>()];
+  // lds: [T][CB] transforms of length N, padded
   const int T = a.T, P = a.P, Q = a.Q;
   const int CB = col_block(CAP, Q);
-  const int c0 = blockIdx.x * CB;
+  const int c0 = b.bx * CB;
   const long fs = (long)P * Q;
   fft_twiddles<N, kPenNT>(twt, a.tw);
   const int per_t = CB * BS;  // LDS stride of a frame
@@ -317,6 +329,13 @@ __global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
     for (int t = h; t < T; t += 2) a.buf[(long)t * fs + po] = lds[t * per_t + pl];
 }
 
+template <int N, int M>
+__global__ __launch_bounds__(kPenNT) void k_cols_pen(PenArgs a) {
+  extern __shared__ float2 lds[];
+  __shared__ float2 twt[fft_tw_size<N>()];
+  cols_pen_body<N, M>(a, launch_blk(), lds, twt);
+}
+
 // Plain column DFT of up to 16 columns of one frame: transposed in, row-major out.
 template <int N, int SIGN>
 __global__ __launch_bounds__(kNT) void k_cols_plain(ColArgs a) {
@@ -348,18 +367,14 @@ __global__ __launch_bounds__(kNT) void k_cols_plain(ColArgs a) {
 // COIL (multichannel data term): no S o x; instead the complex128 forward row
 // DFT of the coil combination's group sums is added to pen before rounding.
 template <int N, bool COIL>
-__global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
+SLRX_DEV void rows_fin_body(const FinArgs& a, const Blk& b, float2* lds, float2* twt, double2* lds64,
+                            double2* twt64, double* red) {
   constexpr int RBMAX = kRowB;
   constexpr int BS = fft_stride(N);
-  __shared__ float2 lds[RBMAX * BS];
-  __shared__ float2 twt[fft_tw_size<N>()];
-  __shared__ double2 lds64[COIL ? RBMAX * BS : 1];
-  __shared__ double2 twt64[COIL ? fft_tw_size<N>() : 1];
-  __shared__ double red[kNT / 64];
   const int P = a.P, Q = a.Q;
   const int RB = row_block(P);
   int band, t;
-  row_tile(band, t);
+  row_tile(b, band, t);
   const int r0 = band * RB;
   const long fo = (long)t * P * Q;
   const int nel = RB * N;
@@ -434,17 +449,26 @@ __global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
     combine(e, a.v[g0 + e], a.S[g0 + e], a.init ? a.y[g0 + e] : make_float2(0.f, 0.f));
   dot = block_sum<kNT>(dot, red);
   if (threadIdx.x == 0) {
-    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    const int bid = b.by * b.gx + b.bx;
     a.part[bid] = dot;
     if (a.init && bid == 0) *a.flag = 0;
   }
 }
 
+template <int N, bool COIL>
+__global__ __launch_bounds__(kNT) void k_rows_fin(FinArgs a) {
+  __shared__ float2 lds[kRowB * fft_stride(N)];
+  __shared__ float2 twt[fft_tw_size<N>()];
+  __shared__ double2 lds64[COIL ? kRowB * fft_stride(N) : 1];
+  __shared__ double2 twt64[COIL ? fft_tw_size<N>() : 1];
+  __shared__ double red[kNT / 64];
+  rows_fin_body<N, COIL>(a, launch_blk(), lds, twt, lds64, twt64, red);
+}
+
 // --------------------------------------------------------------- update
 // Two complex elements per 16-byte access, kUpdU accesses per thread in flight.
 constexpr int kUpdU = 4;
-__global__ __launch_bounds__(kNT) void k_update(UpdArgs a) {
-  __shared__ double red[kNT / 64];
+SLRX_DEV void update_body(const UpdArgs& a, const Blk& b, double* red) {
   const double pq = reduce_partials<kNT>(a.partA, a.nA, red);
   const double rr = a.rr_hist[a.k];
   const bool stop = (*a.flag != 0) || !(rr > 0.0) || !(pq > 0.0);
@@ -455,12 +479,12 @@ __global__ __launch_bounds__(kNT) void k_update(UpdArgs a) {
   const float4* p4 = (const float4*)a.p;
   const float4* q4 = (const float4*)a.q;
   double acc = 0.0;
-  const long stride = (long)gridDim.x * kNT;
-  for (long b = (long)blockIdx.x * kNT + threadIdx.x; b < n4; b += stride * kUpdU) {
+  const long stride = (long)b.gx * kNT;
+  for (long i0 = (long)b.bx * kNT + threadIdx.x; i0 < n4; i0 += stride * kUpdU) {
     float4 rv[kUpdU], xv[kUpdU], pv[kUpdU], qv[kUpdU];
 #pragma unroll
     for (int u = 0; u < kUpdU; ++u) {
-      const long i = b + u * stride;
+      const long i = i0 + u * stride;
       if (i < n4) {
         rv[u] = r4[i];
         if (!stop) {
@@ -472,7 +496,7 @@ __global__ __launch_bounds__(kNT) void k_update(UpdArgs a) {
     }
 #pragma unroll
     for (int u = 0; u < kUpdU; ++u) {
-      const long i = b + u * stride;
+      const long i = i0 + u * stride;
       if (i >= n4) continue;
       float4 ri = rv[u];
       if (!stop) {
@@ -487,9 +511,14 @@ __global__ __launch_bounds__(kNT) void k_update(UpdArgs a) {
   }
   acc = block_sum<kNT>(acc, red);
   if (threadIdx.x == 0) {
-    a.partB[blockIdx.x] = acc;
-    if (stop && blockIdx.x == 0) *a.flag = 1;
+    a.partB[b.bx] = acc;
+    if (stop && b.bx == 0) *a.flag = 1;
   }
+}
+
+__global__ __launch_bounds__(kNT) void k_update(UpdArgs a) {
+  __shared__ double red[kNT / 64];
+  update_body(a, launch_blk(), red);
 }
 
 __global__ void k_mask_data(long n, const uint8_t* S, const float2* b, float2* out) {
@@ -517,6 +546,196 @@ __global__ void k_transpose_planes(int W, int A, int B, const float2* in, float2
   const int rem = (int)(o % ((long)A * B));
   const int j = rem / A, i = rem % A;  // output index [w][j][i]
   out[o] = in[(w * A + i) * B + j];
+}
+
+// ------------------------------------------------ grouped launches (batches)
+// One launch of a CG pass for every problem of a group (problems of any frame
+// size and count that share the tap count M).  The grid is the concatenation
+// of the problems' own grids, each starting at a multiple of 8 blocks (so a
+// block keeps its XCD); a block finds its problem in the group's table and
+// runs exactly the work, with exactly the same arithmetic and partial-sum
+// slots, that it runs in a launch for that problem alone.
+constexpr int kTwMax = fft_tw_size<256>() > fft_tw_size<192>()
+                           ? (fft_tw_size<256>() > fft_tw_size<160>() ? fft_tw_size<256>() : fft_tw_size<160>())
+                           : (fft_tw_size<192>() > fft_tw_size<160>() ? fft_tw_size<192>() : fft_tw_size<160>());
+static_assert(kTwMax >= fft_tw_size<128>() && kTwMax >= fft_tw_size<96>() && kTwMax >= fft_tw_size<64>(),
+              "twiddle table of the grouped passes");
+
+// Largest LDS row count of a column block over the transform lengths (CB * stride).
+constexpr int pen_cols(int cap, int n) { return cap * fft_stride(n); }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kPenCols = cmax(cmax(cmax(pen_cols(ColCap<8>::v, 8), pen_cols(ColCap<16>::v, 16)),
+                                   cmax(pen_cols(ColCap<32>::v, 32), pen_cols(ColCap<64>::v, 64))),
+                              cmax(cmax(pen_cols(ColCap<96>::v, 96), pen_cols(ColCap<128>::v, 128)),
+                                   cmax(cmax(pen_cols(ColCap<160>::v, 160), pen_cols(ColCap<192>::v, 192)),
+                                        pen_cols(ColCap<256>::v, 256))));
+
+SLRX_DEV int group_slice(const CgSlice* tab, int ns, int gb, int CgSlice::*start) {
+  int i = 0;
+  while (i + 1 < ns && gb >= tab[i + 1].*start) ++i;
+  return i;
+}
+
+#define SLRX_SWITCH_N(n, ...)                                                 \
+  switch (n) {                                                                \
+    case 8: { constexpr int N_ = 8; __VA_ARGS__; } break;                     \
+    case 16: { constexpr int N_ = 16; __VA_ARGS__; } break;                   \
+    case 32: { constexpr int N_ = 32; __VA_ARGS__; } break;                   \
+    case 64: { constexpr int N_ = 64; __VA_ARGS__; } break;                   \
+    case 96: { constexpr int N_ = 96; __VA_ARGS__; } break;                   \
+    case 128: { constexpr int N_ = 128; __VA_ARGS__; } break;                 \
+    case 160: { constexpr int N_ = 160; __VA_ARGS__; } break;                 \
+    case 192: { constexpr int N_ = 192; __VA_ARGS__; } break;                 \
+    case 256: { constexpr int N_ = 256; __VA_ARGS__; } break;                 \
+  }
+
+// mode ROW_PLAIN: x into the row pass (initial residual); ROW_PUPDATE: p = r + beta p.
+__global__ __launch_bounds__(kNT) void k_group_rows(const CgSlice* tab, int ns, int mode, int k) {
+  __shared__ float2 lds[kRowB * fft_stride(256)];
+  __shared__ float2 twt[kTwMax];
+  __shared__ double red[kNT / 64];
+  const int gb = (int)blockIdx.x;
+  const CgSlice& c = tab[group_slice(tab, ns, gb, &CgSlice::rows0)];
+  const int lb = gb - c.rows0;
+  if (lb >= c.rows_gx * c.rows_gy) return;  // alignment padding
+  const Blk b{lb % c.rows_gx, lb / c.rows_gx, c.rows_gx, c.rows_gy};
+  RowArgs a{};
+  a.P = c.P; a.Q = c.Q; a.T = c.T;
+  a.mode = mode;
+  a.sign = +1;
+  a.src = mode == ROW_PUPDATE ? c.r : c.x;
+  a.pvec = c.p;
+  a.dst = c.t;
+  a.scale = 1.0f;
+  a.tw = c.twQ;
+  a.k = k;
+  a.part = k == 0 ? c.partA : c.partB;
+  a.npart = k == 0 ? c.nfin : c.nupd;
+  a.rr_hist = c.rr_hist;
+  SLRX_SWITCH_N(c.Q, rows_t_body<N_, +1>(a, b, lds, twt, red))
+}
+
+template <int M>
+__global__ __launch_bounds__(kPenNT) void k_group_pen(const CgSlice* tab, int ns) {
+  extern __shared__ float2 lds[];
+  __shared__ float2 twt[kTwMax];
+  const int gb = (int)blockIdx.x;
+  const CgSlice& c = tab[group_slice(tab, ns, gb, &CgSlice::cols0)];
+  const int lb = gb - c.cols0;
+  if (lb >= c.cols_gx) return;
+  const Blk b{lb, 0, c.cols_gx, 1};
+  PenArgs a{};
+  a.P = c.P; a.Q = c.Q; a.T = c.T; a.M = M;
+  a.buf = c.t;
+  a.Et = c.Et;
+  a.scale = c.pen_scale;
+  a.tw = c.twP;
+  a.circ = c.circ;
+  SLRX_SWITCH_N(c.P, cols_pen_body<N_, M>(a, b, lds, twt))
+}
+
+__global__ __launch_bounds__(kNT) void k_group_fin(const CgSlice* tab, int ns, int init) {
+  __shared__ float2 lds[kRowB * fft_stride(256)];
+  __shared__ float2 twt[kTwMax];
+  __shared__ double red[kNT / 64];
+  const int gb = (int)blockIdx.x;
+  const CgSlice& c = tab[group_slice(tab, ns, gb, &CgSlice::rows0)];
+  const int lb = gb - c.rows0;
+  if (lb >= c.rows_gx * c.rows_gy) return;
+  const Blk b{lb % c.rows_gx, lb / c.rows_gx, c.rows_gx, c.rows_gy};
+  FinArgs a{};
+  a.P = c.P; a.Q = c.Q; a.T = c.T;
+  a.init = init;
+  a.t = c.t;
+  a.v = init ? c.x : c.p;
+  a.S = c.S;
+  a.y = c.bm;
+  a.out = init ? c.r : c.q;
+  a.part = c.partA;
+  a.flag = c.flag;
+  a.tw = c.twQ;
+  SLRX_SWITCH_N(c.Q, rows_fin_body<N_, false>(a, b, lds, twt, nullptr, nullptr, red))
+}
+
+__global__ __launch_bounds__(kNT) void k_group_update(const CgSlice* tab, int ns, int k) {
+  __shared__ double red[kNT / 64];
+  const int gb = (int)blockIdx.x;
+  const CgSlice& c = tab[group_slice(tab, ns, gb, &CgSlice::upd0)];
+  const int lb = gb - c.upd0;
+  if (lb >= c.upd_gx) return;
+  UpdArgs a{};
+  a.n = (long)c.T * c.P * c.Q;
+  a.x = c.x;
+  a.r = c.r;
+  a.p = c.p;
+  a.q = c.q;
+  a.partA = c.partA;
+  a.nA = c.nfin;
+  a.rr_hist = c.rr_hist;
+  a.k = k;
+  a.partB = c.partB;
+  a.flag = c.flag;
+  update_body(a, Blk{lb, 0, c.upd_gx, 1}, red);
+}
+
+// The problem's own grids and partial counts (what its single launches use).
+void cg_slice_grids(CgSlice& c) {
+  c.rows_gx = c.P / row_block(c.P);
+  c.rows_gy = c.T;
+  int cb = 1;
+  SLRX_SWITCH_N(c.P, cb = col_block(ColCap<N_>::v, c.Q))
+  c.cols_gx = c.Q / cb;
+  c.upd_gx = update_blocks((long)c.T * c.P * c.Q);
+  c.nfin = fin_blocks(c.P, c.T);
+  c.nupd = c.upd_gx;
+}
+
+size_t group_pen_lds(int P, int Q, int T) {
+  size_t lds = 0;
+  SLRX_SWITCH_N(P, lds = (size_t)T * col_block(ColCap<N_>::v, Q) * fft_stride(N_) * sizeof(float2))
+  return lds;
+}
+
+hipError_t launch_group_rows(const CgGroup& g, int mode, int k, hipStream_t s) {
+  k_group_rows<<<g.rows_blocks, kNT, 0, s>>>(g.tab, g.ns, mode, k);
+  return hipGetLastError();
+}
+
+template <int M>
+static hipError_t group_pen_m(const CgGroup& g, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_group_pen<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)((size_t)kTMax * kPenCols * sizeof(float2)));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  k_group_pen<M><<<g.cols_blocks, kPenNT, g.pen_lds, s>>>(g.tab, g.ns);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_pen(const CgGroup& g, hipStream_t s) {
+  switch (g.M) {
+    case 1: return group_pen_m<1>(g, s);
+    case 2: return group_pen_m<2>(g, s);
+    case 3: return group_pen_m<3>(g, s);
+    case 4: return group_pen_m<4>(g, s);
+    case 5: return group_pen_m<5>(g, s);
+    case 6: return group_pen_m<6>(g, s);
+    case 7: return group_pen_m<7>(g, s);
+    case 8: return group_pen_m<8>(g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_group_fin(const CgGroup& g, int init, hipStream_t s) {
+  k_group_fin<<<g.rows_blocks, kNT, 0, s>>>(g.tab, g.ns, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_update(const CgGroup& g, int k, hipStream_t s) {
+  k_group_update<<<g.upd_blocks, kNT, 0, s>>>(g.tab, g.ns, k);
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------- launches

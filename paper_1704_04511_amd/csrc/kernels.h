@@ -99,6 +99,37 @@ struct UpdArgs {
 hipError_t launch_update(const UpdArgs& a, hipStream_t s);
 int update_blocks(long n);
 
+// Grouped CG passes (batches): one launch covers every problem of a group (any
+// frame sizes and counts, one tap count M, single-channel data); each problem's
+// blocks do exactly what they do in the problem's own launches.
+struct CgSlice {
+  int P, Q, T, circ;
+  float pen_scale;                      // lam / (P Q)
+  float2 *x, *r, *p, *q, *t;
+  const float2* bm;                     // right-hand side S o b
+  const uint8_t* S;
+  const float2* Et;                     // masks, transposed planes
+  const float2 *twQ, *twP;              // complex64 twiddles of the row and column lengths
+  double *partA, *partB, *rr_hist;
+  int* flag;
+  int nfin, nupd;                       // partial counts of the finishing and update passes
+  int rows_gx, rows_gy, cols_gx, upd_gx;  // the problem's own grids
+  int rows0, cols0, upd0;               // its first block in the grouped grids (multiples of 8)
+};
+struct CgGroup {
+  const CgSlice* tab;                   // device copy of the table, ns entries
+  int ns, M;
+  int rows_blocks, cols_blocks, upd_blocks;
+  size_t pen_lds;                       // dynamic LDS of the grouped column pass
+};
+void cg_slice_grids(CgSlice& c);        // fills the grids and partial counts from P, Q, T
+size_t group_pen_lds(int P, int Q, int T);
+// mode: ROW_PLAIN (initial residual, x) or ROW_PUPDATE (iteration k)
+hipError_t launch_group_rows(const CgGroup& g, int mode, int k, hipStream_t s);
+hipError_t launch_group_pen(const CgGroup& g, hipStream_t s);
+hipError_t launch_group_fin(const CgGroup& g, int init, hipStream_t s);
+hipError_t launch_group_update(const CgGroup& g, int k, hipStream_t s);
+
 // Multichannel data term (k_coil.hip): complex64 forward half, complex128
 // adjoint half after the sampling mask.
 struct CoilArgs {

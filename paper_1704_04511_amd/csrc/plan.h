@@ -113,6 +113,7 @@ struct slrx_plan {
 
   hipEvent_t ev_run[2] = {nullptr, nullptr};
   hipEvent_t ev_step = nullptr;  // ordering against a shared batched eigen-decomposition
+  hipEvent_t ev_begin = nullptr; // start of a lock-step engine step (timing of the CG strategy)
   int it_next = 0;               // next outer iteration (lock-step engine)
   hipEvent_t ev_iter[2] = {nullptr, nullptr};  // end of the last two engine steps (server pacing)
   std::vector<hipEvent_t> ev_phase;

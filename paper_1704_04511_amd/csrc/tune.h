@@ -6,7 +6,9 @@ namespace slrx {
 
 // Kernel classes with tuned launch configurations.
 enum TuneKind {
-  TUNE_TRI = 1,  // Householder tridiagonalisation: workgroups per column launch (a = n, b = problems)
+  TUNE_TRI = 1,       // Householder tridiagonalisation: workgroups per column launch (a = n, b = problems)
+  TUNE_CG_GROUP = 2,  // engine step: the CG of each problem on its own stream (0) or grouped launches (1)
+                      // (a = problems, b = their summed volume / 4096, c = largest M << 16 | largest n_cg)
 };
 
 // Timing of one call made with a candidate configuration.
