@@ -36,6 +36,11 @@ namespace slrx {
 
 constexpr int kTriNT = 256;
 constexpr int kTriRB = 4;      // rows of a workgroup whose elements are loaded at kernel entry
+// Rows held in registers at a time for U vector entries per thread: fewer for the
+// long columns of Gram matrices above 2048 (their register arrays otherwise need
+// about 500 registers per lane, and the U = 12 instance holding four rows gave wrong
+// eigenvalues for n > 2560 while U = 9 and 10 were exact).
+template <int U> constexpr int tri_rb() { return U > 10 ? 1 : (U > 8 ? 2 : kTriRB); }
 constexpr int kTriRMax = 32;   // rows per workgroup at most
 
 SLRX_DEV double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -108,9 +113,10 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
       }
     }
   }
-  double2 xr[kTriRB][U];
+  constexpr int RB = tri_rb<U>();
+  double2 xr[RB][U];
 #pragma unroll
-  for (int r = 0; r < kTriRB; ++r)
+  for (int r = 0; r < RB; ++r)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = k + tid + kTriNT * u;
@@ -227,18 +233,18 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
     if (lane == 0) xc[wave][r] = acc;
   };
 #pragma unroll
-  for (int r = 0; r < kTriRB; ++r)
+  for (int r = 0; r < RB; ++r)
     if (r < nrow) row_work(r, xr[r]);
-  for (int r0 = kTriRB; r0 < nrow; r0 += kTriRB) {  // rows beyond the prefetched ones
+  for (int r0 = RB; r0 < nrow; r0 += RB) {  // rows beyond the prefetched ones
 #pragma unroll
-    for (int r = 0; r < kTriRB; ++r)
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = k + tid + kTriNT * u;
         xr[r][u] = (r0 + r < nrow && j > k && j < n) ? Aw[(size_t)(row0 + r0 + r) * n + j] : zero;
       }
 #pragma unroll
-    for (int r = 0; r < kTriRB; ++r)
+    for (int r = 0; r < RB; ++r)
       if (r0 + r < nrow) row_work(r0 + r, xr[r]);
   }
   __syncthreads();
@@ -437,6 +443,8 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int bu
     else if (u <= 5) launch_col<5>(a, nbatch, rows, s);
     else if (u <= 6) launch_col<6>(a, nbatch, rows, s);
     else if (u <= 8) launch_col<8>(a, nbatch, rows, s);
+    else if (u <= 9) launch_col<9>(a, nbatch, rows, s);
+    else if (u <= 10) launch_col<10>(a, nbatch, rows, s);
     else launch_col<12>(a, nbatch, rows, s);
   }
   const int L = n - k0;

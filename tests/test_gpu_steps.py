@@ -97,6 +97,29 @@ def test_weights_and_masks_match_oracle(shape):
         assert nrmse(E[w], E_ref[m, mp]) < 2e-5, (m, mp)
 
 
+@pytest.mark.parametrize("shape", [(8, 64, 64, 16, 18, 8), (8, 64, 64, 19, 19, 8), (8, 64, 64, 15, 25, 8)])
+def test_weights_at_the_largest_filters(shape):
+    """Gram sizes 2304, 2888 and 3000 (the largest the own eigensolver chain takes):
+    the tridiagonalisation's long-column kernel instances (more than 2048 entries per
+    column) against the oracle's eigenvalues, H and masks."""
+    T, P, Q, N1, N2, M = shape
+    say(f"weights, large filter {shape}")
+    rng, x, _ = problem(7, T, P, Q)
+    R_ref = oracle.gram(x.astype(np.complex128), N1, N2, M)
+    lam_ref = np.linalg.eigvalsh(R_ref)
+    eps = 0.01 * lam_ref.max()
+    with make_plan(*shape) as pl:
+        pl.set_kspace(x)
+        pl.set_mask(np.ones((T, P, Q), np.uint8))
+        lam, H, E = pl.step_weights(eps)
+    assert np.all(np.abs(lam - lam_ref) <= 1e-5 * lam_ref + 2e-7 * lam_ref.max())
+    ev, U, alpha = oracle.eig_weights(R_ref, eps, 0.6)
+    assert nrmse(H, oracle.weight_matrix(U, alpha)) < 2e-5
+    E_ref = oracle.penalty_masks(U, alpha, N1, N2, M, P, Q)
+    for w, (m, mp) in enumerate(pairs(M)):
+        assert nrmse(E[w], E_ref[m, mp]) < 2e-5, (m, mp)
+
+
 def masks_from_H(H, N1, N2, M, P, Q):
     """Masks straight from H: the lag sums w_{m',m}[a' - a] of the (m', m) block, then
     E(r) = sum_Delta w[Delta] e^{+2 pi i (Delta1 r1 / P + Delta2 r2 / Q)} (FP64)."""
