@@ -411,12 +411,17 @@ static void launch_col(const TriArgs& a, int nbatch, int rows, hipStream_t s) {
 // Workgroup budgets per column launch (all problems of a batch together) the
 // tuner chooses from: each workgroup recomputes the reflector, so many small
 // problems want more rows per workgroup than one large one.
-static const int kTriBudget1[] = {128, 256};
+// One problem also tries 256 with long columns split so that every row of a
+// workgroup is loaded at kernel entry (kTriRB rows each, up to 320 workgroups):
+// 8.03 against 8.13 ms per 1125 x 1125 decomposition when measured.
+static const int kTriBudget1[] = {128, 256, 256};
 static const int kTriBudgetN[] = {256, 512, 1024, 2048, 4096};
-int tri_budget_candidates(int nbatch) { return nbatch > 1 ? 5 : 2; }
+int tri_budget_candidates(int nbatch) { return nbatch > 1 ? 5 : 3; }
 int tri_budget(int nbatch, int cand) { return nbatch > 1 ? kTriBudgetN[cand] : kTriBudget1[cand]; }
 
-hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int budget) {
+hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int cand) {
+  const int budget = tri_budget(nbatch, cand);
+  const bool fit = nbatch == 1 && cand == 2;
   const int n = base.n;
   if (n > tri_max_n()) return hipErrorInvalidValue;
   static bool tail_attr = false;
@@ -436,6 +441,8 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int bu
     const int rb = (int)(((long)nr * nbatch + budget - 1) / budget);
     if (rb > rows) rows = rb < kTriRMax ? rb : kTriRMax;
     const int u = (n - k + kTriNT - 1) / kTriNT;      // vector entries per thread
+    const int rbu = u > 10 ? 1 : (u > 8 ? 2 : kTriRB); // rows loaded at entry (tri_rb<U>)
+    if (fit && rows > rbu && (nr + rbu - 1) / rbu <= 320) rows = rbu;
     if (u <= 1) launch_col<1>(a, nbatch, rows, s);
     else if (u <= 2) launch_col<2>(a, nbatch, rows, s);
     else if (u <= 3) launch_col<3>(a, nbatch, rows, s);

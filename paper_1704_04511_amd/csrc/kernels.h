@@ -267,9 +267,10 @@ struct TriArgs {
   double2* vbuf[2];
   double2* pbuf[2];
 };
-// budget: workgroups per column launch across the batch (tri_budget); results
-// do not depend on it.
-hipError_t launch_tridiag(const TriArgs& a, int nbatch, hipStream_t s, int budget);
+// cand: the tuner's candidate launch shape (tri_budget: workgroups per column
+// launch across the batch; for one problem candidate 2 also caps the rows per
+// workgroup at those loaded at kernel entry); results do not depend on it.
+hipError_t launch_tridiag(const TriArgs& a, int nbatch, hipStream_t s, int cand);
 int tri_budget_candidates(int nbatch);
 int tri_budget(int nbatch, int cand);
 int tri_max_n();

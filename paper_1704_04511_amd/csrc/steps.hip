@@ -177,7 +177,7 @@ hipError_t slrx::eigh_tri(const EighBufs& e, hipStream_t st) {
   // workgroups per launch: tuned per (n, problems) on the first decompositions
   TuneTicket tk;
   const int cand = tune_begin(TUNE_TRI, e.n, e.nb, 0, tri_budget_candidates(e.nb), st, tk);
-  const hipError_t err = launch_tridiag(ta, e.nb, st, tri_budget(e.nb, cand));
+  const hipError_t err = launch_tridiag(ta, e.nb, st, cand);
   tune_end(tk, st);
   return err;
 }
