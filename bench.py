@@ -97,6 +97,7 @@ def spectral_flop(N1: int, N2: int, M: int) -> float:
 
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix
 FP64_VALU_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 
 
 def tri_flop(n: int) -> float:
@@ -670,6 +671,38 @@ def bench_direct(args) -> int:
             return (time.perf_counter() - t0) / args.steps, pl.images()
 
     nr = lambda a, b: float(f"{np.linalg.norm(a - b) / np.linalg.norm(b):.4e}")
+
+    def direct_roofline(pb):
+        """IRLS-direct on the 128x128x16 data with its two classes timed: the Gram
+        matrix (lifting + zgemm, 8 s^2 rows flop on FP64 MFMA) and the CG (per operator
+        application lifting + cgemm, 8 s^2 rows flop on FP32 MFMA, + adjoint)."""
+        T, P, Q = pb.b.shape
+        s = pb.N1 * pb.N2 * pb.M
+        nrows = (T - pb.M + 1) * (P - pb.N1 + 1) * (Q - pb.N2 + 1)
+        prm = slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg, p=pb.p, gamma=pb.gamma,
+                               eps0_frac=pb.eps0_frac, direct=True, ktime=True, ktime_classes=("gram", "direct"))
+        with slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M, prm) as pl:
+            pl.set_kspace(pb.b)
+            pl.set_mask(pb.S)
+            pl.run()
+            pl.sync()
+            st = pl.stats()
+        kms, kcnt = st["kernel_ms"], st["kernel_count"]
+        gram_ms = kms["gram"] / kcnt["gram"]
+        cg_ms = kms["direct"] / kcnt["direct"]
+        gram_tf = 8.0 * s * s * nrows / (gram_ms * 1e-3) / 1e12
+        cg_tf = (pb.n_cg + 1) * 8.0 * s * s * nrows / (cg_ms * 1e-3) / 1e12
+        return {
+            "gram": {"bound": "mfma", "achieved": round(gram_tf, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(gram_tf / FP64_MFMA_PEAK_TFLOPS, 4),
+                     "ms_per_outer_iteration": round(gram_ms, 3), "flop": 8.0 * s * s * nrows},
+            "cg": {"bound": "mfma", "achieved": round(cg_tf, 2), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(cg_tf / FP32_MFMA_PEAK_TFLOPS, 4), "ms_per_least_squares_step": round(cg_ms, 3),
+                   "flop": (pb.n_cg + 1) * 8.0 * s * s * nrows,
+                   "note": "the GEMM flops of the n_cg + 1 operator applications over the whole CG region "
+                           "(lifting and adjoint gathers included in the time)"},
+        }
+
     rows = {}
     for name in ("c1", "c2"):
         pb = workload.config_problem(name)
@@ -691,6 +724,8 @@ def bench_direct(args) -> int:
         "note": "the paper reports 7.5x for its MATLAB implementations on real data (Fig. 2); here both methods "
                 "run on one MI355X",
     }
+    out["roofline_direct_128x128x16"] = direct_roofline(workload.config_problem("c2"))
+    out["roofline"] = dict(out["roofline_direct_128x128x16"]["cg"], kernel="direct CG (lifting, cgemm, adjoint)")
     if not args.no_cpu_baseline:
         pb = workload.config_problem("c1")
         cores = len(os.sched_getaffinity(0))
