@@ -221,7 +221,7 @@ def cpu_baseline(pb, n_outer: int = 1):
 
 
 def measure_batch(steps: int, warmup: int, slices: int = 32, oracle_seconds: float = 0.0,
-                  check_bits: bool = True) -> dict:
+                  check_bits: bool = True, grouping: int = -1) -> dict:
     """Batch of uneven slices (9x9x5, 15 x 10 each) in lock step with shared batched
     eigen-decompositions, against the same slices one plan at a time."""
     import numpy as np
@@ -231,6 +231,7 @@ def measure_batch(steps: int, warmup: int, slices: int = 32, oracle_seconds: flo
     import workload
 
     torch.cuda.set_device(0)
+    slrx.set_cg_grouping(grouping)
     specs = workload.batch_specs(slices, seed=11)
     pbs = [workload.make_problem(name=f"slice{j}", **sp) for j, sp in enumerate(specs)]
     plans = []
@@ -277,7 +278,7 @@ def measure_batch(steps: int, warmup: int, slices: int = 32, oracle_seconds: flo
             torch.cuda.synchronize()
             return len(ps) * reps / (time.perf_counter() - t)
         finally:
-            slrx.set_cg_grouping(-1)
+            slrx.set_cg_grouping(grouping)
     small = [workload.make_problem(seed=500 + i, P=64, Q=64, T=8, K=1, R=4, N1=5, N2=5, M=3, n_irls=15, n_cg=10)
              for i in range(32)]
     splans = []
@@ -318,7 +319,8 @@ def measure_batch(steps: int, warmup: int, slices: int = 32, oracle_seconds: flo
 def bench_batch(args) -> int:
     """32 independent slices of uneven sizes: lock-step batch (shared batched
     eigen-decompositions) vs one plan at a time."""
-    m = measure_batch(args.steps, args.warmup, 32, 0.0 if args.no_cpu_baseline else 10.0)
+    m = measure_batch(args.steps, args.warmup, 32, 0.0 if args.no_cpu_baseline else 10.0,
+                      grouping=args.cg_grouping)
     out = {
         "metric": "slices/s, batch of 32 uneven slices (batched vs one at a time)",
         "value": m["slices_per_s"], "unit": "slices/s", "n_gpus": 1, "steps": args.steps,
@@ -817,6 +819,47 @@ def _counter_per_kernel(root: str, sub: str):
     return agg
 
 
+def grouped_rooflines(root: str, sub: str) -> list:
+    """HBM rooflines of the grouped CG kernels of the 32-slice draw: the algorithmic
+    bytes of one grouped launch (the sum over the slices of each pass's bytes per
+    launch) over the average duration of that kernel's dispatches with the largest
+    grid (the launches that hold the whole draw; the smaller-slice draw of the
+    strategy comparison launches smaller grids)."""
+    import workload
+    specs = workload.batch_specs(32, seed=11)
+    V = sum(sp["T"] * sp["P"] * sp["Q"] for sp in specs)
+    PQ = sum(sp["P"] * sp["Q"] for sp in specs)
+    W = 15  # M = 5 for every slice of the draw
+    nbytes = {"k_group_rows": 32 * V, "k_group_pen<5>": 16 * V + 8 * W * PQ, "k_group_fin": 25 * V,
+              "k_group_update": 48 * V}
+    rows = _csv_rows(root, sub, "group_dispatches.csv")
+    gcols = [c for c in ("Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z") if c in rows[0]] or ["Grid_Size"]
+    by = {}
+    for r in rows:
+        name = _kernel_short(r["Kernel_Name"]).split("::")[-1]
+        key = next((k for k in nbytes if name.startswith(k)), None)
+        if key is None:
+            continue
+        grid = 1
+        for c in gcols:
+            grid *= int(r[c])
+        by.setdefault(key, []).append((grid, int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = ["", f"# grouped CG launches of the whole draw (sum of T*P*Q = {V} elements, {V * 8 / 1e6:.0f} MB per "
+               "complex FP32 vector: the working set is beyond the 256 MB MALL) against the 8 TB/s HBM peak: "
+               "algorithmic bytes per launch / average duration of the launches with the largest grid "
+               "(rows: the p-update launches' 32 B per element; the one initial-residual launch per outer "
+               "iteration moves 16 and is averaged in)",
+           f"{'kernel':<16} {'launches':>9} {'MB_per_launch':>14} {'avg_us':>9} {'GB_per_s':>10} {'frac_of_8TB':>12}"]
+    for key, d in by.items():
+        gmax = max(g for g, _ in d)
+        ns = [t for g, t in d if g == gmax]
+        us = sum(ns) / len(ns) * 1e-3
+        gbs = nbytes[key] / (us * 1e-6) / 1e9
+        out.append(f"{key:<16} {len(ns):>9} {nbytes[key] / 1e6:>14.1f} {us:>9.1f} {gbs:>10.1f} "
+                   f"{gbs / 8000:>12.3f}")
+    return out
+
+
 def summarize_profiles(args) -> int:
     """Write profiles/c3_kernel_trace.txt, c3_hbm_counters.txt and c3_traffic.json from
     the rocprofv3 csv output of the runs named in their headers (no GPU needed)."""
@@ -837,6 +880,11 @@ def summarize_profiles(args) -> int:
          "128x128x16 (9x9x5) workloads, 15 x 10 each: per workload and method 1 warm-up and 1 timed "
          "reconstruction", "python3 bench.py --workload direct --steps 1 --warmup 1 --no-cpu-baseline"),
     ]
+    traces.append(("prof_batch_grouped", "batch_grouped_kernel_trace.txt",
+                   "the 32-slice batch draw (96..256 squared, 8..20 echoes, 9x9x5, 15 x 10) with the CG in "
+                   "grouped launches: 1 warm-up and 1 timed batch, then the single-plan runs and the strategy "
+                   "comparisons of the batch line", "python3 bench.py --workload batch --steps 1 --warmup 1 "
+                   "--no-cpu-baseline --cg-grouping 1"))
     for sub, fname, what, cmd in traces:
         if not os.path.isdir(os.path.join(root, sub)):
             continue
@@ -850,6 +898,8 @@ def summarize_profiles(args) -> int:
             ms = float(r["TotalDurationNs"]) * 1e-6
             lines.append(f"{_kernel_short(r['Name'])[:72]:<72} {int(r['Calls']):>8} {ms:>10.3f} "
                          f"{float(r['AverageNs']) * 1e-3:>9.2f} {100 * ms * 1e6 / tot:>6.2f}")
+        if sub == "prof_batch_grouped":
+            lines += grouped_rooflines(root, sub)
         with open(os.path.join(prof, fname), "w") as f:
             f.write("\n".join(lines) + "\n")
     # counters, calibrated by the copy
@@ -939,6 +989,8 @@ def main() -> int:
                          "calib: the plain copy that calibrates the HBM counters")
     ap.add_argument("--requests", type=int, default=120, help="serve: number of requests")
     ap.add_argument("--calib-mb", type=int, default=256, help="calib: MiB copied per launch")
+    ap.add_argument("--cg-grouping", type=int, default=-1, choices=(-1, 0, 1),
+                    help="batch: CG strategy of the engine steps (-1 tuned, 0 per problem, 1 grouped launches)")
     ap.add_argument("--prof-root", default="gpurun_out",
                     help="profiles: folder holding the rocprofv3 csv output of the runs the summaries name")
     ap.add_argument("--no-extras", action="store_true",

@@ -394,9 +394,11 @@ slrx_status slrx::engine_step(const std::vector<slrx_plan*>& plans, BatchEig& be
     grouped = forced == 1 && ng >= 1;
   } else if (ng >= 2) {
     bool settled = true;
-    for (auto& kv : groups)
-      settled = settled && (tri_budget_candidates((int)kv.second.size()) <= 1 ||
-                            tune_choice(TUNE_TRI, kv.first, (int)kv.second.size(), 0) >= 0);
+    for (auto& kv : groups) {
+      const int nb = (int)kv.second.size();
+      const int c = tune_choice(TUNE_TRI, kv.first, nb, 0);
+      settled = settled && c >= 0 && tune_choice(TUNE_TRI_ACCESS, kv.first, nb, c) >= 0;
+    }
     if (settled) {
       if (!be.cg_stream) {
         HIPCHK(hipStreamCreateWithFlags(&be.cg_stream, hipStreamNonBlocking));

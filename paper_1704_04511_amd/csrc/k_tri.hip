@@ -44,6 +44,26 @@ template <int U> constexpr int tri_rb() { return U > 10 ? 1 : (U > 8 ? 2 : kTriR
 constexpr int kTriRMax = 32;   // rows per workgroup at most
 
 SLRX_DEV double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// Trailing-block rows are read and written once per column launch.  STREAM
+// marks those accesses nontemporal (the nt cache-policy bit of the load and
+// store instructions); the values are the same either way.
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <bool STREAM> SLRX_DEV double2 row_load(const double2* p) {
+  if constexpr (STREAM) {
+    const d2v v = __builtin_nontemporal_load((const d2v*)p);
+    return make_double2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+template <bool STREAM> SLRX_DEV void row_store(double2* p, double2 e) {
+  if constexpr (STREAM) {
+    const d2v v = {e.x, e.y};
+    __builtin_nontemporal_store(v, (d2v*)p);
+  } else {
+    *p = e;
+  }
+}
 SLRX_DEV double2 dscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
 // Copy of v from the lane selected by a DPP control (rows masked by RM keep 0).
@@ -78,8 +98,9 @@ SLRX_DEV double2 sum4(const double2* s, int stride) {
 }
 
 // One column of the reduction.  U: vector entries per thread (n - k <= 256 U);
-// rows: rows of the trailing block per workgroup (blockIdx.x * rows + k + 1 ..).
-template <int U>
+// rows: rows of the trailing block per workgroup (blockIdx.x * rows + k + 1 ..);
+// STREAM: nontemporal row accesses.
+template <int U, bool STREAM>
 __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
   // exchange slots: [wave][item] for the three reductions
   __shared__ double2 xa[4][3];
@@ -120,7 +141,7 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = k + tid + kTriNT * u;
-      xr[r][u] = (r < nrow && j > k && j < n) ? Aw[(size_t)(row0 + r) * n + j] : zero;
+      xr[r][u] = (r < nrow && j > k && j < n) ? row_load<STREAM>(&Aw[(size_t)(row0 + r) * n + j]) : zero;
     }
 
   // 1. d = p^H v of the pending reflector; p_{k-1}(k), v_{k-1}(k) ride along
@@ -224,7 +245,7 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
         double2 e = x[u];
         if (pending) {
           e = dsub(e, dadd(dmul(vi, dconj(w[u])), dmul(wi, dconj(vp[u]))));
-          Aw[(size_t)i * n + j] = e;
+          row_store<STREAM>(&Aw[(size_t)i * n + j], e);
         }
         acc = dadd(acc, dmul(e, v[u]));
       }
@@ -241,7 +262,8 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = k + tid + kTriNT * u;
-        xr[r][u] = (r0 + r < nrow && j > k && j < n) ? Aw[(size_t)(row0 + r0 + r) * n + j] : zero;
+        xr[r][u] = (r0 + r < nrow && j > k && j < n) ? row_load<STREAM>(&Aw[(size_t)(row0 + r0 + r) * n + j])
+                                                     : zero;
       }
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -402,10 +424,11 @@ int tri_max_n() { return 3000; }
 static size_t tail_lds(int L) { return (size_t)(2 * L * L + 3 * L) * sizeof(double2) + 2 * (size_t)L * sizeof(double); }
 
 template <int U>
-static void launch_col(const TriArgs& a, int nbatch, int rows, hipStream_t s) {
+static void launch_col(const TriArgs& a, int nbatch, int rows, bool stream, hipStream_t s) {
   const int nr = a.n - a.k - 1;
   const dim3 grid((nr + rows - 1) / rows, nbatch);
-  k_tri_col<U><<<grid, kTriNT, 0, s>>>(a, rows);
+  if (stream) k_tri_col<U, true><<<grid, kTriNT, 0, s>>>(a, rows);
+  else k_tri_col<U, false><<<grid, kTriNT, 0, s>>>(a, rows);
 }
 
 // Workgroup budgets per column launch (all problems of a batch together) the
@@ -413,13 +436,16 @@ static void launch_col(const TriArgs& a, int nbatch, int rows, hipStream_t s) {
 // problems want more rows per workgroup than one large one.
 // One problem also tries 256 with long columns split so that every row of a
 // workgroup is loaded at kernel entry (kTriRB rows each, up to 320 workgroups):
-// 8.03 against 8.13 ms per 1125 x 1125 decomposition when measured.
+// 8.03 against 8.13 ms per 1125 x 1125 decomposition when measured.  The row
+// access policy is tuned afterwards for the chosen budget: nontemporal rows took
+// 7.15 against 8.04 ms for one 1125 x 1125 problem, but made a batch of 32
+// problems of 405 about 6% slower.
 static const int kTriBudget1[] = {128, 256, 256};
 static const int kTriBudgetN[] = {256, 512, 1024, 2048, 4096};
 int tri_budget_candidates(int nbatch) { return nbatch > 1 ? 5 : 3; }
 int tri_budget(int nbatch, int cand) { return nbatch > 1 ? kTriBudgetN[cand] : kTriBudget1[cand]; }
 
-hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int cand) {
+hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int cand, bool stream) {
   const int budget = tri_budget(nbatch, cand);
   const bool fit = nbatch == 1 && cand == 2;
   const int n = base.n;
@@ -443,16 +469,16 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int ca
     const int u = (n - k + kTriNT - 1) / kTriNT;      // vector entries per thread
     const int rbu = u > 10 ? 1 : (u > 8 ? 2 : kTriRB); // rows loaded at entry (tri_rb<U>)
     if (fit && rows > rbu && (nr + rbu - 1) / rbu <= 320) rows = rbu;
-    if (u <= 1) launch_col<1>(a, nbatch, rows, s);
-    else if (u <= 2) launch_col<2>(a, nbatch, rows, s);
-    else if (u <= 3) launch_col<3>(a, nbatch, rows, s);
-    else if (u <= 4) launch_col<4>(a, nbatch, rows, s);
-    else if (u <= 5) launch_col<5>(a, nbatch, rows, s);
-    else if (u <= 6) launch_col<6>(a, nbatch, rows, s);
-    else if (u <= 8) launch_col<8>(a, nbatch, rows, s);
-    else if (u <= 9) launch_col<9>(a, nbatch, rows, s);
-    else if (u <= 10) launch_col<10>(a, nbatch, rows, s);
-    else launch_col<12>(a, nbatch, rows, s);
+    if (u <= 1) launch_col<1>(a, nbatch, rows, stream, s);
+    else if (u <= 2) launch_col<2>(a, nbatch, rows, stream, s);
+    else if (u <= 3) launch_col<3>(a, nbatch, rows, stream, s);
+    else if (u <= 4) launch_col<4>(a, nbatch, rows, stream, s);
+    else if (u <= 5) launch_col<5>(a, nbatch, rows, stream, s);
+    else if (u <= 6) launch_col<6>(a, nbatch, rows, stream, s);
+    else if (u <= 8) launch_col<8>(a, nbatch, rows, stream, s);
+    else if (u <= 9) launch_col<9>(a, nbatch, rows, stream, s);
+    else if (u <= 10) launch_col<10>(a, nbatch, rows, stream, s);
+    else launch_col<12>(a, nbatch, rows, stream, s);
   }
   const int L = n - k0;
   k_tri_tail<<<dim3(1, nbatch), kTailNT, tail_lds(L), s>>>(a, k0);

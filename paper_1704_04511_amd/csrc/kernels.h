@@ -269,8 +269,9 @@ struct TriArgs {
 };
 // cand: the tuner's candidate launch shape (tri_budget: workgroups per column
 // launch across the batch; for one problem candidate 2 also caps the rows per
-// workgroup at those loaded at kernel entry); results do not depend on it.
-hipError_t launch_tridiag(const TriArgs& a, int nbatch, hipStream_t s, int cand);
+// workgroup at those loaded at kernel entry); stream: nontemporal loads and
+// stores of the trailing-block rows.  Results depend on neither.
+hipError_t launch_tridiag(const TriArgs& a, int nbatch, hipStream_t s, int cand, bool stream);
 int tri_budget_candidates(int nbatch);
 int tri_budget(int nbatch, int cand);
 int tri_max_n();

@@ -174,11 +174,16 @@ hipError_t slrx::eigh_tri(const EighBufs& e, hipStream_t st) {
   ta.vbuf[1] = e.triv[1];
   ta.pbuf[0] = e.trip[0];
   ta.pbuf[1] = e.trip[1];
-  // workgroups per launch: tuned per (n, problems) on the first decompositions
-  TuneTicket tk;
+  // workgroups per launch: tuned per (n, problems) on the first decompositions;
+  // then the row access policy for the chosen budget
+  TuneTicket tk, tk_access;
   const int cand = tune_begin(TUNE_TRI, e.n, e.nb, 0, tri_budget_candidates(e.nb), st, tk);
-  const hipError_t err = launch_tridiag(ta, e.nb, st, cand);
+  bool stream = false;
+  if (tune_choice(TUNE_TRI, e.n, e.nb, 0) == cand)
+    stream = tune_begin(TUNE_TRI_ACCESS, e.n, e.nb, cand, 2, st, tk_access) == 1;
+  const hipError_t err = launch_tridiag(ta, e.nb, st, cand, stream);
   tune_end(tk, st);
+  tune_end(tk_access, st);
   return err;
 }
 

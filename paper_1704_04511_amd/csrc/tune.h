@@ -9,6 +9,8 @@ enum TuneKind {
   TUNE_TRI = 1,       // Householder tridiagonalisation: workgroups per column launch (a = n, b = problems)
   TUNE_CG_GROUP = 2,  // engine step: the CG of each problem on its own stream (0) or grouped launches (1)
                       // (a = problems, b = their summed volume / 4096, c = largest M << 16 | largest n_cg)
+  TUNE_TRI_ACCESS = 3,  // tridiagonalisation rows cached (0) or nontemporal (1), once TUNE_TRI has chosen
+                        // (a = n, b = problems, c = the chosen TUNE_TRI candidate)
 };
 
 // Timing of one call made with a candidate configuration.

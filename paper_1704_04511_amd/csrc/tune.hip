@@ -8,8 +8,9 @@
 // for the rest of the process and appended to the file named by the
 // SLRX_TUNE_CACHE environment variable, if set, which later processes read
 // back instead of tuning again.  Only choices that leave results unchanged bit
-// for bit are tuned this way (how rows are split among workgroups), so the
-// calls made while tuning are ordinary calls.
+// for bit are tuned this way (how rows are split among workgroups, cache
+// policies, how launches are grouped), so the calls made while tuning are
+// ordinary calls.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>

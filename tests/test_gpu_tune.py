@@ -1,9 +1,10 @@
 """The online tuner of launch configurations: while it tries the candidate
 workgroup budgets of the tridiagonalisation on the first decompositions of a
-shape, and after it has chosen, results stay the same bit for bit (the row
-split among workgroups does not enter the arithmetic); it settles on a choice
-for the batch shape; and with SLRX_TUNE_CACHE set the choice is written to
-that file."""
+shape, then the row access policy (cached or nontemporal) for the chosen
+budget, and after it has chosen, results stay the same bit for bit (neither the
+row split among workgroups nor the cache policy enters the arithmetic); it
+settles on both choices for the batch shape; and with SLRX_TUNE_CACHE set the
+choices are written to that file."""
 import os
 
 import numpy as np
@@ -40,8 +41,12 @@ def test_tuned_batches_are_bitwise_stable_and_settle(tmp_path):
         budget = int(slrx.lib().slrx_tri_workgroup_budget(108, 5))
         say(f"tuned workgroup budget for 5 x 108: {budget}")
         assert budget in (256, 512, 1024, 2048, 4096)
-        lines = (tmp_path / "tune.txt").read_text().split()
-        assert len(lines) >= 7 and lines[2:4] == ["108", "5"]
+        rows = [[int(x) for x in ln.split()] for ln in (tmp_path / "tune.txt").read_text().splitlines()]
+        # device kind a b c ncand chosen
+        budget_rows = [r for r in rows if r[1] == 1 and r[2:4] == [108, 5]]
+        access_rows = [r for r in rows if r[1] == 3 and r[2:4] == [108, 5]]
+        assert len(budget_rows) == 1 and len(access_rows) == 1, rows
+        assert access_rows[0][4] == budget_rows[0][6] and access_rows[0][5:] in ([2, 0], [2, 1])
     finally:
         os.environ.pop("SLRX_TUNE_CACHE", None)
         for pl in plans:
