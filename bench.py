@@ -866,6 +866,10 @@ def summarize_profiles(args) -> int:
     root = args.prof_root
     prof = os.path.join(ROOT, "profiles")
     pre = "cd /tmp && export TMPDIR=/tmp && cd /root/repo && "
+    # the c3 runs share one tuner cache: an unprofiled run of the same command
+    # settles and records the launch choices first (a profiler changes the timings
+    # they are made from), and every profiled run reads them back
+    pre_c3 = pre + "export SLRX_TUNE_CACHE=gpurun_out/tune_c3.txt && "
     c3 = "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-extras"
     c3_pmc = "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --n-irls 2"
     calib = "python3 bench.py --workload calib --calib-mb 256"
@@ -890,10 +894,15 @@ def summarize_profiles(args) -> int:
             continue
         st = _csv_rows(root, sub, "kernel_stats.csv")
         tot = sum(float(r["TotalDurationNs"]) for r in st)
-        lines = [f"# Kernel trace, {what}",
-                 f"# command: {pre}rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/{sub} -o run -- {cmd}",
-                 "# durations from the kernel trace (rocprofv3 kernel_stats)",
-                 f"{'kernel':<72} {'calls':>8} {'total_ms':>10} {'avg_us':>9} {'pct':>6}"]
+        lines = [f"# Kernel trace, {what}"]
+        if sub == "prof_c3":
+            lines.append("# the tuner's launch choices read from that cache, recorded first by the same command "
+                         "without the profiler")
+        lines += [
+                  f"# command: {pre_c3 if sub == 'prof_c3' else pre}rocprofv3 --kernel-trace --stats -f csv "
+                  f"-d gpurun_out/{sub} -o run -- {cmd}",
+                  "# durations from the kernel trace (rocprofv3 kernel_stats)",
+                  f"{'kernel':<72} {'calls':>8} {'total_ms':>10} {'avg_us':>9} {'pct':>6}"]
         for r in sorted(st, key=lambda r: -float(r["TotalDurationNs"])):
             ms = float(r["TotalDurationNs"]) * 1e-6
             lines.append(f"{_kernel_short(r['Name'])[:72]:<72} {int(r['Calls']):>8} {ms:>10.3f} "
@@ -902,7 +911,14 @@ def summarize_profiles(args) -> int:
             lines += grouped_rooflines(root, sub)
         with open(os.path.join(prof, fname), "w") as f:
             f.write("\n".join(lines) + "\n")
-    # counters, calibrated by the copy
+    # counters, calibrated by the copy; stamped with the hash of the kernel sources
+    # that the counter runs profiled (written on the GPU side before those runs)
+    hfile = os.path.join(root, "pmc_source_sha256.txt")
+    if not os.path.isfile(hfile):
+        print(json.dumps({"written": "kernel traces only", "note": f"{hfile} missing: counters not summarised"}))
+        return 0
+    with open(hfile) as f:
+        profiled_hash = f.read().strip()
     fetch = _counter_per_kernel(root, "pmc_fetch")
     write = _counter_per_kernel(root, "pmc_write")
     cf = _counter_per_kernel(root, "pmc_copy_fetch")
@@ -913,8 +929,10 @@ def summarize_profiles(args) -> int:
     sf, sw = kib / f_copy, kib / w_copy
     lines = ["# HBM traffic per dispatch, 256x256x20 workload (filter 15x15x5), two outer iterations",
              "# commands (each its own run):",
-             f"#   {pre}rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o run -- {c3_pmc}",
-             f"#   {pre}rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o run -- {c3_pmc}",
+             f"#   {pre_c3}rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o run -- {c3_pmc}",
+             f"#   {pre_c3}rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o run -- {c3_pmc}",
+             "# (the tuner's launch choices read from that cache, recorded by an unprofiled run of the "
+             "command of c3_kernel_trace.txt)",
              f"# calibration: a {args.calib_mb} MiB device copy ({copy_k}) under the same counters:",
              f"#   {pre}rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_copy_fetch -o run -- {calib}",
              f"#   {pre}rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_copy_write -o run -- {calib}",
@@ -943,7 +961,7 @@ def summarize_profiles(args) -> int:
             units = sum(per[k][0] for k in names if k.split("::")[-1].startswith(main))
         if names and units:
             bpl[cls] = total / units
-    rec = {"source_sha256": kernel_source_hash(), "workload": "256x256x20 filter 15x15x5",
+    rec = {"source_sha256": profiled_hash, "workload": "256x256x20 filter 15x15x5",
            "scale_fetch": sf, "scale_write": sw, "bytes_per_launch": bpl}
     with open(os.path.join(prof, "c3_traffic.json"), "w") as f:
         json.dump(rec, f, indent=1)
