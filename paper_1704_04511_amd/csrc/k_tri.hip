@@ -23,8 +23,8 @@
 // threads need (p_k, v_k, the subdiagonal entry, the rows' own coefficients)
 // passed through the same exchange.  Results are bit-reproducible and do not
 // depend on how many workgroups run or which rows a workgroup takes.
-// The last columns, once the trailing block fits in the LDS of one workgroup,
-// are reduced in a single launch (k_tri_tail).
+// The last 128 columns, whose trailing block fits in the registers of one
+// workgroup, are reduced in a single launch (k_tri_tail).
 // The working matrix Aw is full (both triangles) and row-major; reflectors are
 // stored as LAPACK's zhetrd (lower) stores them: v(k+2:n) in column k of the
 // column-major matrix Vst below the subdiagonal, tau(k), diagonal D, real
@@ -273,155 +273,210 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
   if (tid < nrow) pout[row0 + tid] = sum4(&xc[0][tid], kTriRMax);
 }
 
-// The last kTriTail columns in one launch: the trailing block (rows and columns
-// k0..n-1) is small enough for the LDS of one workgroup, so its columns need
-// only block barriers instead of launches.  First the pending update of
-// reflector k0-1 is applied to the block, then each column is reduced as in
-// k_tri_col (same reflector convention, same outputs), the rank-2 update
-// applied to the whole block.  The outputs are kept in LDS and written at the
-// end: a barrier waits for the wave's outstanding stores.
-constexpr int kTriTail = 64;
-constexpr int kTailNT = 256;
+// The last kTriTail columns in one launch, one workgroup of 512 threads per
+// problem with the trailing block (rows and columns k0..n-1, at most 128 x 128)
+// in registers: thread t holds row i = t / 4 at the columns j = t % 4 + 4 c,
+// c = 0..31, zero beyond the block.  First the pending update of reflector
+// k0-1 is applied, then each column is reduced as in k_tri_col (same reflector
+// convention, same outputs): the wave holding row k forms reflector k from it
+// (the block is Hermitian, so column k below the diagonal is the conjugate of
+// row k) and publishes v; every row forms its entry of p = A v (four lanes, a
+// fixed DPP tree) and p^H v is summed over the waves in order; then the rank-2
+// update runs on the registers, written as
+//   A - v w^H - w v^H = A - conj(tau) v p^H - (tau p + 2 Re(c d) v) v^H
+// for w = tau p + c d v, c = -|tau|^2 / 2, d = p^H v (real for a Hermitian A).
+// v and p are zero outside rows k+1.., so the update leaves the finished rows
+// and columns unchanged without masks (slots are skipped in chunks of eight,
+// whose loads the compiler can then issue together); v and p are double-buffered by column
+// parity, which leaves two barriers per column.  The outputs stay in LDS until
+// the end (a barrier would otherwise wait for each column's global stores).
+constexpr int kTriTail = 128;
+constexpr int kTailNT = 512;
+constexpr int kTailLanes = 4;                   // lanes per row
+constexpr int kTailC = kTriTail / kTailLanes;   // columns per thread
+constexpr int kTailRowsW = 64 / kTailLanes;     // rows per wave
+constexpr int kTailChunk = 8;                   // column slots skipped or processed together
+// packed reflectors of the block: column kk's entries kk+1..L-1 at voff(kk)
+__host__ __device__ inline int tail_voff(int L, int kk) { return kk * (2 * L - kk - 1) / 2; }
+inline size_t tail_lds(int L) { return (size_t)tail_voff(L, L - 1) * sizeof(double2); }
 
-// Sum over the 64 lanes of a wave, every lane gets the total (fixed order).
-SLRX_DEV double2 wave_sum2(double2 v) {
-  for (int off = 1; off < 64; off <<= 1) {
-    v.x += __shfl_xor(v.x, off, 64);
-    v.y += __shfl_xor(v.y, off, 64);
-  }
+// Sum over each aligned quad of lanes (fixed order); every lane of the quad
+// gets its total.  Call with all 64 lanes active.
+SLRX_DEV double sum_quad(double v) {
+  v += dpp_mov<0xB1, 0xf>(v);  // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E, 0xf>(v);  // quad_perm [2,3,0,1]
   return v;
+}
+SLRX_DEV double2 sum_quad2(double2 v) { return make_double2(sum_quad(v.x), sum_quad(v.y)); }
+// LDS writes of a wave made visible to its other lanes (a wave executes its LDS
+// accesses in order; the fences keep the compiler from moving them across).
+SLRX_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+SLRX_DEV double readlane_d(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
 }
 
 __global__ __launch_bounds__(kTailNT) void k_tri_tail(TriArgs a, int k0) {
-  extern __shared__ double2 sm[];
-  __shared__ double2 sc[4];  // tau, scale, d; beta in sc[3].x
+  extern __shared__ double2 vl[];  // reflectors, packed (tail_voff)
+  __shared__ double2 vs[2][kTriTail], ps[2][kTriTail];
+  __shared__ double2 xrow[kTriTail];  // row k, exchanged within the wave holding it
+  __shared__ double2 tl[kTriTail];
+  __shared__ double Dl[kTriTail], El[kTriTail];
+  __shared__ double2 red[kTailNT / 64];
+  __shared__ double2 tau_s[2];
   const int n = a.n, L = n - k0;
   const int b = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double2* B = sm;           // L x L block, row-major, B[i][j] = A(k0 + i, k0 + j)
-  double2* vv = B + L * L;   // reflector
-  double2* pw = vv + L;      // A v
-  double2* Vl = pw + L;      // reflectors of the block, column kk at Vl[kk * L]
-  double2* tl = Vl + L * L;  // tau
-  double* Dl = (double*)(tl + L);
-  double* El = Dl + L;
+  const int i = tid / kTailLanes, q = tid % kTailLanes;
   const double2* Aw = a.Aw + (size_t)b * a.strideA;
-  double2* Vst = a.Vst + (size_t)b * a.strideA;
-  double* D = a.D + (size_t)b * n;
-  double* E = a.E + (size_t)b * n;
-  double2* taus = a.tau + (size_t)b * n;
   const double2 zero = make_double2(0.0, 0.0);
-  for (int e = tid; e < L * L; e += kTailNT) B[e] = Aw[(size_t)(k0 + e / L) * n + k0 + e % L];
-  if (k0 > 0) {  // pending update of reflector k0-1: w = tau p + c (p^H v) v
+  double2 A[kTailC];
+#pragma unroll
+  for (int c = 0; c < kTailC; ++c) {
+    const int j = q + kTailLanes * c;
+    A[c] = (i < L && j < L) ? Aw[(size_t)(k0 + i) * n + k0 + j] : zero;
+  }
+  // the rank-2 update of one reflector from v and p in LDS slot s; columns from slot c0
+  auto rank2 = [&](int s, double2 t, double2 d, double2 vi, double2 pi, int c0) __attribute__((always_inline)) {
+    const double2 al = dmul(dconj(t), vi);                                    // conj(tau) v_i
+    const double2 be = dadd(dmul(t, pi), dscale(vi, -(t.x * t.x + t.y * t.y) * d.x));  // tau p_i + 2 Re(c d) v_i
+#pragma unroll
+    for (int h = 0; h < kTailC / kTailChunk; ++h) {
+      if (kTailChunk * h + kTailChunk - 1 < c0) continue;  // chunks of slots left of the block
+#pragma unroll
+      for (int u = 0; u < kTailChunk; ++u) {
+        const int c = kTailChunk * h + u, j = q + kTailLanes * c;
+        const double2 pj = ps[s][j], vj = vs[s][j];
+        A[c] = dsub(A[c], dadd(dmul(al, dconj(pj)), dmul(be, dconj(vj))));
+      }
+    }
+  };
+  // p^H v from the rows' terms: per wave in a fixed tree, then the waves in order
+  auto wave_sums = [&](double2 part) __attribute__((always_inline)) {
+    part = wave_total2(part);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    double2 d = red[0];
+#pragma unroll
+    for (int w = 1; w < kTailNT / 64; ++w) d = dadd(d, red[w]);
+    return d;
+  };
+  if (k0 > 0) {  // pending update of reflector k0-1 (v, p from the last column launch)
     const double2* vprev = a.vbuf[(k0 + 1) & 1] + (size_t)b * n + k0;
     const double2* pprev = a.pbuf[(k0 + 1) & 1] + (size_t)b * n + k0;
-    const double2 t = taus[k0 - 1];
-    if (tid < L) {
-      vv[tid] = vprev[tid];
-      pw[tid] = pprev[tid];
+    if (tid < kTriTail) {
+      vs[1][tid] = tid < L ? vprev[tid] : zero;
+      ps[1][tid] = tid < L ? pprev[tid] : zero;
     }
-    if (wave == 0) {
-      const double2 d = wave_sum2(lane < L ? dcmul(pprev[lane], vprev[lane]) : zero);
-      if (lane == 0) sc[2] = d;
-    }
+    const double2 vi = i < L ? vprev[i] : zero, pi = i < L ? pprev[i] : zero;
+    const double2 d = wave_sums(q == 0 ? dcmul(pi, vi) : zero);  // its barrier also publishes vs, ps
+    rank2(1, a.tau[(size_t)b * n + k0 - 1], d, vi, pi, 0);
     __syncthreads();
-    const double c = -0.5 * (t.x * t.x + t.y * t.y);
-    const double2 cd = dscale(sc[2], c);
-    for (int e = tid; e < L * L; e += kTailNT) {
-      const int i = e / L, j = e % L;
-      const double2 wi = dadd(dmul(t, pw[i]), dmul(cd, vv[i]));
-      const double2 wj = dadd(dmul(t, pw[j]), dmul(cd, vv[j]));
-      B[e] = dsub(B[e], dadd(dmul(vv[i], dconj(wj)), dmul(wi, dconj(vv[j]))));
-    }
   }
-  __syncthreads();
   for (int kk = 0; kk < L - 1; ++kk) {
-    // 1. reflector from x = column kk below the diagonal (B Hermitian: x_i = conj(B[kk][i]))
-    if (wave == 0) {
-      const int i = kk + 2 + lane;
-      double2 x = i < L ? B[kk * L + i] : zero;
-      const double xn2 = wave_sum2(make_double2(x.x * x.x + x.y * x.y, 0.0)).x;
-      if (lane == 0) {
-        const double2 alpha = dconj(B[kk * L + kk + 1]);
-        double beta;
-        double2 tau, scale;
-        if (xn2 == 0.0 && alpha.y == 0.0) {
-          tau = zero;
-          beta = alpha.x;
-          scale = zero;
-        } else {
-          const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
-          beta = alpha.x >= 0.0 ? -nrm : nrm;
-          tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-          const double2 den = make_double2(alpha.x - beta, alpha.y);
-          const double dd = den.x * den.x + den.y * den.y;
-          scale = make_double2(den.x / dd, -den.y / dd);
+    const int s = kk & 1;
+    const int c1 = (kk + 1) / kTailLanes;  // first column slot that can be in the trailing block
+    // 1. reflector kk from row kk (x_j = conj A(kk, j), j >= kk + 2; alpha = conj A(kk, kk + 1))
+    if (wave == kk / kTailRowsW) {
+      const bool mine = i == kk;
+      double xn = 0.0;
+      if (mine) {
+#pragma unroll
+        for (int c = 0; c < kTailC; ++c) {
+          const int j = q + kTailLanes * c;
+          if (j >= kk + 2) xn += A[c].x * A[c].x + A[c].y * A[c].y;
+          xrow[j] = A[c];
         }
-        sc[0] = tau;
-        sc[1] = scale;
-        sc[3] = make_double2(beta, 0.0);
-        Dl[kk] = B[kk * L + kk].x;
+      }
+      xn = sum_quad(xn);
+      wave_sync();  // row kk in xrow for the whole wave
+      const double xn2 = readlane_d(xn, (kk % kTailRowsW) * kTailLanes);
+      const double2 alpha = dconj(xrow[kk + 1]);
+      const double dk = xrow[kk].x;
+      double beta;
+      double2 tau, scale;
+      if (xn2 == 0.0 && alpha.y == 0.0) {
+        tau = zero;
+        beta = alpha.x;
+        scale = zero;
+      } else {
+        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+        beta = alpha.x >= 0.0 ? -nrm : nrm;
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double2 den = make_double2(alpha.x - beta, alpha.y);  // scale = 1 / (alpha - beta)
+        const double dd = den.x * den.x + den.y * den.y;
+        scale = make_double2(den.x / dd, -den.y / dd);
+      }
+      // v from the row in xrow: lane l writes entries l, l + 64 (all 128 slots)
+      const int vo = tail_voff(L, kk) - kk - 1;
+#pragma unroll
+      for (int h = 0; h < kTriTail / 64; ++h) {
+        const int j = lane + 64 * h;
+        const double2 v = j == kk + 1 ? make_double2(1.0, 0.0)
+                                      : (j >= kk + 2 && j < L ? dmul(dconj(xrow[j]), scale) : zero);
+        vs[s][j] = v;
+        if (j > kk && j < L) vl[vo + j] = j == kk + 1 ? make_double2(beta, 0.0) : v;
+      }
+      if (lane == 0) {
+        tau_s[s] = tau;
+        Dl[kk] = dk;
         El[kk] = beta;
         tl[kk] = tau;
       }
     }
     __syncthreads();
-    const double2 tau = sc[0], scale = sc[1];
-    for (int i = kk + 1 + tid; i < L; i += kTailNT) {
-      const double2 v = (i == kk + 1) ? make_double2(1.0, 0.0) : dmul(dconj(B[kk * L + i]), scale);
-      vv[i] = v;
-      Vl[kk * L + i] = (i == kk + 1) ? sc[3] : v;
+    // 2. p_i = sum_j A_ij v_j for the rows of the trailing block, p^H v
+    const double2 vi = vs[s][i];
+    double2 pi = zero;
+    const bool live = wave * kTailRowsW + kTailRowsW - 1 >= kk + 1;  // the wave holds trailing rows
+    if (live) {
+      double2 acc[4] = {zero, zero, zero, zero};  // four chains, added in order
+#pragma unroll
+      for (int h = 0; h < kTailC / kTailChunk; ++h) {
+        if (kTailChunk * h + kTailChunk - 1 < c1) continue;
+#pragma unroll
+        for (int u = 0; u < kTailChunk; ++u) {
+          const int c = kTailChunk * h + u;
+          acc[u & 3] = dadd(acc[u & 3], dmul(A[c], vs[s][q + kTailLanes * c]));
+        }
+      }
+      pi = sum_quad2(dadd(dadd(acc[0], acc[1]), dadd(acc[2], acc[3])));
+      if (i <= kk || i >= L) pi = zero;
     }
-    __syncthreads();
-    // 2. p = B v on the trailing rows: four threads per row, p_i = sum_j conj(B[j][i]) v_j
-    {
-      const int i = kk + 1 + (tid >> 2), q = tid & 3;
-      double2 acc = zero;
-      if (i < L)
-        for (int j = kk + 1 + q; j < L; j += 4) acc = dadd(acc, dmul(dconj(B[j * L + i]), vv[j]));
-      acc.x += __shfl_xor(acc.x, 1, 64);
-      acc.y += __shfl_xor(acc.y, 1, 64);
-      acc.x += __shfl_xor(acc.x, 2, 64);
-      acc.y += __shfl_xor(acc.y, 2, 64);
-      if (i < L && q == 0) pw[i] = acc;
-    }
-    __syncthreads();
-    // 3. d = p^H v, then the rank-2 update with w = tau p + c d v formed on the fly
-    if (wave == 0) {
-      const int i = kk + 1 + lane;
-      const double2 d = wave_sum2(i < L ? dcmul(pw[i], vv[i]) : zero);
-      if (lane == 0) sc[2] = d;
-    }
-    __syncthreads();
-    const double c = -0.5 * (tau.x * tau.x + tau.y * tau.y);
-    const double2 cd = dscale(sc[2], c);
-    const int T = L - kk - 1;
-    for (int e = tid; e < T * T; e += kTailNT) {
-      const int i = kk + 1 + e / T, j = kk + 1 + e % T;
-      const double2 wi = dadd(dmul(tau, pw[i]), dmul(cd, vv[i]));
-      const double2 wj = dadd(dmul(tau, pw[j]), dmul(cd, vv[j]));
-      B[i * L + j] = dsub(B[i * L + j], dadd(dmul(vv[i], dconj(wj)), dmul(wi, dconj(vv[j]))));
-    }
-    __syncthreads();
+    if (q == 0) ps[s][i] = pi;
+    const double2 d = wave_sums(q == 0 ? dcmul(pi, vi) : zero);
+    // 3. the rank-2 update of the trailing block
+    if (live) rank2(s, tau_s[s], d, vi, pi, c1);
   }
-  if (tid == 0) Dl[L - 1] = B[(L - 1) * L + L - 1].x;
+  if (wave == (L - 1) / kTailRowsW) {  // the last diagonal entry
+    if (i == L - 1) {
+#pragma unroll
+      for (int c = 0; c < kTailC; ++c) xrow[q + kTailLanes * c] = A[c];
+    }
+    wave_sync();
+    if (lane == 0) Dl[L - 1] = xrow[L - 1].x;
+  }
   __syncthreads();
-  for (int e = tid; e < (L - 1) * L; e += kTailNT) {
-    const int kk = e / L, i = e % L;
-    if (i > kk) Vst[(size_t)(k0 + kk) * n + k0 + i] = Vl[kk * L + i];
+  double2* Vst = a.Vst + (size_t)b * a.strideA;
+  for (int kk = 0; kk < L - 1; ++kk) {
+    const int vo = tail_voff(L, kk) - kk - 1;
+    for (int j = kk + 1 + tid; j < L; j += kTailNT) Vst[(size_t)(k0 + kk) * n + k0 + j] = vl[vo + j];
   }
   for (int kk = tid; kk < L; kk += kTailNT) {
-    D[k0 + kk] = Dl[kk];
+    a.D[(size_t)b * n + k0 + kk] = Dl[kk];
     if (kk < L - 1) {
-      E[k0 + kk] = El[kk];
-      taus[k0 + kk] = tl[kk];
+      a.E[(size_t)b * n + k0 + kk] = El[kk];
+      a.tau[(size_t)b * n + k0 + kk] = tl[kk];
     }
   }
 }
 
 int tri_max_n() { return 3000; }
-
-static size_t tail_lds(int L) { return (size_t)(2 * L * L + 3 * L) * sizeof(double2) + 2 * (size_t)L * sizeof(double); }
 
 template <int U>
 static void launch_col(const TriArgs& a, int nbatch, int rows, bool stream, hipStream_t s) {
@@ -450,13 +505,6 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int ca
   const bool fit = nbatch == 1 && cand == 2;
   const int n = base.n;
   if (n > tri_max_n()) return hipErrorInvalidValue;
-  static bool tail_attr = false;
-  if (!tail_attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_tri_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)tail_lds(kTriTail));
-    if (e != hipSuccess) return e;
-    tail_attr = true;
-  }
   const int k0 = n > kTriTail ? n - kTriTail : 0;  // columns k0.. in one launch
   TriArgs a = base;
   for (int k = 0; k < k0; ++k) {
@@ -479,6 +527,13 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int ca
     else if (u <= 9) launch_col<9>(a, nbatch, rows, stream, s);
     else if (u <= 10) launch_col<10>(a, nbatch, rows, stream, s);
     else launch_col<12>(a, nbatch, rows, stream, s);
+  }
+  static bool tail_attr = false;
+  if (!tail_attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_tri_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)tail_lds(kTriTail));
+    if (e != hipSuccess) return e;
+    tail_attr = true;
   }
   const int L = n - k0;
   k_tri_tail<<<dim3(1, nbatch), kTailNT, tail_lds(L), s>>>(a, k0);
