@@ -120,6 +120,31 @@ def test_weights_at_the_largest_filters(shape):
         assert nrmse(E[w], E_ref[m, mp]) < 2e-5, (m, mp)
 
 
+@pytest.mark.parametrize("shape", [(4, 16, 128, 1, 127, 1), (8, 32, 32, 4, 4, 8), (4, 64, 64, 1, 43, 3),
+                                   (4, 32, 32, 5, 13, 2), (4, 64, 64, 2, 43, 3)])
+def test_weights_around_the_last_columns_kernel(shape):
+    """Gram sizes 127, 128, 129, 130 and 258: the tridiagonalisation's last 128
+    columns run in one register-resident workgroup, so 127 and 128 never launch a
+    column kernel, 129 and 130 hand one or two columns' pending update to it, and
+    258 crosses from two vector entries per thread to one in the column launches."""
+    T, P, Q, N1, N2, M = shape
+    say(f"weights around the last-columns kernel {shape} (s = {N1 * N2 * M})")
+    rng, x, _ = problem(11, T, P, Q)
+    R_ref = oracle.gram(x.astype(np.complex128), N1, N2, M)
+    lam_ref = np.linalg.eigvalsh(R_ref)
+    eps = 0.01 * lam_ref.max()
+    with make_plan(*shape) as pl:
+        pl.set_kspace(x)
+        pl.set_mask(np.ones((T, P, Q), np.uint8))
+        lam, H, E = pl.step_weights(eps)
+    assert np.all(np.abs(lam - lam_ref) <= 1e-5 * lam_ref + 2e-7 * lam_ref.max())
+    ev, U, alpha = oracle.eig_weights(R_ref, eps, 0.6)
+    assert nrmse(H, oracle.weight_matrix(U, alpha)) < 2e-5
+    E_ref = oracle.penalty_masks(U, alpha, N1, N2, M, P, Q)
+    for w, (m, mp) in enumerate(pairs(M)):
+        assert nrmse(E[w], E_ref[m, mp]) < 2e-5, (m, mp)
+
+
 def masks_from_H(H, N1, N2, M, P, Q):
     """Masks straight from H: the lag sums w_{m',m}[a' - a] of the (m', m) block, then
     E(r) = sum_Delta w[Delta] e^{+2 pi i (Delta1 r1 / P + Delta2 r2 / Q)} (FP64)."""
