@@ -287,9 +287,10 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
 // for w = tau p + c d v, c = -|tau|^2 / 2, d = p^H v (real for a Hermitian A).
 // v and p are zero outside rows k+1.., so the update leaves the finished rows
 // and columns unchanged without masks (slots are skipped in chunks of eight,
-// whose loads the compiler can then issue together); v and p are double-buffered by column
-// parity, which leaves two barriers per column.  The outputs stay in LDS until
-// the end (a barrier would otherwise wait for each column's global stores).
+// whose loads the compiler can then issue together); v and p are
+// double-buffered by column parity, which leaves two barriers per column.  The
+// outputs stay in LDS until the end (a barrier would otherwise wait for each
+// column's global stores).
 constexpr int kTriTail = 128;
 constexpr int kTailNT = 512;
 constexpr int kTailLanes = 4;                   // lanes per row
