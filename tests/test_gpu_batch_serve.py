@@ -198,6 +198,41 @@ def test_server_mix_equals_alone_within_budget():
         np.testing.assert_array_equal(c, b, err_msg=f"request {i} on a reused plan")
 
 
+def test_server_mix_with_a_full_size_request():
+    """The serving mix at its stated counts: one 256x256x20 request (15x15x5, 20 x 15)
+    among three slices of the batch workload (9x9x5, 15 x 10), submitted together.
+    Each served result equals its single-plan batch run bit for bit (the full-size
+    request's single run is pinned to the oracle at these counts elsewhere), and
+    the large request overlaps the small ones on the device."""
+    pbs = [workload.make_problem(seed=3, P=256, Q=256, T=20, K=2, R=8, N1=15, N2=15, M=5, n_irls=20, n_cg=15,
+                                 phase=True, name="c3-size")]
+    pbs += [workload.make_problem(n_irls=15, n_cg=10, name=f"slice{i}", **s) for i, s in enumerate(SPECS[:3])]
+    say("server mix with a 256x256x20 request at 20 x 15 and three slices at 15 x 10")
+    refs = []
+    for pb in pbs:
+        T, P, Q = pb.b.shape
+        with slrx.Plan(P, Q, T, pb.N1, pb.N2, pb.M,
+                       slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg)) as pl:
+            pl.set_kspace(pb.b)
+            pl.set_mask(pb.S)
+            slrx.run_batch([pl])
+            refs.append(pl.images())
+    srv = slrx.Server(8 << 30, max_slots=4)
+    try:
+        tickets = [srv.submit_data(pb.b, pb.S, pb.N1, pb.N2, pb.M,
+                                   slrx.make_params(lam=pb.lam, n_irls=pb.n_irls, n_cg=pb.n_cg)) for pb in pbs]
+        for t in tickets:
+            srv.wait(t)
+        infos = [srv.info(t) for t in tickets]
+        out = [srv.fetch(t, pb.b.shape) for t, pb in zip(tickets, pbs)]
+    finally:
+        srv.close()
+    for i, (a, b) in enumerate(zip(out, refs)):
+        np.testing.assert_array_equal(a, b, err_msg=f"request {i} ({pbs[i].name})")
+    big = infos[0]
+    assert any(i["t_admit"] < big["t_done"] and big["t_admit"] < i["t_done"] for i in infos[1:])
+
+
 def test_server_rejects_request_larger_than_budget():
     pb = problems()[1]
     srv = slrx.Server(1 << 20, max_slots=1)
