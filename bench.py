@@ -1016,7 +1016,8 @@ def main() -> int:
                     help="headline only: skip the serving and batch measurements (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU (every box here has one); --gpus must be 1",
+        print(json.dumps({"error": "one GPU only: the library runs each problem on a single device and its "
+                                   "multi-GPU sharding is a design, not code; --gpus must be 1",
                           "gpus_requested": args.gpus}))
         return 2
     if args.workload == "profiles":
