@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #define SLRX_DEV __device__ __forceinline__
 
 // ---------------------------------------------------------------- complex
@@ -58,3 +60,20 @@ SLRX_DEV double reduce_partials(const double* part, int n, double* red) {
   for (int i = threadIdx.x; i < n; i += NT) v += part[i];
   return block_sum<NT>(v, red);
 }
+
+// Raises a kernel's dynamic-LDS limit once per device: the first launches on a
+// device set it (concurrent first launches may both set it, which is harmless);
+// the flag bits are atomic, so host threads can launch concurrently.
+struct LdsLimit {
+  std::atomic<uint32_t> set_on{0};  // bit d: device d
+  hipError_t ensure(const void* kernel, size_t bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint32_t bit = dev >= 0 && dev < 32 ? 1u << dev : 0u;
+    if (bit && (set_on.load(std::memory_order_acquire) & bit)) return hipSuccess;
+    e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess && bit) set_on.fetch_or(bit, std::memory_order_release);
+    return e;
+  }
+};

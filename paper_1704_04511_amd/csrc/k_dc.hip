@@ -822,22 +822,14 @@ size_t dc_ws_ints(int n) { return (size_t)4 * n + 4 * (size_t)n + n; }  // ws_i,
 size_t dc_ws_doubles(int n) { return (size_t)7 * n; }
 int dc_max_n() { return kDcMaxN; }
 
-template <typename K>
-static hipError_t set_lds(K kern, size_t bytes) {
-  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
 hipError_t launch_tdeig(const TdArgs& t, hipStream_t st) {
   const int n = t.n;
   if (n < 1 || n > kDcMaxN) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = set_lds(k_dc_deflate, dc_deflate_lds(kDcMaxN));
-    if (e == hipSuccess) e = set_lds(k_dc_gather, (size_t)4 * kDcMaxN * sizeof(double));
-    if (e == hipSuccess) e = set_lds(k_dc_sort, (size_t)4096 * (sizeof(double) + sizeof(int)));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static LdsLimit lim_deflate, lim_gather, lim_sort;
+  hipError_t e = lim_deflate.ensure((const void*)k_dc_deflate, dc_deflate_lds(kDcMaxN));
+  if (e == hipSuccess) e = lim_gather.ensure((const void*)k_dc_gather, (size_t)4 * kDcMaxN * sizeof(double));
+  if (e == hipSuccess) e = lim_sort.ensure((const void*)k_dc_sort, (size_t)4096 * (sizeof(double) + sizeof(int)));
+  if (e != hipSuccess) return e;
   DcArgs a{};
   a.n = n;
   a.D = t.D;

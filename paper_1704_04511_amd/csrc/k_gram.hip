@@ -148,13 +148,9 @@ template <int M>
 static hipError_t gram_m(const GramArgs& a, hipStream_t s) {
   constexpr int W = M * (M + 1) / 2;
   const size_t lds = ((size_t)W * a.Q + a.Q) * sizeof(double2);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_gram_rows<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(((size_t)W * 256 + 256) * sizeof(double2)));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static LdsLimit lim;
+  const hipError_t e = lim.ensure((const void*)k_gram_rows<M>, ((size_t)W * 256 + 256) * sizeof(double2));
+  if (e != hipSuccess) return e;
   k_gram_rows<M><<<a.P, 256, lds, s>>>(a);
   return hipGetLastError();
 }

@@ -703,13 +703,9 @@ hipError_t launch_group_rows(const CgGroup& g, int mode, int k, hipStream_t s) {
 
 template <int M>
 static hipError_t group_pen_m(const CgGroup& g, hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_group_pen<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)((size_t)kTMax * kPenCols * sizeof(float2)));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static LdsLimit lim;
+  const hipError_t e = lim.ensure((const void*)k_group_pen<M>, (size_t)kTMax * kPenCols * sizeof(float2));
+  if (e != hipSuccess) return e;
   k_group_pen<M><<<g.cols_blocks, kPenNT, g.pen_lds, s>>>(g.tab, g.ns);
   return hipGetLastError();
 }
@@ -763,13 +759,10 @@ template <int N, int M>
 static hipError_t pen_nm(const PenArgs& a, hipStream_t s) {
   const int cb = col_block(ColCap<N>::v, a.Q);
   const size_t lds = (size_t)a.T * cb * fft_stride(N) * sizeof(float2);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_cols_pen<N, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)((size_t)kTMax * ColCap<N>::v * fft_stride(N) * sizeof(float2)));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static LdsLimit lim;
+  const hipError_t e = lim.ensure((const void*)k_cols_pen<N, M>,
+                                  (size_t)kTMax * ColCap<N>::v * fft_stride(N) * sizeof(float2));
+  if (e != hipSuccess) return e;
   k_cols_pen<N, M><<<dim3(a.Q / cb), kPenNT, lds, s>>>(a);
   return hipGetLastError();
 }

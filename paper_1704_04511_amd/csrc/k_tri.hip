@@ -529,13 +529,9 @@ hipError_t launch_tridiag(const TriArgs& base, int nbatch, hipStream_t s, int ca
     else if (u <= 10) launch_col<10>(a, nbatch, rows, stream, s);
     else launch_col<12>(a, nbatch, rows, stream, s);
   }
-  static bool tail_attr = false;
-  if (!tail_attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_tri_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)tail_lds(kTriTail));
-    if (e != hipSuccess) return e;
-    tail_attr = true;
-  }
+  static LdsLimit lim;
+  const hipError_t e = lim.ensure((const void*)k_tri_tail, tail_lds(kTriTail));
+  if (e != hipSuccess) return e;
   const int L = n - k0;
   k_tri_tail<<<dim3(1, nbatch), kTailNT, tail_lds(L), s>>>(a, k0);
   return hipGetLastError();
