@@ -138,8 +138,8 @@ def backtr_flop(n: int, nb: int = 64) -> float:
 
 def tri_launches(n: int) -> int:
     """Launches of one tridiagonalisation (the library's launch schedule): one per
-    column up to the last 128, which share one launch."""
-    return max(n - 128, 0) + 1
+    column up to the last 96, which share one launch."""
+    return max(n - 96, 0) + 1
 
 
 def roofline(kind, avg_ms, T, P, Q, M, N1, N2, nc=0):

@@ -23,7 +23,7 @@
 // threads need (p_k, v_k, the subdiagonal entry, the rows' own coefficients)
 // passed through the same exchange.  Results are bit-reproducible and do not
 // depend on how many workgroups run or which rows a workgroup takes.
-// The last 128 columns, whose trailing block fits in the registers of one
+// The last 96 columns, whose trailing block fits in the registers of one
 // workgroup, are reduced in a single launch (k_tri_tail).
 // The working matrix Aw is full (both triangles) and row-major; reflectors are
 // stored as LAPACK's zhetrd (lower) stores them: v(k+2:n) in column k of the
@@ -273,10 +273,10 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
   if (tid < nrow) pout[row0 + tid] = sum4(&xc[0][tid], kTriRMax);
 }
 
-// The last kTriTail columns in one launch, one workgroup of 512 threads per
-// problem with the trailing block (rows and columns k0..n-1, at most 128 x 128)
-// in registers: thread t holds row i = t / 4 at the columns j = t % 4 + 4 c,
-// c = 0..31, zero beyond the block.  First the pending update of reflector
+// The last kTriTail columns in one launch, one workgroup of kTailNT threads per
+// problem with the trailing block (rows and columns k0..n-1, at most
+// kTriTail x kTriTail) in registers: thread t holds row i = t / 4 at the columns
+// j = t % 4 + 4 c, c < kTriTail / 4, zero beyond the block.  First the pending update of reflector
 // k0-1 is applied, then each column is reduced as in k_tri_col (same reflector
 // convention, same outputs): the wave holding row k forms reflector k from it
 // (the block is Hermitian, so column k below the diagonal is the conjugate of
@@ -291,12 +291,15 @@ __global__ __launch_bounds__(kTriNT) void k_tri_col(TriArgs a, int rows) {
 // double-buffered by column parity, which leaves two barriers per column.  The
 // outputs stay in LDS until the end (a barrier would otherwise wait for each
 // column's global stores).
-constexpr int kTriTail = 128;
-constexpr int kTailNT = 512;
+constexpr int kTriTail = 96;
+constexpr int kTailNT = 384;
 constexpr int kTailLanes = 4;                   // lanes per row
 constexpr int kTailC = kTriTail / kTailLanes;   // columns per thread
 constexpr int kTailRowsW = 64 / kTailLanes;     // rows per wave
 constexpr int kTailChunk = 8;                   // column slots skipped or processed together
+static_assert(kTailLanes == 4, "row sums are quad sums (sum_quad)");
+static_assert(kTailNT / kTailLanes == kTriTail, "one row of the block per kTailLanes threads");
+static_assert(kTailC % kTailChunk == 0 && kTailNT % 64 == 0, "whole chunks and waves");
 // packed reflectors of the block: column kk's entries kk+1..L-1 at voff(kk)
 __host__ __device__ inline int tail_voff(int L, int kk) { return kk * (2 * L - kk - 1) / 2; }
 inline size_t tail_lds(int L) { return (size_t)tail_voff(L, L - 1) * sizeof(double2); }
@@ -413,11 +416,12 @@ __global__ __launch_bounds__(kTailNT) void k_tri_tail(TriArgs a, int k0) {
         const double dd = den.x * den.x + den.y * den.y;
         scale = make_double2(den.x / dd, -den.y / dd);
       }
-      // v from the row in xrow: lane l writes entries l, l + 64 (all 128 slots)
+      // v from the row in xrow: lane l writes entries l, l + 64, .. (every slot)
       const int vo = tail_voff(L, kk) - kk - 1;
 #pragma unroll
-      for (int h = 0; h < kTriTail / 64; ++h) {
+      for (int h = 0; h < (kTriTail + 63) / 64; ++h) {
         const int j = lane + 64 * h;
+        if (j >= kTriTail) continue;
         const double2 v = j == kk + 1 ? make_double2(1.0, 0.0)
                                       : (j >= kk + 2 && j < L ? dmul(dconj(xrow[j]), scale) : zero);
         vs[s][j] = v;

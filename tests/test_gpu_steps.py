@@ -120,13 +120,14 @@ def test_weights_at_the_largest_filters(shape):
         assert nrmse(E[w], E_ref[m, mp]) < 2e-5, (m, mp)
 
 
-@pytest.mark.parametrize("shape", [(4, 16, 128, 1, 127, 1), (8, 32, 32, 4, 4, 8), (4, 64, 64, 1, 43, 3),
-                                   (4, 32, 32, 5, 13, 2), (4, 64, 64, 2, 43, 3)])
+@pytest.mark.parametrize("shape", [(4, 32, 32, 5, 19, 1), (8, 32, 32, 4, 4, 6), (4, 16, 128, 1, 97, 1),
+                                   (4, 32, 32, 7, 7, 2), (4, 64, 64, 1, 43, 3), (4, 64, 64, 2, 43, 3)])
 def test_weights_around_the_last_columns_kernel(shape):
-    """Gram sizes 127, 128, 129, 130 and 258: the tridiagonalisation's last 128
-    columns run in one register-resident workgroup, so 127 and 128 never launch a
-    column kernel, 129 and 130 hand one or two columns' pending update to it, and
-    258 crosses from two vector entries per thread to one in the column launches."""
+    """Gram sizes 95, 96, 97, 98, 129 and 258: the tridiagonalisation's last 96
+    columns run in one register-resident workgroup, so 95 and 96 never launch a
+    column kernel, 97 and 98 hand one or two columns' pending update to it, 129
+    hands it 33, and 258 crosses from two vector entries per thread to one in the
+    column launches."""
     T, P, Q, N1, N2, M = shape
     say(f"weights around the last-columns kernel {shape} (s = {N1 * N2 * M})")
     rng, x, _ = problem(11, T, P, Q)
